@@ -1,0 +1,194 @@
+/*
+ * cdcs.h -- C ABI of the MI355X (gfx950) HSDE-ADMM for chordally sparse SDPs.
+ *
+ * The solver computes the ADMM iteration of Zheng, Fantuzzi,
+ * Papachristodoulou, Goulart & Wynn, "Fast ADMM for homogeneous self-dual
+ * embedding of sparse SDPs": the primal/dual pair of Section 3 (eqs.
+ * PrimalSDP / DualSDP), decomposed over the maximal cliques of a chordal
+ * pattern (Theorems 1-2, eqs. DecomposedPriaml / DecomposedDual), embedded
+ * as in Section 3.2 (eq. HomogeneousEmbedding) and iterated with steps
+ * (Step1)-(Step3) of Section 4.1, where step 1 uses the block eliminations
+ * and the matrix inversion lemma of Sections 4.2-4.3.
+ *
+ * Conventions (all entry points):
+ *  - Indices are 0-based int32.  Symmetric matrices (C and every A_i) are
+ *    given as lower-triangular COO (row >= col); an off-diagonal entry (i,j)
+ *    stands for both X_ij and X_ji.  Duplicate entries are summed.
+ *  - Cliques: p vertex lists in CSR form (clique_ptr[p+1], clique_vtx), each
+ *    list strictly increasing (the natural order of Section 2.1).  Every
+ *    vertex must lie in some clique and every data entry inside some
+ *    C_k x C_k (the chordal pattern E').  The optional clique_parent array
+ *    (p entries, -1 = root) is checked for the running-intersection
+ *    property.  Chordal extension and clique-tree construction are done by
+ *    the caller on the host.
+ *  - Coordinates.  Vectors over the pattern ("entry space") hold svec of a
+ *    symmetric matrix over the lower entries of E' (off-diagonals scaled by
+ *    sqrt 2) in canonical order: sorted by column, then row.  Clique blocks
+ *    ("slot space": s, z, v) are stored clique after clique in the given
+ *    clique order, each as the packed lower triangle in column-major local
+ *    order, off-diagonals scaled by sqrt 2.  This is an isometry of the
+ *    paper's vec coordinates on symmetric matrices.
+ *  - State u = (x, s, y, v, tau) and v~ = (h, z, r, w, kappa) of eq.
+ *    (ADMMForm) are flattened in that block order; each has length
+ *    nE + 2 ns + m + 1.
+ *  - Return values: 0 = OK, negative = error (CDCS_E_*), with a message
+ *    from cdcs_last_error() (thread-local).  Nothing throws across the ABI.
+ *    Solver outcomes (infeasible, iteration limit) are reported in
+ *    cdcs_info.status, not as errors.
+ *  - Ownership: inputs are copied during setup; the caller may free them on
+ *    return.  The handle owns all device memory until cdcs_destroy.  Output
+ *    buffers are caller-allocated.  A handle must not be used from two
+ *    threads at once.  All device work runs on the stream given at setup
+ *    (NULL = the default stream); host-pointer outputs synchronise it.
+ */
+#ifndef CDCS_H
+#define CDCS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CDCS_ABI_VERSION 1
+
+/* outcomes (cdcs_info.status) */
+enum {
+  CDCS_RUNNING = 0,
+  CDCS_SOLVED = 1,
+  CDCS_PRIMAL_INFEASIBLE = 2,
+  CDCS_DUAL_INFEASIBLE = 3,
+  CDCS_MAX_ITER = 4
+};
+
+/* errors (negative return values) */
+enum {
+  CDCS_OK = 0,
+  CDCS_E_ARG = -1,        /* null pointer, size out of range, bad setting */
+  CDCS_E_PATTERN = -2,    /* a C or A_i entry outside the union of C_k x C_k */
+  CDCS_E_CLIQUES = -3,    /* unsorted/out-of-range clique, uncovered vertex, tree violates running intersection */
+  CDCS_E_NONFINITE = -4,  /* NaN or Inf in the data */
+  CDCS_E_FACTOR = -5,     /* the m x m factorisation failed */
+  CDCS_E_DEVICE = -6,     /* a HIP call failed */
+  CDCS_E_NOMEM = -7,      /* device or host allocation failed */
+  CDCS_E_STATE = -8       /* call not valid in the handle's current state */
+};
+
+typedef struct cdcs_handle cdcs_handle;
+
+/* One SDP instance: min <C,X> s.t. <A_i,X> = b_i, X PSD (eq. PrimalSDP),
+ * with the cliques C_1..C_p of a chordal extension of its pattern. */
+typedef struct {
+  int32_t n;                 /* order of X */
+  int32_t m;                 /* number of equality constraints */
+  int64_t c_nnz;             /* entries of C (lower COO) */
+  const int32_t* c_row;
+  const int32_t* c_col;
+  const double* c_val;
+  int64_t a_nnz;             /* entries of all A_i (lower COO + constraint id) */
+  const int32_t* a_con;      /* constraint index i in [0, m) */
+  const int32_t* a_row;
+  const int32_t* a_col;
+  const double* a_val;
+  const double* b;           /* m values */
+  int32_t p;                 /* number of cliques */
+  const int32_t* clique_ptr; /* p + 1 offsets into clique_vtx */
+  const int32_t* clique_vtx; /* vertex lists, strictly increasing per clique */
+  const int32_t* clique_parent; /* p parents (-1 = root) or NULL */
+} cdcs_problem;
+
+typedef struct {
+  double eps_tol;      /* termination tolerance (Section 5: 1e-4) */
+  int32_t max_iter;    /* iteration limit (Section 5: 2000) */
+  int32_t check_every; /* cdcs_solve reads the status words back every this many iterations */
+  int32_t timing;      /* 1 = time each kernel phase with HIP events (cdcs_get_phase_times) */
+  int32_t use_graph;   /* 1 = replay the iteration from a captured HIP graph */
+} cdcs_settings;
+
+typedef struct {
+  int32_t iter;        /* iterations performed so far */
+  int32_t status;      /* CDCS_RUNNING ... CDCS_MAX_ITER */
+  double eps_p, eps_d, eps_g;   /* relative residuals of the current iterate */
+  double obj_p, obj_d;          /* c^T x / tau and b^T y / tau */
+  double tau, kappa;
+  double cx, by;                /* c^T x and b^T y (certificate scales) */
+} cdcs_info;
+
+/* Fill s with eps_tol = 1e-4, max_iter = 2000, check_every = 1, timing = 0,
+ * use_graph = 0. */
+void cdcs_default_settings(cdcs_settings* s);
+
+/* Build the cached data of step 1 (the m x m factor of the matrix of eq.
+ * FactorizationMatrix after the matrix inversion lemma, and the
+ * Sherman-Morrison vector M^{-1} zeta and scalar 1 + zeta^T M^{-1} zeta of
+ * eq. MatrixInverseResult), move everything to the GPU and set
+ * u = v~ = (0, 0, 0, 0, 1).  `stream` is a hipStream_t or NULL. */
+int cdcs_setup(const cdcs_problem* prob, const cdcs_settings* s, void* stream, cdcs_handle** out);
+
+/* The same for `count` independent instances solved together in one
+ * launch per phase (prob[count]). */
+int cdcs_setup_batch(int32_t count, const cdcs_problem* prob, const cdcs_settings* s,
+                     void* stream, cdcs_handle** out);
+
+/* Exactly k ADMM iterations (eqs. Step1-Step3) of every instance, without
+ * early exit.  infos (may be NULL) receives one cdcs_info per instance. */
+int cdcs_iterate(cdcs_handle* h, int32_t k, cdcs_info* infos);
+
+/* Iterate until every instance has a status other than CDCS_RUNNING (an
+ * instance that stops keeps its final iterate while others continue) or
+ * max_iter.  infos (may be NULL) receives one cdcs_info per instance. */
+int cdcs_solve(cdcs_handle* h, cdcs_info* infos);
+
+/* dims[0..3] = nE, ns, m, p of instance `inst`. */
+int cdcs_get_dims(const cdcs_handle* h, int32_t inst, int64_t dims[4]);
+
+/* The nE lower entries (row >= col) of E' in canonical order. */
+int cdcs_get_entries(const cdcs_handle* h, int32_t inst, int32_t* row, int32_t* col);
+
+/* Solution of a SOLVED instance (Section 3.2, recovery as in O'Donoghue et
+ * al. 2016): X = svec(x)/tau on E' (nE values, canonical order; any PSD
+ * completion gives the off-pattern entries, Theorem 1), y/tau (m), and
+ * Z = sum_k E_k^T Z_k E_k with Z_k = smat(z_k)/tau (Theorem 2) as svec over
+ * E' (nE).  Any output may be NULL.  on_device = 1: outputs are device
+ * pointers written on the handle's stream.  CDCS_E_STATE if not solved. */
+int cdcs_get_solution(const cdcs_handle* h, int32_t inst, double* X, double* y, double* Z,
+                      int32_t on_device);
+
+/* Certificate of an infeasible instance: PRIMAL_INFEASIBLE gives
+ * y_cert = y / b^T y (m) with A^T y_cert + H^T v ~ 0, v ~ z PSD, b^T y_cert = 1
+ * (X_cert untouched); DUAL_INFEASIBLE gives X_cert = x / (-c^T x) (nE) with
+ * A x ~ 0, H x ~ s PSD, c^T x = -1 (y_cert untouched).  CDCS_E_STATE
+ * otherwise. */
+int cdcs_get_certificate(const cdcs_handle* h, int32_t inst, double* y_cert, double* X_cert,
+                         int32_t on_device);
+
+/* Copy the iterate (u, v~) of instance `inst` out of / into the solver, in
+ * the flattened coordinates above (host pointers).  set_state also resets
+ * the instance's status to RUNNING; the iteration counter is kept. */
+int cdcs_get_state(const cdcs_handle* h, int32_t inst, double* u, double* vt);
+int cdcs_set_state(cdcs_handle* h, int32_t inst, const double* u, const double* vt);
+
+/* Accumulated HIP-event time (ms) and launch count per kernel phase since
+ * setup or the last reset (timing must be enabled).  names/ms/launches may
+ * be NULL; returns the number of phases. */
+int cdcs_get_phase_times(const cdcs_handle* h, const char** names, double* ms, int64_t* launches,
+                         int32_t cap);
+int cdcs_reset_phase_times(cdcs_handle* h);
+
+/* The conic step on its own (eq. Step2, PSD part): project `count` packed
+ * symmetric blocks onto their PSD cones, out_k = svec(V max(Lambda,0) V^T)
+ * for in_k = svec(V Lambda V^T).  sizes[k] = order of block k (1..1024),
+ * offsets[k] = its first element in `in`/`out` (host arrays); in/out are
+ * device pointers (may alias).  Runs on `stream` and synchronises it. */
+int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets,
+                     const double* in, double* out, void* stream);
+
+const char* cdcs_last_error(void);
+int cdcs_abi_version(void);
+void cdcs_destroy(cdcs_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDCS_H */

@@ -1,0 +1,838 @@
+// C ABI of the solver (declared in include/cdcs.h): setup packs one or more
+// instances into concatenated device arrays, the iteration is a fixed
+// sequence of kernel launches on the handle's stream, and results are read
+// back in the canonical coordinates the header documents.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "device.h"
+#include "plan.h"
+
+using namespace cdcs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return set_error(CDCS_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+enum Phase {
+  PH_R0 = 0, PH_SPMV_A, PH_TRSV, PH_SPMV_AT, PH_SCALAR1, PH_UPDATE_E, PH_UPDATE_R,
+  PH_CONE16, PH_CONE32, PH_CONE64, PH_CONE96, PH_CONE_LARGE, PH_SCALAR2, kNumPhases
+};
+const char* kPhaseNames[kNumPhases] = {
+    "r0_scatter", "spmv_A", "trsv", "spmv_At", "scalar1", "update_x", "update_y",
+    "cone_jacobi16", "cone_jacobi32", "cone_jacobi64", "cone_jacobi96", "cone_large", "scalar2"};
+
+}  // namespace
+
+struct cdcs_handle {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  cdcs_settings set{};
+  int32_t B = 0;
+  std::vector<Instance> inst;
+  std::vector<int64_t> ent_off, slot_off;
+  std::vector<int32_t> row_off, clq_off;
+  std::vector<void*> allocs;
+  DevPlan d{};
+  // cone work lists by kernel variant
+  int32_t* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int32_t ntasks[5] = {0, 0, 0, 0, 0};
+  int32_t kmax_large = 0;
+  std::vector<int32_t> large_sizes;      // host copy of large task sizes (launch shapes)
+  // timing
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  std::vector<std::pair<int, size_t>> ev_used;   // (phase, pool index) since last harvest
+  double phase_ms[kNumPhases] = {};
+  int64_t phase_n[kNumPhases] = {};
+  // graphs
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  double setup_s = 0.0;
+};
+
+namespace {
+
+template <typename T>
+int dev_alloc(cdcs_handle* h, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return set_error(CDCS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  h->allocs.push_back(q);
+  *p = (T*)q;
+  return 0;
+}
+
+template <typename T>
+int dev_upload(cdcs_handle* h, T** p, const std::vector<T>& v) {
+  int rc = dev_alloc(h, p, v.size());
+  if (rc) return rc;
+  if (!v.empty()) HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return 0;
+}
+
+template <typename T>
+int dev_zeros(cdcs_handle* h, T** p, size_t count) {
+  int rc = dev_alloc(h, p, count);
+  if (rc) return rc;
+  HIPCHK(hipMemset(*p, 0, std::max<size_t>(count, 1) * sizeof(T)));
+  return 0;
+}
+
+int bucket_of(int K) {
+  if (K <= 16) return 0;
+  if (K <= 32) return 1;
+  if (K <= 64) return 2;
+  if (K <= kJacobiMax) return 3;
+  return 4;
+}
+
+// record a phase launch between two events when timing is on
+struct PhaseTimer {
+  cdcs_handle* h;
+  int ph;
+  size_t slot = 0;
+  bool on;
+  PhaseTimer(cdcs_handle* hh, int p) : h(hh), ph(p), on(hh->set.timing != 0) {
+    if (!on) return;
+    if (h->ev_used.size() >= h->ev_pool.size()) {
+      hipEvent_t a, b;
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      h->ev_pool.push_back({a, b});
+    }
+    slot = h->ev_used.size();
+    (void)hipEventRecord(h->ev_pool[slot].first, h->stream);
+  }
+  ~PhaseTimer() {
+    if (!on) return;
+    (void)hipEventRecord(h->ev_pool[slot].second, h->stream);
+    h->ev_used.push_back({ph, slot});
+  }
+};
+
+void harvest_timers(cdcs_handle* h) {
+  for (auto& u : h->ev_used) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev_pool[u.second].first, h->ev_pool[u.second].second) == hipSuccess) {
+      h->phase_ms[u.first] += ms;
+      h->phase_n[u.first] += 1;
+    }
+  }
+  h->ev_used.clear();
+}
+
+int launch_iteration(cdcs_handle* h, int32_t stop) {
+  const DevPlan& d = h->d;
+  hipStream_t st = h->stream;
+  { PhaseTimer t(h, PH_R0); launch_r0(d, st); }
+  { PhaseTimer t(h, PH_SPMV_A); launch_spmv_a(d, st); }
+  { PhaseTimer t(h, PH_TRSV); launch_trsv(d, st); }
+  { PhaseTimer t(h, PH_SPMV_AT); launch_spmv_at(d, st); }
+  { PhaseTimer t(h, PH_SCALAR1); launch_scalar1(d, st); }
+  { PhaseTimer t(h, PH_UPDATE_E); launch_update_e(d, st); }
+  { PhaseTimer t(h, PH_UPDATE_R); launch_update_r(d, st); }
+  const int kmaxs[4] = {16, 32, 64, kJacobiMax};
+  for (int bk = 0; bk < 4; ++bk)
+    if (h->ntasks[bk]) {
+      PhaseTimer t(h, PH_CONE16 + bk);
+      launch_cone_jacobi(d, h->tasks[bk], h->ntasks[bk], kmaxs[bk], st);
+    }
+  if (h->ntasks[4]) {
+    PhaseTimer t(h, PH_CONE_LARGE);
+    launch_cone_large(d, h->tasks[4], h->large_sizes.data(), h->ntasks[4], h->kmax_large, st);
+  }
+  { PhaseTimer t(h, PH_SCALAR2); launch_scalar2(d, h->set.eps_tol, h->set.max_iter, stop, st); }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return 0;
+}
+
+int capture_graph(cdcs_handle* h, int stop) {
+  if (h->graph[stop]) return 0;
+  hipGraph_t g;
+  HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  const int saved = h->set.timing;
+  h->set.timing = 0;
+  int rc = launch_iteration(h, stop);
+  h->set.timing = saved;
+  hipError_t e = hipStreamEndCapture(h->stream, &g);
+  if (rc) return rc;
+  if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&h->graph[stop], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return 0;
+}
+
+int run_iterations(cdcs_handle* h, int32_t k, int32_t stop) {
+  if (h->set.use_graph && !h->set.timing) {
+    int rc = capture_graph(h, stop);
+    if (rc) return rc;
+    for (int32_t i = 0; i < k; ++i) HIPCHK(hipGraphLaunch(h->graph[stop], h->stream));
+    return 0;
+  }
+  for (int32_t i = 0; i < k; ++i) {
+    int rc = launch_iteration(h, stop);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+int read_infos(cdcs_handle* h, cdcs_info* infos) {
+  HIPCHK(hipStreamSynchronize(h->stream));
+  harvest_timers(h);
+  if (!infos) return 0;
+  std::vector<double> sc((size_t)h->B * kNsc);
+  std::vector<int32_t> st((size_t)h->B * kNst);
+  HIPCHK(hipMemcpy(sc.data(), h->d.sc, sc.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(st.data(), h->d.st, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < h->B; ++i) {
+    const double* s = &sc[(size_t)i * kNsc];
+    cdcs_info& o = infos[i];
+    o.iter = st[(size_t)i * kNst + ST_ITER];
+    o.status = st[(size_t)i * kNst + ST_STATUS];
+    o.eps_p = s[SC_EPS_P];
+    o.eps_d = s[SC_EPS_D];
+    o.eps_g = s[SC_EPS_G];
+    o.tau = s[SC_TAU];
+    o.kappa = s[SC_KAPPA];
+    o.cx = s[SC_CX];
+    o.by = s[SC_BY];
+    o.obj_p = s[SC_TAU] > 0 ? s[SC_CX] / s[SC_TAU] : NAN;
+    o.obj_d = s[SC_TAU] > 0 ? s[SC_BY] / s[SC_TAU] : NAN;
+  }
+  return 0;
+}
+
+int pack_and_upload(cdcs_handle* h) {
+  const int32_t B = h->B;
+  auto& I = h->inst;
+  h->ent_off.assign(B + 1, 0);
+  h->slot_off.assign(B + 1, 0);
+  h->row_off.assign(B + 1, 0);
+  h->clq_off.assign(B + 1, 0);
+  for (int32_t i = 0; i < B; ++i) {
+    h->ent_off[i + 1] = h->ent_off[i] + I[i].nE;
+    h->slot_off[i + 1] = h->slot_off[i] + I[i].ns;
+    h->row_off[i + 1] = h->row_off[i] + I[i].m;
+    h->clq_off[i + 1] = h->clq_off[i] + I[i].p;
+  }
+  const int64_t NE = h->ent_off[B], NS = h->slot_off[B];
+  const int32_t M = h->row_off[B], P = h->clq_off[B];
+  int64_t nnzA = 0;
+  for (auto& in : I) nnzA += (int64_t)in.acol.size();
+  if (NE >= INT32_MAX || NS >= INT32_MAX || nnzA >= INT32_MAX)
+    return set_error(CDCS_E_ARG, "batch too large for 32-bit indices");
+  DevPlan& d = h->d;
+  d.B = B;
+  d.M = M;
+  d.NE = NE;
+  d.NS = NS;
+  d.P = P;
+  // entry space
+  std::vector<double> c(NE), pinv(NE), halfD(NE), ztx(NE), atzy(NE);
+  std::vector<int32_t> slot2ent(NS), sptr(NE + 1, 0), slots(NS);
+  for (int32_t i = 0; i < B; ++i) {
+    const int64_t eo = h->ent_off[i], so = h->slot_off[i];
+    for (int64_t e = 0; e < I[i].nE; ++e) {
+      c[eo + e] = I[i].c[e];
+      pinv[eo + e] = 1.0 / (1.0 + 0.5 * I[i].D[e]);
+      halfD[eo + e] = 0.5 * I[i].D[e];
+      ztx[eo + e] = I[i].zt_x[e];
+      atzy[eo + e] = I[i].atzy[e];
+    }
+    for (int64_t s = 0; s < I[i].ns; ++s) {
+      slot2ent[so + s] = (int32_t)(eo + I[i].slot2ent[s]);
+      sptr[eo + I[i].slot2ent[s] + 1]++;
+    }
+  }
+  for (int64_t e = 0; e < NE; ++e) sptr[e + 1] += sptr[e];
+  {
+    std::vector<int32_t> fill(sptr.begin(), sptr.end() - 1);
+    for (int64_t s = 0; s < NS; ++s) slots[fill[slot2ent[s]]++] = (int32_t)s;
+  }
+  int rc;
+  if ((rc = dev_upload(h, (double**)&d.c, c)) || (rc = dev_upload(h, (double**)&d.pinv, pinv)) ||
+      (rc = dev_upload(h, (double**)&d.halfD, halfD)) || (rc = dev_upload(h, (double**)&d.zt_x, ztx)) ||
+      (rc = dev_upload(h, (double**)&d.atzy, atzy)) || (rc = dev_upload(h, (int32_t**)&d.ent_sptr, sptr)) ||
+      (rc = dev_upload(h, (int32_t**)&d.ent_slots, slots)) ||
+      (rc = dev_upload(h, (int32_t**)&d.slot2ent, slot2ent)) || (rc = dev_zeros(h, &d.x, NE)) ||
+      (rc = dev_zeros(h, &d.hsum, NE)) || (rc = dev_zeros(h, &d.q, NE)) || (rc = dev_zeros(h, &d.px, NE)) ||
+      (rc = dev_zeros(h, &d.atw, NE)) || (rc = dev_zeros(h, &d.s, NS)) || (rc = dev_zeros(h, &d.z, NS)) ||
+      (rc = dev_zeros(h, &d.v, NS)))
+    return rc;
+  // row space and A, A^T
+  std::vector<double> b(M), zty(M), aval(nnzA), atval(nnzA);
+  std::vector<int32_t> aptr(M + 1, 0), acol(nnzA), atptr(NE + 1, 0), atrow(nnzA);
+  {
+    int64_t at = 0;
+    for (int32_t i = 0; i < B; ++i) {
+      const int32_t ro = h->row_off[i];
+      const int64_t eo = h->ent_off[i];
+      for (int32_t r = 0; r < I[i].m; ++r) {
+        b[ro + r] = I[i].b[r];
+        zty[ro + r] = I[i].zt_y[r];
+        aptr[ro + r] = (int32_t)at;
+        for (int32_t q = I[i].aptr[r]; q < I[i].aptr[r + 1]; ++q) {
+          acol[at] = (int32_t)(eo + I[i].acol[q]);
+          aval[at] = I[i].aval[q];
+          atptr[acol[at] + 1]++;
+          ++at;
+        }
+      }
+    }
+    aptr[M] = (int32_t)at;
+    for (int64_t e = 0; e < NE; ++e) atptr[e + 1] += atptr[e];
+    std::vector<int32_t> fill(atptr.begin(), atptr.end() - 1);
+    for (int32_t r = 0; r < M; ++r)
+      for (int32_t q = aptr[r]; q < aptr[r + 1]; ++q) {
+        const int32_t pos = fill[acol[q]]++;
+        atrow[pos] = r;
+        atval[pos] = aval[q];
+      }
+  }
+  if ((rc = dev_upload(h, (double**)&d.b, b)) || (rc = dev_upload(h, (double**)&d.zt_y, zty)) ||
+      (rc = dev_upload(h, (int32_t**)&d.a_ptr, aptr)) || (rc = dev_upload(h, (int32_t**)&d.a_col, acol)) ||
+      (rc = dev_upload(h, (double**)&d.a_val, aval)) || (rc = dev_upload(h, (int32_t**)&d.at_ptr, atptr)) ||
+      (rc = dev_upload(h, (int32_t**)&d.at_row, atrow)) || (rc = dev_upload(h, (double**)&d.at_val, atval)) ||
+      (rc = dev_zeros(h, &d.y, M)) || (rc = dev_zeros(h, &d.g, M)) || (rc = dev_zeros(h, &d.w, M)))
+    return rc;
+  // factors
+  std::vector<int32_t> fmode(B), perm(M, 0), lptr, lcol, uptr, ucol, flev_off(B + 1, 0), flev_ptr,
+      flev_rows, blev_off(B + 1, 0), blev_ptr, blev_rows;
+  std::vector<int64_t> fdoff(B, 0);
+  std::vector<double> Ld, fdiag(M, 1.0), lval, uval;
+  for (int32_t i = 0; i < B; ++i) {
+    const Factor& f = I[i].fac;
+    const int32_t ro = h->row_off[i];
+    fmode[i] = f.dense ? 0 : 1;
+    if (f.dense) {
+      fdoff[i] = (int64_t)Ld.size();
+      Ld.insert(Ld.end(), f.Ld.begin(), f.Ld.end());
+      for (int32_t r = 0; r < f.m; ++r) lptr.push_back((int32_t)lcol.size());
+      lptr.push_back((int32_t)lcol.size());
+      for (int32_t r = 0; r < f.m; ++r) uptr.push_back((int32_t)ucol.size());
+      uptr.push_back((int32_t)ucol.size());
+    } else {
+      for (int32_t r = 0; r < f.m; ++r) {
+        perm[ro + r] = f.perm[r];
+        fdiag[ro + r] = f.diag[r];
+      }
+      const int32_t lbase = (int32_t)lcol.size(), ubase = (int32_t)ucol.size();
+      for (int32_t r = 0; r <= f.m; ++r) lptr.push_back(lbase + f.lptr[r]);
+      for (int32_t r = 0; r <= f.m; ++r) uptr.push_back(ubase + f.uptr[r]);
+      lcol.insert(lcol.end(), f.lcol.begin(), f.lcol.end());
+      lval.insert(lval.end(), f.lval.begin(), f.lval.end());
+      ucol.insert(ucol.end(), f.ucol.begin(), f.ucol.end());
+      uval.insert(uval.end(), f.uval.begin(), f.uval.end());
+      const int32_t fb = (int32_t)flev_rows.size(), bb = (int32_t)blev_rows.size();
+      for (size_t l = 0; l + 1 < f.flev_ptr.size(); ++l) flev_ptr.push_back(fb + f.flev_ptr[l]);
+      for (size_t l = 0; l + 1 < f.blev_ptr.size(); ++l) blev_ptr.push_back(bb + f.blev_ptr[l]);
+      flev_rows.insert(flev_rows.end(), f.flev_rows.begin(), f.flev_rows.end());
+      blev_rows.insert(blev_rows.end(), f.blev_rows.begin(), f.blev_rows.end());
+    }
+    flev_off[i + 1] = (int32_t)flev_ptr.size();
+    blev_off[i + 1] = (int32_t)blev_ptr.size();
+  }
+  flev_ptr.push_back((int32_t)flev_rows.size());
+  blev_ptr.push_back((int32_t)blev_rows.size());
+  if ((rc = dev_upload(h, (int32_t**)&d.f_mode, fmode)) || (rc = dev_upload(h, (int64_t**)&d.f_dense_off, fdoff)) ||
+      (rc = dev_upload(h, (double**)&d.f_Ld, Ld)) || (rc = dev_upload(h, (int32_t**)&d.f_perm, perm)) ||
+      (rc = dev_upload(h, (double**)&d.f_diag, fdiag)) || (rc = dev_upload(h, (int32_t**)&d.f_lptr, lptr)) ||
+      (rc = dev_upload(h, (int32_t**)&d.f_lcol, lcol)) || (rc = dev_upload(h, (double**)&d.f_lval, lval)) ||
+      (rc = dev_upload(h, (int32_t**)&d.f_uptr, uptr)) || (rc = dev_upload(h, (int32_t**)&d.f_ucol, ucol)) ||
+      (rc = dev_upload(h, (double**)&d.f_uval, uval)) || (rc = dev_upload(h, (int32_t**)&d.f_flev_off, flev_off)) ||
+      (rc = dev_upload(h, (int32_t**)&d.f_flev_ptr, flev_ptr)) ||
+      (rc = dev_upload(h, (int32_t**)&d.f_flev_rows, flev_rows)) ||
+      (rc = dev_upload(h, (int32_t**)&d.f_blev_off, blev_off)) ||
+      (rc = dev_upload(h, (int32_t**)&d.f_blev_ptr, blev_ptr)) ||
+      (rc = dev_upload(h, (int32_t**)&d.f_blev_rows, blev_rows)))
+    return rc;
+  // blocks
+  std::vector<int4> eblk, rblk;
+  std::vector<int32_t> eblk_off(B + 1, 0), rblk_off(B + 1, 0);
+  for (int32_t i = 0; i < B; ++i) {
+    for (int64_t e = h->ent_off[i]; e < h->ent_off[i + 1]; e += kEntChunk)
+      eblk.push_back(make_int4(i, (int)e, (int)std::min<int64_t>(e + kEntChunk, h->ent_off[i + 1]), 0));
+    for (int32_t r = h->row_off[i]; r < h->row_off[i + 1]; r += kRowChunk)
+      rblk.push_back(make_int4(i, r, std::min(r + kRowChunk, h->row_off[i + 1]), 0));
+    eblk_off[i + 1] = (int32_t)eblk.size();
+    rblk_off[i + 1] = (int32_t)rblk.size();
+  }
+  d.n_eblk = (int32_t)eblk.size();
+  d.n_rblk = (int32_t)rblk.size();
+  std::vector<int64_t> ent_off64(h->ent_off);
+  if ((rc = dev_upload(h, (int4**)&d.eblk, eblk)) || (rc = dev_upload(h, (int4**)&d.rblk, rblk)) ||
+      (rc = dev_upload(h, (int32_t**)&d.eblk_off, eblk_off)) ||
+      (rc = dev_upload(h, (int32_t**)&d.rblk_off, rblk_off)) ||
+      (rc = dev_upload(h, (int64_t**)&d.ent_off, ent_off64)) ||
+      (rc = dev_upload(h, (int32_t**)&d.row_off, h->row_off)) ||
+      (rc = dev_upload(h, (int32_t**)&d.clq_off, h->clq_off)) ||
+      (rc = dev_zeros(h, &d.part_e, (size_t)d.n_eblk * 4)) ||
+      (rc = dev_zeros(h, &d.part_r, (size_t)d.n_rblk * 4)) || (rc = dev_zeros(h, &d.part_c, (size_t)P * 2)))
+    return rc;
+  // cliques and cone work lists (bucketed by size, largest first within a bucket)
+  std::vector<int32_t> csize(P), cinst(P);
+  std::vector<int64_t> cslot(P);
+  std::vector<std::vector<int32_t>> bk(5);
+  for (int32_t i = 0; i < B; ++i)
+    for (int32_t k = 0; k < I[i].p; ++k) {
+      const int32_t g = h->clq_off[i] + k;
+      csize[g] = I[i].csize[k];
+      cinst[g] = i;
+      cslot[g] = h->slot_off[i] + I[i].slot_off[k];
+      bk[bucket_of(csize[g])].push_back(g);
+    }
+  for (auto& v : bk)
+    std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b2) { return csize[a] > csize[b2]; });
+  if ((rc = dev_upload(h, (int32_t**)&d.clq_size, csize)) || (rc = dev_upload(h, (int32_t**)&d.clq_inst, cinst)) ||
+      (rc = dev_upload(h, (int64_t**)&d.clq_slot, cslot)))
+    return rc;
+  for (int bkt = 0; bkt < 5; ++bkt) {
+    h->ntasks[bkt] = (int32_t)bk[bkt].size();
+    if ((rc = dev_upload(h, &h->tasks[bkt], bk[bkt]))) return rc;
+  }
+  // large-clique workspace: one K x K (column-major) matrix + eigen data per task
+  h->large_sizes.clear();
+  std::vector<int64_t> boff;
+  int64_t btot = 0;
+  for (int32_t g : bk[4]) {
+    const int64_t K = csize[g];
+    h->large_sizes.push_back((int32_t)K);
+    h->kmax_large = std::max<int32_t>(h->kmax_large, (int32_t)K);
+    boff.push_back(btot);
+    btot += 2 * K * K + 8 * K;
+  }
+  boff.push_back(btot);
+  if ((rc = dev_zeros(h, &d.big_work, (size_t)btot)) || (rc = dev_upload(h, (int64_t**)&d.big_off, boff))) return rc;
+  // scalars and status
+  std::vector<double> sc((size_t)B * kNsc, 0.0);
+  for (int32_t i = 0; i < B; ++i) {
+    double* s = &sc[(size_t)i * kNsc];
+    s[SC_TAU] = 1.0;
+    s[SC_KAPPA] = 1.0;
+    s[SC_DEN] = I[i].den;
+    s[SC_CTZX] = I[i].ctzx;
+    s[SC_BTZY] = I[i].btzy;
+    s[SC_NB] = I[i].nb;
+    s[SC_NC] = I[i].nc;
+  }
+  if ((rc = dev_upload(h, &d.sc, sc)) || (rc = dev_zeros(h, &d.st, (size_t)B * kNst))) return rc;
+  return 0;
+}
+
+bool valid_inst(const cdcs_handle* h, int32_t inst) { return h && inst >= 0 && inst < h->B; }
+
+}  // namespace
+
+extern "C" {
+
+void cdcs_default_settings(cdcs_settings* s) {
+  if (!s) return;
+  s->eps_tol = 1e-4;
+  s->max_iter = 2000;
+  s->check_every = 1;
+  s->timing = 0;
+  s->use_graph = 0;
+}
+
+int cdcs_abi_version(void) { return CDCS_ABI_VERSION; }
+
+const char* cdcs_last_error(void) { return g_last_error.c_str(); }
+
+void cdcs_destroy(cdcs_handle* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  for (int i = 0; i < 2; ++i)
+    if (h->graph[i]) (void)hipGraphExecDestroy(h->graph[i]);
+  for (auto& e : h->ev_pool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->own_stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+int cdcs_setup_batch(int32_t count, const cdcs_problem* prob, const cdcs_settings* s, void* stream,
+                     cdcs_handle** out) {
+  if (!out) return set_error(CDCS_E_ARG, "null output handle");
+  *out = nullptr;
+  if (count < 1 || !prob) return set_error(CDCS_E_ARG, "need count >= 1 problems");
+  cdcs_settings set;
+  cdcs_default_settings(&set);
+  if (s) set = *s;
+  if (!(set.eps_tol > 0.0) || set.max_iter < 1 || set.check_every < 1)
+    return set_error(CDCS_E_ARG, "settings: need eps_tol > 0, max_iter >= 1, check_every >= 1");
+  const auto t0 = std::chrono::steady_clock::now();
+  cdcs_handle* h = new cdcs_handle();
+  h->stream = (hipStream_t)stream;
+  if (!h->stream) {
+    // a stream of our own (default priority) so that the iteration can be captured
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete h;
+      return set_error(CDCS_E_DEVICE, "hipStreamCreateWithFlags failed");
+    }
+    h->own_stream = true;
+  }
+  h->set = set;
+  h->B = count;
+  h->inst.resize(count);
+  // host setup of independent instances in parallel
+  std::vector<int> rcs(count, 0);
+  std::vector<Error> errs(count);
+  const int nthr = std::max(1, std::min<int>(count, (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthr; ++t)
+    pool.emplace_back([&, t]() {
+      for (int i = t; i < count; i += nthr) rcs[i] = build_instance(prob[i], h->inst[i], errs[i]);
+    });
+  for (auto& th : pool) th.join();
+  for (int i = 0; i < count; ++i)
+    if (rcs[i]) {
+      int rc = set_error(rcs[i], "instance " + std::to_string(i) + ": " + errs[i].msg);
+      cdcs_destroy(h);
+      return rc;
+    }
+  int rc = pack_and_upload(h);
+  if (rc) {
+    cdcs_destroy(h);
+    return rc;
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    cdcs_destroy(h);
+    return set_error(CDCS_E_DEVICE, std::string("setup sync: ") + hipGetErrorString(e));
+  }
+  h->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = h;
+  return 0;
+}
+
+int cdcs_setup(const cdcs_problem* prob, const cdcs_settings* s, void* stream, cdcs_handle** out) {
+  return cdcs_setup_batch(1, prob, s, stream, out);
+}
+
+int cdcs_iterate(cdcs_handle* h, int32_t k, cdcs_info* infos) {
+  if (!h || k < 0) return set_error(CDCS_E_ARG, "bad handle or k");
+  // exactly k iterations of every instance: nothing is frozen
+  std::vector<int32_t> st((size_t)h->B * kNst);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(st.data(), h->d.st, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < h->B; ++i) st[(size_t)i * kNst + ST_FROZEN] = 0;
+  HIPCHK(hipMemcpy(h->d.st, st.data(), st.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  int rc = run_iterations(h, k, 0);
+  if (rc) return rc;
+  return read_infos(h, infos);
+}
+
+int cdcs_solve(cdcs_handle* h, cdcs_info* infos) {
+  if (!h) return set_error(CDCS_E_ARG, "null handle");
+  std::vector<int32_t> st((size_t)h->B * kNst);
+  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(st.data(), h->d.st, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < h->B; ++i) {
+    int32_t* s = &st[(size_t)i * kNst];
+    s[ST_FROZEN] = (s[ST_STATUS] != CDCS_RUNNING || s[ST_ITER] >= h->set.max_iter) ? 1 : 0;
+    if (s[ST_STATUS] == CDCS_RUNNING && s[ST_ITER] >= h->set.max_iter) s[ST_STATUS] = CDCS_MAX_ITER;
+  }
+  HIPCHK(hipMemcpy(h->d.st, st.data(), st.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  for (;;) {
+    bool all = true;
+    int32_t maxit = 0;
+    for (int32_t i = 0; i < h->B; ++i) {
+      all = all && st[(size_t)i * kNst + ST_FROZEN];
+      maxit = std::max(maxit, st[(size_t)i * kNst + ST_ITER]);
+    }
+    if (all) break;
+    const int32_t chunk = std::min(h->set.check_every, std::max(1, h->set.max_iter - maxit));
+    int rc = run_iterations(h, chunk, 1);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpy(st.data(), h->d.st, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  }
+  return read_infos(h, infos);
+}
+
+int cdcs_get_dims(const cdcs_handle* h, int32_t inst, int64_t dims[4]) {
+  if (!valid_inst(h, inst) || !dims) return set_error(CDCS_E_ARG, "bad handle, instance or dims");
+  dims[0] = h->inst[inst].nE;
+  dims[1] = h->inst[inst].ns;
+  dims[2] = h->inst[inst].m;
+  dims[3] = h->inst[inst].p;
+  return 0;
+}
+
+int cdcs_get_entries(const cdcs_handle* h, int32_t inst, int32_t* row, int32_t* col) {
+  if (!valid_inst(h, inst)) return set_error(CDCS_E_ARG, "bad handle or instance");
+  const Instance& I = h->inst[inst];
+  if (row) std::memcpy(row, I.erow.data(), I.nE * sizeof(int32_t));
+  if (col) std::memcpy(col, I.ecol.data(), I.nE * sizeof(int32_t));
+  return 0;
+}
+
+namespace {
+
+struct HostState {
+  std::vector<double> x, s, y, v, z;
+  double tau = 0, kappa = 0;
+  int32_t status = 0, iter = 0;
+};
+
+int fetch_state(const cdcs_handle* h, int32_t inst, HostState& S) {
+  const Instance& I = h->inst[inst];
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const int64_t eo = h->ent_off[inst], so = h->slot_off[inst];
+  const int32_t ro = h->row_off[inst];
+  S.x.resize(I.nE);
+  S.s.resize(I.ns);
+  S.z.resize(I.ns);
+  S.v.resize(I.ns);
+  S.y.resize(I.m);
+  HIPCHK(hipMemcpy(S.x.data(), h->d.x + eo, I.nE * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(S.s.data(), h->d.s + so, I.ns * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(S.z.data(), h->d.z + so, I.ns * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(S.v.data(), h->d.v + so, I.ns * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(S.y.data(), h->d.y + ro, I.m * sizeof(double), hipMemcpyDeviceToHost));
+  double sc[kNsc];
+  int32_t st[kNst];
+  HIPCHK(hipMemcpy(sc, h->d.sc + (size_t)inst * kNsc, sizeof(sc), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(st, h->d.st + (size_t)inst * kNst, sizeof(st), hipMemcpyDeviceToHost));
+  S.tau = sc[SC_TAU];
+  S.kappa = sc[SC_KAPPA];
+  S.status = st[ST_STATUS];
+  S.iter = st[ST_ITER];
+  return 0;
+}
+
+int put_out(const cdcs_handle* h, double* dst, const std::vector<double>& src, int32_t on_device) {
+  if (!dst) return 0;
+  if (on_device) {
+    HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } else {
+    std::memcpy(dst, src.data(), src.size() * sizeof(double));
+  }
+  return 0;
+}
+
+}  // namespace
+
+int cdcs_get_state(const cdcs_handle* h, int32_t inst, double* u, double* vt) {
+  if (!valid_inst(h, inst)) return set_error(CDCS_E_ARG, "bad handle or instance");
+  HostState S;
+  int rc = fetch_state(h, inst, S);
+  if (rc) return rc;
+  const Instance& I = h->inst[inst];
+  if (u) {
+    double* p = u;
+    std::memcpy(p, S.x.data(), I.nE * sizeof(double)); p += I.nE;
+    std::memcpy(p, S.s.data(), I.ns * sizeof(double)); p += I.ns;
+    std::memcpy(p, S.y.data(), I.m * sizeof(double)); p += I.m;
+    std::memcpy(p, S.v.data(), I.ns * sizeof(double)); p += I.ns;
+    *p = S.tau;
+  }
+  if (vt) {
+    double* p = vt;
+    std::memset(p, 0, I.nE * sizeof(double)); p += I.nE;
+    std::memcpy(p, S.z.data(), I.ns * sizeof(double)); p += I.ns;
+    std::memset(p, 0, I.m * sizeof(double)); p += I.m;
+    std::memset(p, 0, I.ns * sizeof(double)); p += I.ns;
+    *p = S.kappa;
+  }
+  return 0;
+}
+
+int cdcs_set_state(cdcs_handle* h, int32_t inst, const double* u, const double* vt) {
+  if (!valid_inst(h, inst) || !u || !vt) return set_error(CDCS_E_ARG, "bad handle, instance or state");
+  const Instance& I = h->inst[inst];
+  // h, r, w are identically zero along the iteration (step Step3); a state
+  // with non-zero h, r or w is not one the method produces
+  const double* hv = vt;
+  const double* rv = vt + I.nE + I.ns;
+  const double* wv = rv + I.m;
+  for (int64_t e = 0; e < I.nE; ++e)
+    if (hv[e] != 0.0) return set_error(CDCS_E_ARG, "h must be zero");
+  for (int32_t r = 0; r < I.m; ++r)
+    if (rv[r] != 0.0) return set_error(CDCS_E_ARG, "r must be zero");
+  for (int64_t s = 0; s < I.ns; ++s)
+    if (wv[s] != 0.0) return set_error(CDCS_E_ARG, "w must be zero");
+  const int64_t eo = h->ent_off[inst], so = h->slot_off[inst];
+  const int32_t ro = h->row_off[inst];
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const double* p = u;
+  HIPCHK(hipMemcpy(h->d.x + eo, p, I.nE * sizeof(double), hipMemcpyHostToDevice)); p += I.nE;
+  HIPCHK(hipMemcpy(h->d.s + so, p, I.ns * sizeof(double), hipMemcpyHostToDevice)); p += I.ns;
+  HIPCHK(hipMemcpy(h->d.y + ro, p, I.m * sizeof(double), hipMemcpyHostToDevice)); p += I.m;
+  HIPCHK(hipMemcpy(h->d.v + so, p, I.ns * sizeof(double), hipMemcpyHostToDevice)); p += I.ns;
+  const double tau = *p;
+  HIPCHK(hipMemcpy(h->d.z + so, vt + I.nE, I.ns * sizeof(double), hipMemcpyHostToDevice));
+  const double kappa = vt[I.nE + 2 * I.ns + I.m];
+  double sc[kNsc];
+  HIPCHK(hipMemcpy(sc, h->d.sc + (size_t)inst * kNsc, sizeof(sc), hipMemcpyDeviceToHost));
+  sc[SC_TAU] = tau;
+  sc[SC_KAPPA] = kappa;
+  HIPCHK(hipMemcpy(h->d.sc + (size_t)inst * kNsc, sc, sizeof(sc), hipMemcpyHostToDevice));
+  int32_t st[kNst];
+  HIPCHK(hipMemcpy(st, h->d.st + (size_t)inst * kNst, sizeof(st), hipMemcpyDeviceToHost));
+  st[ST_STATUS] = CDCS_RUNNING;
+  st[ST_FROZEN] = 0;
+  HIPCHK(hipMemcpy(h->d.st + (size_t)inst * kNst, st, sizeof(st), hipMemcpyHostToDevice));
+  return 0;
+}
+
+int cdcs_get_solution(const cdcs_handle* h, int32_t inst, double* X, double* y, double* Z, int32_t on_device) {
+  if (!valid_inst(h, inst)) return set_error(CDCS_E_ARG, "bad handle or instance");
+  HostState S;
+  int rc = fetch_state(h, inst, S);
+  if (rc) return rc;
+  if (S.status != CDCS_SOLVED || !(S.tau > 0)) return set_error(CDCS_E_STATE, "instance is not solved");
+  const Instance& I = h->inst[inst];
+  std::vector<double> xo(I.nE), yo(I.m), zo(I.nE, 0.0);
+  for (int64_t e = 0; e < I.nE; ++e) xo[e] = S.x[e] / S.tau;
+  for (int32_t r = 0; r < I.m; ++r) yo[r] = S.y[r] / S.tau;
+  // Z = sum_k E_k^T Z_k E_k (Theorem 2) = H^T z / tau in svec coordinates
+  for (int64_t s = 0; s < I.ns; ++s) zo[I.slot2ent[s]] += S.z[s];
+  for (int64_t e = 0; e < I.nE; ++e) zo[e] /= S.tau;
+  if ((rc = put_out(h, X, xo, on_device)) || (rc = put_out(h, y, yo, on_device)) || (rc = put_out(h, Z, zo, on_device)))
+    return rc;
+  return 0;
+}
+
+int cdcs_get_certificate(const cdcs_handle* h, int32_t inst, double* y_cert, double* X_cert, int32_t on_device) {
+  if (!valid_inst(h, inst)) return set_error(CDCS_E_ARG, "bad handle or instance");
+  HostState S;
+  int rc = fetch_state(h, inst, S);
+  if (rc) return rc;
+  const Instance& I = h->inst[inst];
+  if (S.status == CDCS_PRIMAL_INFEASIBLE) {
+    double by = 0.0;
+    for (int32_t r = 0; r < I.m; ++r) by += I.b[r] * S.y[r];
+    std::vector<double> yo(I.m);
+    for (int32_t r = 0; r < I.m; ++r) yo[r] = S.y[r] / by;
+    return put_out(h, y_cert, yo, on_device);
+  }
+  if (S.status == CDCS_DUAL_INFEASIBLE) {
+    double cx = 0.0;
+    for (int64_t e = 0; e < I.nE; ++e) cx += I.c[e] * S.x[e];
+    std::vector<double> xo(I.nE);
+    for (int64_t e = 0; e < I.nE; ++e) xo[e] = S.x[e] / (-cx);
+    return put_out(h, X_cert, xo, on_device);
+  }
+  return set_error(CDCS_E_STATE, "instance is not infeasible");
+}
+
+int cdcs_get_phase_times(const cdcs_handle* h, const char** names, double* ms, int64_t* launches, int32_t cap) {
+  if (!h) return set_error(CDCS_E_ARG, "null handle");
+  for (int i = 0; i < kNumPhases && i < cap; ++i) {
+    if (names) names[i] = kPhaseNames[i];
+    if (ms) ms[i] = h->phase_ms[i];
+    if (launches) launches[i] = h->phase_n[i];
+  }
+  return kNumPhases;
+}
+
+int cdcs_reset_phase_times(cdcs_handle* h) {
+  if (!h) return set_error(CDCS_E_ARG, "null handle");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  harvest_timers(h);
+  for (int i = 0; i < kNumPhases; ++i) {
+    h->phase_ms[i] = 0.0;
+    h->phase_n[i] = 0;
+  }
+  return 0;
+}
+
+int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets, const double* in, double* out,
+                     void* stream) {
+  if (count < 0 || (count > 0 && (!sizes || !offsets || !in || !out)))
+    return set_error(CDCS_E_ARG, "bad projection arguments");
+  if (count == 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<std::vector<int32_t>> bk(5);
+  std::vector<int32_t> large_sizes;
+  std::vector<int64_t> woff;
+  int64_t wtot = 0;
+  int32_t kmax_large = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    if (sizes[k] < 1 || sizes[k] > 1024 || offsets[k] < 0) return set_error(CDCS_E_ARG, "block size must be 1..1024");
+    bk[bucket_of(sizes[k])].push_back(k);
+  }
+  for (int32_t k : bk[4]) {
+    large_sizes.push_back(sizes[k]);
+    kmax_large = std::max(kmax_large, sizes[k]);
+    woff.push_back(wtot);
+    wtot += 2 * (int64_t)sizes[k] * sizes[k] + 8 * (int64_t)sizes[k];
+  }
+  woff.push_back(wtot);
+  std::vector<int32_t> vsz(sizes, sizes + count);
+  std::vector<int64_t> voff(offsets, offsets + count);
+  std::vector<void*> tmp;
+  auto up = [&](const void* src, size_t bytes, void** dst) -> int {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 8));
+    if (e != hipSuccess) return set_error(CDCS_E_NOMEM, "hipMalloc failed");
+    tmp.push_back(p);
+    if (bytes) {
+      e = hipMemcpy(p, src, bytes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return set_error(CDCS_E_DEVICE, "hipMemcpy failed");
+    }
+    *dst = p;
+    return 0;
+  };
+  int rc = 0;
+  void *dsz, *doff, *dtask[5], *dwork = nullptr, *dwoff = nullptr;
+  auto cleanup = [&]() {
+    for (void* p : tmp) (void)hipFree(p);
+  };
+  if ((rc = up(vsz.data(), vsz.size() * 4, &dsz)) || (rc = up(voff.data(), voff.size() * 8, &doff))) {
+    cleanup();
+    return rc;
+  }
+  for (int b = 0; b < 5; ++b)
+    if ((rc = up(bk[b].data(), bk[b].size() * 4, &dtask[b]))) {
+      cleanup();
+      return rc;
+    }
+  if (!bk[4].empty()) {
+    if ((rc = up(nullptr, (size_t)wtot * 8, &dwork)) || (rc = up(woff.data(), woff.size() * 8, &dwoff))) {
+      cleanup();
+      return rc;
+    }
+  }
+  const int kmaxs[4] = {16, 32, 64, kJacobiMax};
+  for (int b = 0; b < 4; ++b)
+    launch_psd_project((int32_t*)dsz, (int64_t*)doff, (int32_t*)dtask[b], (int32_t)bk[b].size(), kmaxs[b], in, out,
+                       st);
+  if (!bk[4].empty())
+    launch_psd_project_large((int32_t*)dsz, (int64_t*)doff, (int32_t*)dtask[4], large_sizes.data(),
+                             (int32_t)bk[4].size(), kmax_large, in, out, (double*)dwork, (int64_t*)dwoff, st);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  cleanup();
+  if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("projection: ") + hipGetErrorString(e));
+  return 0;
+}
+
+}  // extern "C"

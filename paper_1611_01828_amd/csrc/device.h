@@ -1,0 +1,153 @@
+// Device-side layout of a batched HSDE-ADMM solve on gfx950.
+//
+// All instances of a batch are concatenated: "entry space" (svec over the
+// chordal pattern E'), "slot space" (the clique blocks s, z, v) and "row
+// space" (constraints).  Kernels work on block descriptors that never
+// straddle an instance, so every reduction has a fixed per-instance block
+// range and a fixed summation order (bitwise reproducible, no atomics).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cdcs {
+
+constexpr int kThreads = 256;        // block size of the streaming kernels
+constexpr int kEntChunk = 1024;      // entries per entry block
+constexpr int kRowChunk = 64;        // constraint rows per row block (4 waves)
+constexpr int kJacobiMax = 96;       // largest clique handled by the LDS Jacobi kernel
+
+// per-instance scalar slots (double sc[B * kNsc])
+enum Sc {
+  SC_TAU = 0, SC_KAPPA, SC_DEN, SC_CTZX, SC_BTZY, SC_NB, SC_NC, SC_GAMMA, SC_OMEGA3, SC_BW,
+  SC_CPX, SC_EPS_P, SC_EPS_D, SC_EPS_G, SC_CX, SC_BY, SC_PRI2, SC_DUA2, SC_PINF2, SC_DINF2,
+  SC_UTAU, kNsc = 24
+};
+
+// status words per instance
+enum St { ST_STATUS = 0, ST_FROZEN, ST_ITER, kNst = 4 };
+
+struct DevPlan {
+  int32_t B;
+  int32_t M;
+  int64_t NE, NS;
+  int32_t P;
+  // per instance
+  const int64_t* ent_off;     // B+1
+  const int32_t* row_off;     // B+1
+  const int32_t* clq_off;     // B+1
+  const int32_t* eblk_off;    // B+1 (entry-block ranges)
+  const int32_t* rblk_off;    // B+1 (row-block ranges)
+  double* sc;                 // B * kNsc
+  int32_t* st;                // B * kNst
+  // entry space
+  double* x;
+  double* hsum;               // H^T (s + z + v) / 2
+  double* q;                  // P^{-1} r0
+  double* px;                 // P^{-1}(r0 - A^T w')
+  double* atw;                // A^T w'
+  const double* c;
+  const double* pinv;         // 1 / (1 + D/2)
+  const double* halfD;        // D / 2
+  const double* zt_x;         // x part of M^{-1} zeta
+  const double* atzy;         // A^T (y part of M^{-1} zeta)
+  const int32_t* ent_sptr;    // NE+1: slots covering each entry (H^T as CSR)
+  const int32_t* ent_slots;
+  // slot space
+  double* s;
+  double* z;
+  double* v;
+  const int32_t* slot2ent;    // H as an index map
+  // row space
+  double* y;
+  double* g;                  // right-hand side of the m x m solve
+  double* w;                  // its solution w'
+  const double* b;
+  const double* zt_y;
+  const int32_t* a_ptr;       // A, CSR over global entries
+  const int32_t* a_col;
+  const double* a_val;
+  const int32_t* at_ptr;      // A^T, CSR over global rows
+  const int32_t* at_row;
+  const double* at_val;
+  // m x m factor per instance
+  const int32_t* f_mode;      // 0 dense, 1 sparse
+  const int64_t* f_dense_off; // offset of the dense column-major factor
+  const double* f_Ld;
+  const int32_t* f_perm;      // at row_off (local indices)
+  const double* f_diag;       // at row_off
+  const int32_t* f_lptr;      // at row_off + inst (m+1 each), values global into lcol
+  const int32_t* f_lcol;
+  const double* f_lval;
+  const int32_t* f_uptr;
+  const int32_t* f_ucol;
+  const double* f_uval;
+  const int32_t* f_flev_off;  // B+1 offsets into flev_ptr
+  const int32_t* f_flev_ptr;  // values global into flev_rows
+  const int32_t* f_flev_rows;
+  const int32_t* f_blev_off;
+  const int32_t* f_blev_ptr;
+  const int32_t* f_blev_rows;
+  // work lists
+  const int4* eblk;           // {inst, begin, end, 0}
+  int32_t n_eblk;
+  const int4* rblk;
+  int32_t n_rblk;
+  // partial sums
+  double* part_e;             // n_eblk * 4: [c.px, dres^2, (dres + tau c)^2, c.x]
+  double* part_r;             // n_rblk * 4: [pres^2, (Ax)^2, b.y, 0]
+  double* part_c;             // P * 2: [(Hx - s)^2, (v - z)^2]
+  // cliques
+  const int32_t* clq_size;
+  const int64_t* clq_slot;    // first slot of each clique (global)
+  const int32_t* clq_inst;
+  // large-clique workspace
+  double* big_work;
+  const int64_t* big_off;     // per large task: offset into big_work
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-wide sum in a fixed order (wave tree, then waves in order).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) t += red[i];
+    red[NT / 64] = t;
+  }
+  __syncthreads();
+  return red[NT / 64];
+}
+
+// launchers (defined in the .hip files)
+void launch_r0(const DevPlan& d, hipStream_t st);
+void launch_spmv_a(const DevPlan& d, hipStream_t st);
+void launch_trsv(const DevPlan& d, hipStream_t st);
+void launch_spmv_at(const DevPlan& d, hipStream_t st);
+void launch_scalar1(const DevPlan& d, hipStream_t st);
+void launch_update_e(const DevPlan& d, hipStream_t st);
+void launch_update_r(const DevPlan& d, hipStream_t st);
+void launch_scalar2(const DevPlan& d, double eps_tol, int32_t max_iter, int32_t stop, hipStream_t st);
+// cone step: tasks are clique ids; kind selects the kernel variant
+void launch_cone_jacobi(const DevPlan& d, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st);
+void launch_cone_large(const DevPlan& d, const int32_t* tasks, const int32_t* host_sizes,
+                       int32_t ntask, int32_t kmax, hipStream_t st);
+// stand-alone projection of packed blocks
+void launch_psd_project(const int32_t* sizes, const int64_t* offs, const int32_t* tasks, int32_t ntask,
+                        int kmax, const double* in, double* out, hipStream_t st);
+void launch_psd_project_large(const int32_t* sizes, const int64_t* offs, const int32_t* tasks,
+                              const int32_t* host_sizes, int32_t ntask, int32_t kmax, const double* in,
+                              double* out, double* work, const int64_t* work_off, hipStream_t st);
+
+}  // namespace cdcs

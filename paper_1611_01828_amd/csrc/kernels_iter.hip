@@ -1,0 +1,342 @@
+// Per-iteration streaming kernels of step 1 (the affine projection, Sections
+// 4.2-4.3) and the fused vector updates / residual reductions.
+//
+// With h = r = w = 0 (they stay exactly zero, step (Step3)) and
+// omega = u + v~ = (x, s + z, y, v, tau + kappa), step 1 in the eliminated
+// form reads (eq. MatrixInverse: t = omega_12 - omega_3 zeta, zeta = (c,0,-b,0);
+// eq. SecBlkEliResult/ThirdBlkElm eliminated onto the first block; eq.
+// FactorizationMatrix inverted by the matrix inversion lemma with P = I + D/2
+// and K = I + A P^{-1} A^T):
+//
+//   r0  = x - omega_3 c + H^T(s + z + v)/2                     k_r0
+//   g'  = A P^{-1} r0 - y - omega_3 b                          k_spmv_a
+//   w'  = K^{-1} g'                                            k_trsv
+//   p_x = P^{-1}(r0 - A^T w'),  p_y = -w'                      k_spmv_at
+//   gamma = (c^T p_x + b^T w') / (1 + zeta^T M^{-1} zeta)      k_scalar1 (eq. MatrixInverseResult)
+//   x+ = p_x - gamma zt_x,  y+ = -w' - gamma zt_y              k_update_e / k_update_r
+//   u_tau = omega_3 + c^T x+ - b^T y+                          (eq. FirstBlockElimination)
+//   tau+ = max(0, u_tau - kappa), kappa+ = tau+ - (u_tau - kappa)   (Step2/Step3)
+//
+// The clique blocks (u_s - z, v+ and the PSD projection) are handled by the
+// cone kernels.  Residual norms reuse these intermediates: A x+ = w' + y +
+// omega_3 b + gamma (b + zt_y), A^T y+ = -A^T w' - gamma A^T zt_y and
+// H^T v+ = H^T(s+z+v)/2 - D x+ / 2.
+#include "device.h"
+
+namespace cdcs {
+
+__global__ __launch_bounds__(kThreads) void k_r0(DevPlan d) {
+  const int4 bd = d.eblk[blockIdx.x];
+  const int inst = bd.x;
+  if (d.st[inst * kNst + ST_FROZEN]) return;
+  const double om3 = d.sc[inst * kNsc + SC_TAU] + d.sc[inst * kNsc + SC_KAPPA];
+  for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
+    double acc = 0.0;
+    const int k1 = d.ent_sptr[e + 1];
+    for (int k = d.ent_sptr[e]; k < k1; ++k) {
+      const int sl = d.ent_slots[k];
+      acc += d.s[sl] + d.z[sl] + d.v[sl];
+    }
+    const double hs = 0.5 * acc;
+    const double r0 = d.x[e] - om3 * d.c[e] + hs;
+    d.hsum[e] = hs;
+    d.q[e] = d.pinv[e] * r0;
+  }
+}
+
+// one wavefront per constraint row
+__global__ __launch_bounds__(kThreads) void k_spmv_a(DevPlan d) {
+  const int4 bd = d.rblk[blockIdx.x];
+  const int inst = bd.x;
+  if (d.st[inst * kNst + ST_FROZEN]) return;
+  const double om3 = d.sc[inst * kNsc + SC_TAU] + d.sc[inst * kNsc + SC_KAPPA];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int r = bd.y + wid; r < bd.z; r += kThreads / 64) {
+    double acc = 0.0;
+    const int q1 = d.a_ptr[r + 1];
+    for (int q = d.a_ptr[r] + lane; q < q1; q += 64) acc += d.a_val[q] * d.q[d.a_col[q]];
+    acc = wave_sum(acc);
+    if (lane == 0) d.g[r] = acc - d.y[r] - om3 * d.b[r];
+  }
+}
+
+// K w' = g' for one instance per workgroup: K = L L^T (dense column-major L)
+// or Kp = L L^T in a minimum-degree order with level-scheduled rows.
+constexpr int kTrsvThreads = 256;
+constexpr int kTrsvLds = 8192;
+
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv(DevPlan d) {
+  __shared__ double zl[kTrsvLds];
+  __shared__ double red[kTrsvThreads / 64 + 1];
+  const int inst = blockIdx.x;
+  if (d.st[inst * kNst + ST_FROZEN]) return;
+  const int r0 = d.row_off[inst];
+  const int m = d.row_off[inst + 1] - r0;
+  const int tid = threadIdx.x;
+  if (d.f_mode[inst] == 0) {
+    const double* L = d.f_Ld + d.f_dense_off[inst];
+    for (int i = tid; i < m; i += kTrsvThreads) zl[i] = d.g[r0 + i];
+    __syncthreads();
+    // forward, column oriented: z_j = g_j / L_jj ; g_i -= L_ij z_j (i > j)
+    for (int j = 0; j < m; ++j) {
+      const double zj = zl[j] / L[(size_t)j * m + j];
+      __syncthreads();
+      for (int i = j + 1 + tid; i < m; i += kTrsvThreads) zl[i] -= L[(size_t)j * m + i] * zj;
+      if (tid == 0) zl[j] = zj;
+      __syncthreads();
+    }
+    // backward with L^T, column oriented: w_j = z_j / L_jj ; z_i -= L_ji w_j (i < j)
+    for (int j = m - 1; j >= 0; --j) {
+      const double wj = zl[j] / L[(size_t)j * m + j];
+      __syncthreads();
+      for (int i = tid; i < j; i += kTrsvThreads) zl[i] -= L[(size_t)i * m + j] * wj;
+      if (tid == 0) zl[j] = wj;
+      __syncthreads();
+    }
+    double bw = 0.0;
+    for (int i = tid; i < m; i += kTrsvThreads) {
+      d.w[r0 + i] = zl[i];
+      bw += d.b[r0 + i] * zl[i];
+    }
+    bw = block_sum<kTrsvThreads>(bw, red);
+    if (tid == 0) d.sc[inst * kNsc + SC_BW] = bw;
+    return;
+  }
+  // sparse, permuted: z = g[perm]
+  const int32_t* perm = d.f_perm + r0;
+  const double* dg = d.f_diag + r0;
+  const int32_t* lptr = d.f_lptr + r0 + inst;
+  const int32_t* uptr = d.f_uptr + r0 + inst;
+  for (int i = tid; i < m; i += kTrsvThreads) zl[i] = d.g[r0 + perm[i]];
+  __syncthreads();
+  {
+    const int l0 = d.f_flev_off[inst], l1 = d.f_flev_off[inst + 1];
+    for (int l = l0; l < l1; ++l) {
+      const int a = d.f_flev_ptr[l], bnd = d.f_flev_ptr[l + 1];
+      for (int t = a + tid; t < bnd; t += kTrsvThreads) {
+        const int i = d.f_flev_rows[t];
+        double sacc = zl[i];
+        for (int q = lptr[i]; q < lptr[i + 1]; ++q) sacc -= d.f_lval[q] * zl[d.f_lcol[q]];
+        zl[i] = sacc / dg[i];
+      }
+      __syncthreads();
+    }
+  }
+  {
+    const int l0 = d.f_blev_off[inst], l1 = d.f_blev_off[inst + 1];
+    for (int l = l0; l < l1; ++l) {
+      const int a = d.f_blev_ptr[l], bnd = d.f_blev_ptr[l + 1];
+      for (int t = a + tid; t < bnd; t += kTrsvThreads) {
+        const int i = d.f_blev_rows[t];
+        double sacc = zl[i];
+        for (int q = uptr[i]; q < uptr[i + 1]; ++q) sacc -= d.f_uval[q] * zl[d.f_ucol[q]];
+        zl[i] = sacc / dg[i];
+      }
+      __syncthreads();
+    }
+  }
+  double bw = 0.0;
+  for (int i = tid; i < m; i += kTrsvThreads) {
+    const int r = r0 + perm[i];
+    d.w[r] = zl[i];
+    bw += d.b[r] * zl[i];
+  }
+  bw = block_sum<kTrsvThreads>(bw, red);
+  if (tid == 0) d.sc[inst * kNsc + SC_BW] = bw;
+}
+
+__global__ __launch_bounds__(kThreads) void k_spmv_at(DevPlan d) {
+  __shared__ double red[kThreads / 64 + 1];
+  const int4 bd = d.eblk[blockIdx.x];
+  const int inst = bd.x;
+  if (d.st[inst * kNst + ST_FROZEN]) return;
+  double cpx = 0.0;
+  for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
+    double acc = 0.0;
+    const int q1 = d.at_ptr[e + 1];
+    for (int q = d.at_ptr[e]; q < q1; ++q) acc += d.at_val[q] * d.w[d.at_row[q]];
+    const double px = d.q[e] - d.pinv[e] * acc;
+    d.atw[e] = acc;
+    d.px[e] = px;
+    cpx += d.c[e] * px;
+  }
+  cpx = block_sum<kThreads>(cpx, red);
+  if (threadIdx.x == 0) d.part_e[blockIdx.x * 4 + 0] = cpx;
+}
+
+// gamma of eq. (MatrixInverseResult), u_tau of eq. (FirstBlockElimination),
+// and the R_+ parts of steps 2-3.
+__global__ __launch_bounds__(64) void k_scalar1(DevPlan d) {
+  const int inst = blockIdx.x;
+  if (d.st[inst * kNst + ST_FROZEN]) return;
+  double acc = 0.0;
+  for (int b = d.eblk_off[inst] + threadIdx.x; b < d.eblk_off[inst + 1]; b += 64) acc += d.part_e[b * 4 + 0];
+  acc = wave_sum(acc);
+  if (threadIdx.x == 0) {
+    double* sc = d.sc + inst * kNsc;
+    const double tau = sc[SC_TAU], kap = sc[SC_KAPPA];
+    const double om3 = tau + kap;
+    const double bw = sc[SC_BW];
+    const double gam = (acc + bw) / sc[SC_DEN];
+    const double cx = acc - gam * sc[SC_CTZX];       // c^T x+
+    const double by = -bw - gam * sc[SC_BTZY];       // b^T y+
+    const double ut = om3 + cx - by;
+    const double tn = fmax(0.0, ut - kap);
+    sc[SC_CPX] = acc;
+    sc[SC_GAMMA] = gam;
+    sc[SC_OMEGA3] = om3;
+    sc[SC_UTAU] = ut;
+    sc[SC_TAU] = tn;
+    sc[SC_KAPPA] = kap - ut + tn;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_update_e(DevPlan d) {
+  __shared__ double red[kThreads / 64 + 1];
+  const int4 bd = d.eblk[blockIdx.x];
+  const int inst = bd.x;
+  if (d.st[inst * kNst + ST_FROZEN]) return;
+  const double* sc = d.sc + inst * kNsc;
+  const double gam = sc[SC_GAMMA], tau = sc[SC_TAU];
+  double d2 = 0.0, p2 = 0.0, cx = 0.0;
+  for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
+    const double xn = d.px[e] - gam * d.zt_x[e];
+    // A^T y+ + H^T v+  (dual-feasibility row of eq. DualFeasible)
+    const double lin = -d.atw[e] - gam * d.atzy[e] + d.hsum[e] - d.halfD[e] * xn;
+    const double ce = d.c[e];
+    const double dr = lin - tau * ce;
+    d.x[e] = xn;
+    d2 += dr * dr;
+    p2 += lin * lin;
+    cx += ce * xn;
+  }
+  d2 = block_sum<kThreads>(d2, red);
+  p2 = block_sum<kThreads>(p2, red);
+  cx = block_sum<kThreads>(cx, red);
+  if (threadIdx.x == 0) {
+    double* pe = d.part_e + blockIdx.x * 4;
+    pe[1] = d2;
+    pe[2] = p2;
+    pe[3] = cx;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_update_r(DevPlan d) {
+  __shared__ double red[kThreads / 64 + 1];
+  const int4 bd = d.rblk[blockIdx.x];
+  const int inst = bd.x;
+  if (d.st[inst * kNst + ST_FROZEN]) return;
+  const double* sc = d.sc + inst * kNsc;
+  const double gam = sc[SC_GAMMA], tau = sc[SC_TAU], om3 = sc[SC_OMEGA3];
+  double p2 = 0.0, a2 = 0.0, by = 0.0;
+  for (int r = bd.y + threadIdx.x; r < bd.z; r += kThreads) {
+    const double br = d.b[r], ztr = d.zt_y[r], wr = d.w[r];
+    // A x+ = A p_x - gamma A zt_x = (w' + y + omega_3 b) + gamma (b + zt_y)
+    const double ax = wr + d.y[r] + om3 * br + gam * (br + ztr);
+    const double yn = -wr - gam * ztr;
+    d.y[r] = yn;
+    const double pr = ax - tau * br;
+    p2 += pr * pr;
+    a2 += ax * ax;
+    by += br * yn;
+  }
+  p2 = block_sum<kThreads>(p2, red);
+  a2 = block_sum<kThreads>(a2, red);
+  by = block_sum<kThreads>(by, red);
+  if (threadIdx.x == 0) {
+    double* pr = d.part_r + blockIdx.x * 4;
+    pr[0] = p2;
+    pr[1] = a2;
+    pr[2] = by;
+  }
+}
+
+// Residuals, termination and infeasibility tests (O'Donoghue et al. 2016
+// normalisation of the KKT rows of eqs. PrimalFeasible, DualFeasible,
+// ZeroGap); stop = 1 freezes an instance once it has an outcome.
+__global__ __launch_bounds__(64) void k_scalar2(DevPlan d, double eps_tol, int32_t max_iter, int32_t stop) {
+  const int inst = blockIdx.x;
+  int32_t* st = d.st + inst * kNst;
+  if (st[ST_FROZEN]) return;
+  const int lane = threadIdx.x;
+  double e1 = 0, e2 = 0, e3 = 0, r0 = 0, r1 = 0, r2 = 0, c0 = 0, c1 = 0;
+  for (int b = d.eblk_off[inst] + lane; b < d.eblk_off[inst + 1]; b += 64) {
+    e1 += d.part_e[b * 4 + 1];
+    e2 += d.part_e[b * 4 + 2];
+    e3 += d.part_e[b * 4 + 3];
+  }
+  for (int b = d.rblk_off[inst] + lane; b < d.rblk_off[inst + 1]; b += 64) {
+    r0 += d.part_r[b * 4 + 0];
+    r1 += d.part_r[b * 4 + 1];
+    r2 += d.part_r[b * 4 + 2];
+  }
+  for (int k = d.clq_off[inst] + lane; k < d.clq_off[inst + 1]; k += 64) {
+    c0 += d.part_c[k * 2 + 0];
+    c1 += d.part_c[k * 2 + 1];
+  }
+  e1 = wave_sum(e1);
+  e2 = wave_sum(e2);
+  e3 = wave_sum(e3);
+  r0 = wave_sum(r0);
+  r1 = wave_sum(r1);
+  r2 = wave_sum(r2);
+  c0 = wave_sum(c0);
+  c1 = wave_sum(c1);
+  if (lane != 0) return;
+  double* sc = d.sc + inst * kNsc;
+  const double tau = sc[SC_TAU];
+  const double cx = e3, by = r2;
+  const double pri2 = r0 + c0, dua2 = e1 + c1, pinf2 = e2 + c1, dinf2 = r1 + c0;
+  double ep = INFINITY, ed = INFINITY, eg = INFINITY;
+  if (tau > 0.0) {
+    ep = sqrt(pri2) / (tau * (1.0 + sc[SC_NB]));
+    ed = sqrt(dua2) / (tau * (1.0 + sc[SC_NC]));
+  }
+  const double gden = tau + fabs(cx) + fabs(by);
+  if (gden > 0.0) eg = fabs(cx - by) / gden;
+  int status = 0;
+  if (tau > 0.0 && ep <= eps_tol && ed <= eps_tol && eg <= eps_tol) status = 1;
+  else if (by > 0.0 && sqrt(pinf2) <= eps_tol * by) status = 2;
+  else if (cx < 0.0 && sqrt(dinf2) <= eps_tol * (-cx)) status = 3;
+  sc[SC_EPS_P] = ep;
+  sc[SC_EPS_D] = ed;
+  sc[SC_EPS_G] = eg;
+  sc[SC_CX] = cx;
+  sc[SC_BY] = by;
+  sc[SC_PRI2] = pri2;
+  sc[SC_DUA2] = dua2;
+  sc[SC_PINF2] = pinf2;
+  sc[SC_DINF2] = dinf2;
+  const int it = st[ST_ITER] + 1;
+  st[ST_ITER] = it;
+  if (stop && status == 0 && it >= max_iter) status = 4;
+  st[ST_STATUS] = status;
+  if (stop && status != 0) st[ST_FROZEN] = 1;
+}
+
+void launch_r0(const DevPlan& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_r0, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
+}
+void launch_spmv_a(const DevPlan& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_spmv_a, dim3(d.n_rblk), dim3(kThreads), 0, st, d);
+}
+void launch_trsv(const DevPlan& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_trsv, dim3(d.B), dim3(kTrsvThreads), 0, st, d);
+}
+void launch_spmv_at(const DevPlan& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_spmv_at, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
+}
+void launch_scalar1(const DevPlan& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar1, dim3(d.B), dim3(64), 0, st, d);
+}
+void launch_update_e(const DevPlan& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_e, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
+}
+void launch_update_r(const DevPlan& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_r, dim3(d.n_rblk), dim3(kThreads), 0, st, d);
+}
+void launch_scalar2(const DevPlan& d, double eps_tol, int32_t max_iter, int32_t stop, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar2, dim3(d.B), dim3(64), 0, st, d, eps_tol, max_iter, stop);
+}
+
+}  // namespace cdcs
