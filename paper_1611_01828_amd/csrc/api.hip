@@ -421,7 +421,7 @@ int pack_and_upload(cdcs_handle* h) {
     h->large_sizes.push_back((int32_t)K);
     h->kmax_large = std::max<int32_t>(h->kmax_large, (int32_t)K);
     boff.push_back(btot);
-    btot += 2 * K * K + 8 * K;
+    btot += large_work_size((int)K);
   }
   boff.push_back(btot);
   if ((rc = dev_zeros(h, &d.big_work, (size_t)btot)) || (rc = dev_upload(h, (int64_t**)&d.big_off, boff))) return rc;
@@ -783,7 +783,7 @@ int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets
     large_sizes.push_back(sizes[k]);
     kmax_large = std::max(kmax_large, sizes[k]);
     woff.push_back(wtot);
-    wtot += 2 * (int64_t)sizes[k] * sizes[k] + 8 * (int64_t)sizes[k];
+    wtot += large_work_size(sizes[k]);
   }
   woff.push_back(wtot);
   std::vector<int32_t> vsz(sizes, sizes + count);
@@ -794,7 +794,7 @@ int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets
     hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 8));
     if (e != hipSuccess) return set_error(CDCS_E_NOMEM, "hipMalloc failed");
     tmp.push_back(p);
-    if (bytes) {
+    if (bytes && src) {
       e = hipMemcpy(p, src, bytes, hipMemcpyHostToDevice);
       if (e != hipSuccess) return set_error(CDCS_E_DEVICE, "hipMemcpy failed");
     }

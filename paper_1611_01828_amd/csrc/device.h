@@ -106,6 +106,13 @@ struct DevPlan {
   const int64_t* big_off;     // per large task: offset into big_work
 };
 
+// doubles of workspace one large-clique task needs (matrix, eigenvectors,
+// LU / panel scratch, tridiagonal data, tile partials)
+inline int64_t large_work_size(int K) {
+  const int64_t T = (K + 31) / 32;
+  return 5LL * K * K + 4LL * K + 16 + T * (T + 1) + 64;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -1,10 +1,608 @@
-// Conic step for cliques larger than the LDS Jacobi kernel handles.
+// Conic step (eq. Step2, PSD part) for cliques of 97..1024 vertices.
+//
+// Pi_+(Y) = sum_{lambda_l > 0} lambda_l v_l v_l^T = Y - sum_{lambda_l < 0} lambda_l v_l v_l^T,
+// so only the eigenpairs of the smaller-signed side of the spectrum are
+// computed.  Per clique (one task):
+//   1. gather      Y (K x K, column-major) from the clique's slots
+//   2. tridiag     Q^T Y Q = T by Householder reflections, blocked in panels
+//                  of 32 columns with deferred rank-2k updates (the LAPACK
+//                  sytrd/latrd scheme, Golub & Van Loan Section 8.3.1)
+//   3. eig         Sturm-sequence bisection for the chosen eigenvalues
+//                  (Golub & Van Loan Section 8.4.1), inverse iteration with
+//                  a partially pivoted tridiagonal LU for the eigenvectors,
+//                  re-orthogonalised within clusters of close eigenvalues
+//                  (Peters & Wilkinson; Golub & Van Loan Section 8.2.2)
+//   4. backtrans   V = Q Z, applying the stored reflectors
+//   5. recon       the low-rank sum above on 32 x 32 output tiles, fused with
+//                  s+, z+ = s+ - Y, v+ and the residual partial sums (ADMM
+//                  mode) or written to the output blocks (projection mode)
+//   6. partials    per-clique sum of the tile partials (fixed order)
 #include "device.h"
 
 namespace cdcs {
 
-void launch_cone_large(const DevPlan&, const int32_t*, const int32_t*, int32_t, int32_t, hipStream_t) {}
-void launch_psd_project_large(const int32_t*, const int64_t*, const int32_t*, const int32_t*, int32_t, int32_t,
-                              const double*, double*, double*, const int64_t*, hipStream_t) {}
+namespace {
+
+constexpr int kLT = 1024;        // threads of the per-task kernels
+constexpr int kNB = 32;          // panel width of the tridiagonalisation
+constexpr int kTile = 32;        // reconstruction tile
+constexpr int kBtCols = 16;      // eigenvector columns per back-transform workgroup
+constexpr double kEps = 2.220446049250313e-16;
+constexpr double kSqrt2 = 1.4142135623730951;
+constexpr double kInvSqrt2 = 0.70710678118654752;
+
+__device__ __forceinline__ int packed_index(int a, int b, int K) {
+  return b * K - (b * (b - 1)) / 2 + (a - b);
+}
+
+// workspace layout of one task (doubles), see large_work_size()
+struct Ws {
+  double* W;     // K*K   matrix, then Householder vectors below the subdiagonal
+  double* Z;     // K*K   eigenvectors (first r columns)
+  double* S;     // 3*K*K panel arrays / LU scratch
+  double* d;     // K     diagonal of T
+  double* e;     // K     off-diagonal of T
+  double* tau;   // K     reflector scalars
+  double* lam;   // K     chosen eigenvalues
+  double* meta;  // 16    [0] r, [1] 1 = positive side
+  double* tiles; // 2 * ntiles partial sums
+};
+
+__device__ __forceinline__ Ws ws_of(double* base, int K) {
+  Ws w;
+  const size_t K2 = (size_t)K * K;
+  w.W = base;
+  w.Z = base + K2;
+  w.S = base + 2 * K2;
+  w.d = base + 5 * K2;
+  w.e = w.d + K;
+  w.tau = w.e + K;
+  w.lam = w.tau + K;
+  w.meta = w.lam + K;
+  w.tiles = w.meta + 16;
+  return w;
+}
+
+__device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
+  uint64_t x = ((uint64_t)a << 32) ^ (uint64_t)b ^ 0x9E3779B97F4A7C15ull;
+  x ^= x >> 30;
+  x *= 0xBF58476D1CE4E5B9ull;
+  x ^= x >> 27;
+  x *= 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;   // [-1, 1)
+}
+
+struct LargeArgs {
+  // ADMM mode
+  DevPlan d;
+  const int32_t* tasks;       // clique ids (ADMM) or block ids (projection)
+  // projection mode
+  const int32_t* psizes;
+  const int64_t* poffs;
+  const double* pin;
+  double* pout;
+  // both
+  double* work;
+  const int64_t* woff;        // per task
+};
+
+template <bool ADMM>
+__device__ __forceinline__ bool task_info(const LargeArgs& a, int task, int& K, int64_t& base) {
+  const int k = a.tasks[task];
+  if (ADMM) {
+    if (a.d.st[a.d.clq_inst[k] * kNst + ST_FROZEN]) return false;
+    K = a.d.clq_size[k];
+    base = a.d.clq_slot[k];
+  } else {
+    K = a.psizes[k];
+    base = a.poffs[k];
+  }
+  return true;
+}
+
+// svec(Y) entry of packed slot t of the task (ADMM: (s - z - v + H x+)/2)
+template <bool ADMM>
+__device__ __forceinline__ double yvec_of(const LargeArgs& a, int64_t base, int t) {
+  if (ADMM) {
+    const int64_t sl = base + t;
+    return 0.5 * (a.d.s[sl] - a.d.z[sl] - a.d.v[sl] + a.d.x[a.d.slot2ent[sl]]);
+  }
+  return a.pin[base + t];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// 1. gather
+// ---------------------------------------------------------------------------
+template <bool ADMM>
+__global__ __launch_bounds__(256) void k_large_gather(LargeArgs a) {
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  double* W = a.work + a.woff[blockIdx.x];
+  const int nslot = K * (K + 1) / 2;
+  // walk columns so that consecutive threads read consecutive slots
+  for (int b = 0; b < K; ++b) {
+    const int p0 = packed_index(b, b, K);
+    for (int i = b + threadIdx.x; i < K; i += 256) {
+      double y = yvec_of<ADMM>(a, base, p0 + (i - b));
+      if (i != b) y *= kInvSqrt2;
+      W[(size_t)b * K + i] = y;
+      W[(size_t)i * K + b] = y;
+    }
+  }
+  (void)nslot;
+}
+
+// ---------------------------------------------------------------------------
+// 2. Householder tridiagonalisation (lower, blocked panels)
+// ---------------------------------------------------------------------------
+template <bool ADMM>
+__global__ __launch_bounds__(kLT) void k_large_tridiag(LargeArgs a) {
+  __shared__ double vbuf[1024];
+  __shared__ double ybuf[1024];
+  __shared__ double t1[kNB], t2[kNB];
+  __shared__ double red[kLT / 64 + 1];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  double* W = w.W;
+  double* V = w.S;
+  double* Wp = w.S + (size_t)K * kNB;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  constexpr int NW = kLT / 64;
+  for (int j0 = 0; j0 < K - 2; j0 += kNB) {
+    const int nb = min(kNB, K - 2 - j0);
+    for (int i = 0; i < nb; ++i) {
+      const int j = j0 + i;
+      // (a) bring column j up to date with the panel's earlier reflectors
+      for (int r = j + tid; r < K; r += kLT) {
+        double v = W[(size_t)j * K + r];
+        for (int l = 0; l < i; ++l)
+          v -= V[(size_t)l * K + r] * Wp[(size_t)l * K + j] + Wp[(size_t)l * K + r] * V[(size_t)l * K + j];
+        W[(size_t)j * K + r] = v;
+      }
+      __syncthreads();
+      // (b) reflector H = I - tau v v^T with H x = beta e_1, x = W[j+1:, j]
+      double ss = 0.0;
+      for (int r = j + 2 + tid; r < K; r += kLT) {
+        const double x = W[(size_t)j * K + r];
+        ss += x * x;
+      }
+      ss = block_sum<kLT>(ss, red);
+      const double alpha = W[(size_t)j * K + j + 1];
+      double beta, tu, scale;
+      if (ss == 0.0) {
+        beta = alpha;
+        tu = 0.0;
+        scale = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+        tu = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      if (tid == 0) {
+        w.d[j] = W[(size_t)j * K + j];
+        w.e[j] = beta;
+        w.tau[j] = tu;
+      }
+      for (int r = tid; r < K; r += kLT) {
+        double vr = 0.0;
+        if (r == j + 1) vr = 1.0;
+        else if (r > j + 1) vr = W[(size_t)j * K + r] * scale;
+        vbuf[r] = vr;
+        V[(size_t)i * K + r] = vr;
+      }
+      __syncthreads();
+      for (int r = j + 2 + tid; r < K; r += kLT) W[(size_t)j * K + r] = vbuf[r];
+      // (c) y = A22 v (A22 = trailing block before this panel's updates),
+      //     t1 = Wp^T v, t2 = V^T v for the earlier panel columns
+      const int ncol = K - j - 1;
+      for (int q = wid; q < ncol + 2 * i; q += NW) {
+        const double* col;
+        if (q < ncol) col = W + (size_t)(j + 1 + q) * K;
+        else if (q < ncol + i) col = Wp + (size_t)(q - ncol) * K;
+        else col = V + (size_t)(q - ncol - i) * K;
+        double acc = 0.0;
+        for (int r = j + 1 + lane; r < K; r += 64) acc += col[r] * vbuf[r];
+        acc = wave_sum(acc);
+        if (lane == 0) {
+          if (q < ncol) ybuf[j + 1 + q] = acc;
+          else if (q < ncol + i) t1[q - ncol] = acc;
+          else t2[q - ncol - i] = acc;
+        }
+      }
+      __syncthreads();
+      // (d) y -= V t1 + Wp t2 ; w = tau y ; w += -tau/2 (w^T v) v
+      double pw = 0.0;
+      for (int r = j + 1 + tid; r < K; r += kLT) {
+        double y = ybuf[r];
+        for (int l = 0; l < i; ++l) y -= V[(size_t)l * K + r] * t1[l] + Wp[(size_t)l * K + r] * t2[l];
+        y *= tu;
+        ybuf[r] = y;
+        pw += y * vbuf[r];
+      }
+      pw = block_sum<kLT>(pw, red);
+      const double al = -0.5 * tu * pw;
+      for (int r = tid; r < K; r += kLT) Wp[(size_t)i * K + r] = (r > j) ? ybuf[r] + al * vbuf[r] : 0.0;
+      __syncthreads();
+    }
+    // trailing update A22 -= V Wp^T + Wp V^T on rows/cols >= j0 + nb
+    const int jn = j0 + nb, n2 = K - jn;
+    for (int idx = tid; idx < n2 * n2; idx += kLT) {
+      const int r = jn + idx % n2, c = jn + idx / n2;
+      double v = W[(size_t)c * K + r];
+      for (int l = 0; l < nb; ++l)
+        v -= V[(size_t)l * K + r] * Wp[(size_t)l * K + c] + Wp[(size_t)l * K + r] * V[(size_t)l * K + c];
+      W[(size_t)c * K + r] = v;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    w.d[K - 2] = W[(size_t)(K - 2) * K + K - 2];
+    w.d[K - 1] = W[(size_t)(K - 1) * K + K - 1];
+    w.e[K - 2] = W[(size_t)(K - 2) * K + K - 1];
+    w.e[K - 1] = 0.0;
+    w.tau[K - 2] = 0.0;
+    w.tau[K - 1] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3. eigenpairs of T on the smaller-signed side
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int K, double x, double pivmin) {
+  // number of eigenvalues of T smaller than x (LDL^T signs of T - x I)
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += (q < 0.0);
+  for (int i = 1; i < K; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+  }
+  return cnt;
+}
+
+template <bool ADMM>
+__global__ __launch_bounds__(kLT) void k_large_eig(LargeArgs a) {
+  __shared__ double sd[1024], se[1024], se2[1024];
+  __shared__ double slam[512];
+  __shared__ int cls[513];
+  __shared__ int info[4];
+  __shared__ double red[kLT / 64 + 1];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < K; i += kLT) {
+    sd[i] = w.d[i];
+    se[i] = (i < K - 1) ? w.e[i] : 0.0;
+  }
+  __syncthreads();
+  // negligible off-diagonals split T; they are set to zero
+  double tn = 0.0;
+  for (int i = tid; i < K; i += kLT) {
+    const double em = (i > 0) ? fabs(se[i - 1]) : 0.0;
+    tn = fmax(tn, fabs(sd[i]) + em + fabs(se[i]));
+  }
+  {
+    // block max through the sum helper on per-wave maxima
+    for (int off = 32; off > 0; off >>= 1) tn = fmax(tn, __shfl_xor(tn, off, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = tn;
+    __syncthreads();
+    if (tid == 0) {
+      double m = 0.0;
+      for (int q = 0; q < kLT / 64; ++q) m = fmax(m, red[q]);
+      red[kLT / 64] = m;
+    }
+    __syncthreads();
+    tn = red[kLT / 64];
+    __syncthreads();
+  }
+  double emax2 = 0.0;
+  for (int i = tid; i < K - 1; i += kLT) {
+    double ei = se[i];
+    if (fabs(ei) <= kEps * (fabs(sd[i]) + fabs(sd[i + 1]))) ei = 0.0;
+    se[i] = ei;
+    se2[i] = ei * ei;
+    emax2 = fmax(emax2, ei * ei);
+  }
+  if (tid == 0) se2[K - 1] = 0.0;
+  for (int off = 32; off > 0; off >>= 1) emax2 = fmax(emax2, __shfl_xor(emax2, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = emax2;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int q = 0; q < kLT / 64; ++q) m = fmax(m, red[q]);
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, m) / kEps;
+    const int nneg = sturm_count(sd, se2, K, 0.0, pivmin);
+    const int pos = (nneg <= K - nneg) ? 0 : 1;
+    info[0] = pos ? K - nneg : nneg;     // r
+    info[1] = pos;
+    info[2] = pos ? nneg : 0;            // index of the first chosen eigenvalue
+    red[0] = pivmin;
+  }
+  __syncthreads();
+  const double pivmin = red[0];
+  const int r = info[0], pos = info[1], first = info[2];
+  const double tnorm = fmax(tn, 2.2250738585072014e-308);
+  // Gershgorin interval
+  const double glo = -tnorm * (1.0 + 4.0 * kEps) - pivmin, ghi = tnorm * (1.0 + 4.0 * kEps) + pivmin;
+  for (int t = tid; t < r; t += kLT) {
+    const int k = first + t;
+    double lo = glo, hi = ghi;
+    for (int it = 0; it < 128; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin) break;
+      if (sturm_count(sd, se2, K, mid, pivmin) > k) hi = mid;
+      else lo = mid;
+    }
+    slam[t] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  // clusters of close eigenvalues (consecutive gaps below the threshold)
+  const double ortol = 1e-5 * tnorm;
+  if (tid == 0) {
+    int nc = 0;
+    for (int t = 0; t < r; ++t)
+      if (t == 0 || slam[t] - slam[t - 1] > ortol) cls[nc++] = t;
+    cls[nc] = r;
+    info[3] = nc;
+  }
+  __syncthreads();
+  const int ncl = info[3];
+  const double tiny = kEps * tnorm;
+  // one thread per cluster: inverse iteration with a partially pivoted LU
+  // of T - lambda I, orthogonalised against the cluster's earlier vectors
+  for (int c = tid; c < ncl; c += kLT) {
+    double* S = w.S + (size_t)c * 5 * K;
+    double* L = S;
+    double* U0 = S + K;
+    double* U1 = S + 2 * K;
+    double* U2 = S + 3 * K;
+    double* P = S + 4 * K;
+    for (int t = cls[c]; t < cls[c + 1]; ++t) {
+      const double lamb = slam[t];
+      // factor
+      double al = sd[0] - lamb, be = (K > 1) ? se[0] : 0.0;
+      for (int i = 0; i < K - 1; ++i) {
+        const double cc = se[i], an = sd[i + 1] - lamb, bn = (i + 1 < K - 1) ? se[i + 1] : 0.0;
+        if (fabs(al) >= fabs(cc)) {
+          if (fabs(al) < tiny) al = (al < 0.0) ? -tiny : tiny;
+          const double l = cc / al;
+          U0[i] = al;
+          U1[i] = be;
+          U2[i] = 0.0;
+          P[i] = 0.0;
+          L[i] = l;
+          al = an - l * be;
+          be = bn;
+        } else {
+          const double l = al / cc;
+          U0[i] = cc;
+          U1[i] = an;
+          U2[i] = bn;
+          P[i] = 1.0;
+          L[i] = l;
+          al = be - l * an;
+          be = -l * bn;
+        }
+      }
+      if (fabs(al) < tiny) al = (al < 0.0) ? -tiny : tiny;
+      U0[K - 1] = al;
+      double* z = w.Z + (size_t)t * K;
+      for (int i = 0; i < K; ++i) z[i] = hash_unit((uint32_t)t, (uint32_t)i);
+      for (int it = 0; it < 3; ++it) {
+        for (int i = 0; i < K - 1; ++i) {
+          if (P[i] != 0.0) {
+            const double tmp = z[i];
+            z[i] = z[i + 1];
+            z[i + 1] = tmp;
+          }
+          z[i + 1] -= L[i] * z[i];
+        }
+        z[K - 1] /= U0[K - 1];
+        if (K > 1) z[K - 2] = (z[K - 2] - U1[K - 2] * z[K - 1]) / U0[K - 2];
+        for (int i = K - 3; i >= 0; --i) z[i] = (z[i] - U1[i] * z[i + 1] - U2[i] * z[i + 2]) / U0[i];
+        for (int pass = 0; pass < 2; ++pass)
+          for (int p = cls[c]; p < t; ++p) {
+            const double* q = w.Z + (size_t)p * K;
+            double dot = 0.0;
+            for (int i = 0; i < K; ++i) dot += q[i] * z[i];
+            for (int i = 0; i < K; ++i) z[i] -= dot * q[i];
+          }
+        double nn = 0.0;
+        for (int i = 0; i < K; ++i) nn += z[i] * z[i];
+        const double sc = 1.0 / sqrt(nn);
+        for (int i = 0; i < K; ++i) z[i] *= sc;
+      }
+    }
+  }
+  for (int t = tid; t < r; t += kLT) w.lam[t] = slam[t];
+  if (tid == 0) {
+    w.meta[0] = (double)r;
+    w.meta[1] = (double)pos;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4. back-transformation V = Q Z = H_0 H_1 ... H_{K-3} Z
+// ---------------------------------------------------------------------------
+template <bool ADMM>
+__global__ __launch_bounds__(kLT) void k_large_backtrans(LargeArgs a) {
+  __shared__ double zc[kBtCols][1024];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int r = (int)w.meta[0];
+  const int c0 = blockIdx.y * kBtCols;
+  if (c0 >= r) return;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;   // one wave per column
+  const int col = c0 + wid;
+  if (col >= r) return;       // whole waves exit; no block barriers below
+  double* z = zc[wid];
+  const double* zg = w.Z + (size_t)col * K;
+  for (int i = lane; i < K; i += 64) z[i] = zg[i];
+  for (int j = K - 3; j >= 0; --j) {
+    const double tu = w.tau[j];
+    if (tu == 0.0) continue;
+    const double* vcol = w.W + (size_t)j * K;   // v_{j+1} = 1, v_i = W[i, j] for i >= j+2
+    double acc = 0.0;
+    for (int i = j + 1 + lane; i < K; i += 64) acc += ((i == j + 1) ? 1.0 : vcol[i]) * z[i];
+    acc = wave_sum(acc) * tu;
+    for (int i = j + 1 + lane; i < K; i += 64) z[i] -= acc * ((i == j + 1) ? 1.0 : vcol[i]);
+  }
+  double* zo = w.Z + (size_t)col * K;
+  for (int i = lane; i < K; i += 64) zo[i] = z[i];
+}
+
+// ---------------------------------------------------------------------------
+// 5. reconstruction tiles + fused dual update
+// ---------------------------------------------------------------------------
+template <bool ADMM>
+__global__ __launch_bounds__(256) void k_large_recon(LargeArgs a) {
+  __shared__ double Va[kTile][kTile + 1];
+  __shared__ double Vb[kTile][kTile + 1];
+  __shared__ double red[256 / 64 + 1];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int T = (K + kTile - 1) / kTile;
+  const int ntile = T * (T + 1) / 2;
+  const int q = blockIdx.y;
+  if (q >= ntile) return;
+  int ti = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > q) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= q) ++ti;
+  const int tj = q - ti * (ti + 1) / 2;
+  const int a0 = ti * kTile, b0 = tj * kTile;
+  const int r = (int)w.meta[0], pos = (int)w.meta[1];
+  const int tid = threadIdx.x;
+  const int ty = tid / 8, tx = tid % 8;          // 32 rows x (8 threads x 4 columns)
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int l0 = 0; l0 < r; l0 += kTile) {
+    for (int idx = tid; idx < kTile * kTile; idx += 256) {
+      const int ii = idx % kTile, ll = idx / kTile;
+      const int l = l0 + ll;
+      double va = 0.0, vb = 0.0;
+      if (l < r) {
+        const double* zl = w.Z + (size_t)l * K;
+        const double lm = w.lam[l];
+        if (a0 + ii < K) va = zl[a0 + ii] * lm;
+        if (b0 + ii < K) vb = zl[b0 + ii];
+      }
+      Va[ii][ll] = va;
+      Vb[ii][ll] = vb;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int ll = 0; ll < kTile; ++ll) {
+      const double x = Va[ty][ll];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += x * Vb[tx * 4 + u][ll];
+    }
+    __syncthreads();
+  }
+  double ex = 0.0, ev = 0.0;
+  const int ai = a0 + ty;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int bi = b0 + tx * 4 + u;
+    if (ai < K && bi < K && ai >= bi) {
+      const int t = packed_index(ai, bi, K);
+      const double sc = (ai == bi) ? 1.0 : kSqrt2;
+      const double y = yvec_of<ADMM>(a, base, t);
+      const double sp = pos ? acc[u] * sc : y - acc[u] * sc;
+      if (ADMM) {
+        const int64_t sl = base + t;
+        const double sv = a.d.s[sl], zv = a.d.z[sl], vv = a.d.v[sl];
+        const double xv = a.d.x[a.d.slot2ent[sl]];
+        const double zn = sp - y;
+        const double vn = 0.5 * (sv + zv + vv - xv);
+        a.d.s[sl] = sp;
+        a.d.z[sl] = zn;
+        a.d.v[sl] = vn;
+        ex += (xv - sp) * (xv - sp);
+        ev += (vn - zn) * (vn - zn);
+      } else {
+        a.pout[base + t] = sp;
+      }
+    }
+  }
+  if (ADMM) {
+    ex = block_sum<256>(ex, red);
+    ev = block_sum<256>(ev, red);
+    if (tid == 0) {
+      w.tiles[2 * q] = ex;
+      w.tiles[2 * q + 1] = ev;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_large_partials(LargeArgs a) {
+  int K;
+  int64_t base;
+  if (!task_info<true>(a, blockIdx.x, K, base)) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int T = (K + kTile - 1) / kTile;
+  const int ntile = T * (T + 1) / 2;
+  double ex = 0.0, ev = 0.0;
+  for (int q = threadIdx.x; q < ntile; q += 64) {
+    ex += w.tiles[2 * q];
+    ev += w.tiles[2 * q + 1];
+  }
+  ex = wave_sum(ex);
+  ev = wave_sum(ev);
+  if (threadIdx.x == 0) {
+    const int k = a.tasks[blockIdx.x];
+    a.d.part_c[2 * k] = ex;
+    a.d.part_c[2 * k + 1] = ev;
+  }
+}
+
+template <bool ADMM>
+static void run_large(const LargeArgs& a, int32_t ntask, int32_t kmax, hipStream_t st) {
+  if (ntask <= 0) return;
+  hipLaunchKernelGGL(k_large_gather<ADMM>, dim3(ntask), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_large_tridiag<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
+  hipLaunchKernelGGL(k_large_eig<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
+  const int rmax = kmax / 2 + 1;
+  hipLaunchKernelGGL(k_large_backtrans<ADMM>, dim3(ntask, (rmax + kBtCols - 1) / kBtCols), dim3(kLT), 0, st, a);
+  const int T = (kmax + kTile - 1) / kTile;
+  hipLaunchKernelGGL(k_large_recon<ADMM>, dim3(ntask, T * (T + 1) / 2), dim3(256), 0, st, a);
+  if (ADMM) hipLaunchKernelGGL(k_large_partials, dim3(ntask), dim3(64), 0, st, a);
+}
+
+void launch_cone_large(const DevPlan& d, const int32_t* tasks, const int32_t* /*host_sizes*/, int32_t ntask,
+                       int32_t kmax, hipStream_t st) {
+  LargeArgs a{};
+  a.d = d;
+  a.tasks = tasks;
+  a.work = d.big_work;
+  a.woff = d.big_off;
+  run_large<true>(a, ntask, kmax, st);
+}
+
+void launch_psd_project_large(const int32_t* sizes, const int64_t* offs, const int32_t* tasks,
+                              const int32_t* /*host_sizes*/, int32_t ntask, int32_t kmax, const double* in,
+                              double* out, double* work, const int64_t* work_off, hipStream_t st) {
+  LargeArgs a{};
+  a.tasks = tasks;
+  a.psizes = sizes;
+  a.poffs = offs;
+  a.pin = in;
+  a.pout = out;
+  a.work = work;
+  a.woff = work_off;
+  run_large<false>(a, ntask, kmax, st);
+}
 
 }  // namespace cdcs

@@ -152,11 +152,14 @@ def block_arrow_cliques(n, block, arrow):
     return cl, parent
 
 
-def block_arrow_instance(config, instance, n, block, arrow, m, density=0.3):
+def block_arrow_instance(config, instance, n, block, arrow, m, density=0.3, per_row=None):
+    """Block-arrow SDP; each A_i has `per_row` N(0,1) entries (default: a
+    fraction `density` of the pattern), made strictly feasible."""
     rng = rng_for(config, instance)
     cliques, parent = block_arrow_cliques(n, block, arrow)
     er, ec = pattern_entries(cliques)
-    per_row = int(np.floor(density * len(er) + 0.5))
+    if per_row is None:
+        per_row = int(np.floor(density * len(er) + 0.5))
     A = _random_constraints(rng, m, er, ec, per_row)
     b, C, meta = _feasible_data(rng, n, m, cliques, A)
     meta.update(block=block, arrow=arrow)
@@ -300,6 +303,6 @@ def config4(count=64):
     return out
 
 
-def small_block_arrow(instance, n=12, block=3, arrow=2, m=4):
+def small_block_arrow(instance, n=12, block=3, arrow=2, m=4, per_row=None):
     """Tiny instances for the oracle's pins and quick parity checks."""
-    return block_arrow_instance(90, instance, n=n, block=block, arrow=arrow, m=m)
+    return block_arrow_instance(90, instance, n=n, block=block, arrow=arrow, m=m, per_row=per_row)

@@ -56,6 +56,9 @@ def _rel(a, b):
     [17, 20, 31, 32],
     [33, 40, 63, 64],
     [65, 77, 95, 96],
+    [97, 128, 129, 200],
+    [333, 512, 673],
+    [1024],
 ])
 def test_psd_project_matches_oracle(lib, torch_cuda, sizes):
     torch = torch_cuda
@@ -77,15 +80,18 @@ def test_psd_project_matches_oracle(lib, torch_cuda, sizes):
     got = dev_out.cpu().numpy()
     for K, o in zip(sizes, offs):
         sl = slice(o, o + K * (K + 1) // 2)
-        assert np.linalg.norm(got[sl] - want[sl]) <= 1e-13 * np.linalg.norm(vec[sl]), K
+        err = np.linalg.norm(got[sl] - want[sl]) / np.linalg.norm(vec[sl])
+        _log(f"  K={K} rel err {err:.2e}")
+        assert err <= (1e-13 if K <= 96 else 1e-12), K
 
 
-def test_psd_project_special_blocks(lib, torch_cuda):
+@pytest.mark.parametrize("K", [12, 150])
+def test_psd_project_special_blocks(lib, torch_cuda, K):
     """Zero, PSD, NSD, rank-one and repeated-eigenvalue blocks."""
     torch = torch_cuda
+    _log(f"special blocks K={K}")
     rng = np.random.default_rng(5)
     mats = []
-    K = 12
     mats.append(np.zeros((K, K)))
     G = rng.standard_normal((K, K))
     mats.append(G @ G.T)
@@ -93,7 +99,8 @@ def test_psd_project_special_blocks(lib, torch_cuda):
     q = rng.standard_normal(K)
     mats.append(np.outer(q, q))
     Qm, _ = np.linalg.qr(rng.standard_normal((K, K)))
-    mats.append(Qm @ np.diag([1.0] * 6 + [-1.0] * 6) @ Qm.T)
+    mats.append(Qm @ np.diag([1.0] * (K // 2) + [-1.0] * (K - K // 2)) @ Qm.T)
+    mats.append(Qm @ np.diag([2.0] * 3 + [0.0] * (K - 5) + [-1.0] * 2) @ Qm.T)
     mats.append(np.eye(K) * 3.0)
     vec = np.concatenate([hsde.svec_blocks(M, K) for M in mats])
     sizes = [K] * len(mats)
@@ -105,7 +112,8 @@ def test_psd_project_special_blocks(lib, torch_cuda):
     nb = K * (K + 1) // 2
     for i in range(len(mats)):
         sl = slice(i * nb, (i + 1) * nb)
-        assert np.linalg.norm(got[sl] - want[sl]) <= 1e-13 * max(1.0, np.linalg.norm(vec[sl])), i
+        err = np.linalg.norm(got[sl] - want[sl]) / max(1.0, np.linalg.norm(vec[sl]))
+        assert err <= (1e-13 if K <= 96 else 1e-12), (i, err)
 
 
 # ----------------------------------------------------------------------------
@@ -144,6 +152,35 @@ def test_iterates_small_odd_sizes(lib, torch_cuda, seed):
     _log(f"iterates small seed={seed}")
     inst = configs.small_block_arrow(seed, n=23, block=5, arrow=3, m=7)
     _iterate_parity(lib, inst, 50)
+
+
+def test_iterates_large_cliques(lib, torch_cuda):
+    """Cliques of 130 and 250 vertices go through the tridiagonal path.
+
+    Sparse constraints (8 entries each) keep the data well scaled: with
+    dense constraints the step-1 Sherman-Morrison update cancels
+    O(||zeta||) intermediates down to an O(1e-2) iterate and FP64 itself
+    (either algebra route) carries ~1e-7 error there.
+    """
+    _log("iterates large cliques")
+    inst = configs.small_block_arrow(7, n=500, block=120, arrow=10, m=30, per_row=8)
+    w = _iterate_parity(lib, inst, 30)
+    _log(f"  worst rel {w:.2e}")
+    inst = configs.small_block_arrow(8, n=510, block=240, arrow=10, m=12, per_row=8)
+    w = _iterate_parity(lib, inst, 15)
+    _log(f"  worst rel {w:.2e}")
+
+
+def test_iterates_config2(lib, torch_cuda):
+    _log("iterates config2")
+    w = _iterate_parity(lib, configs.config2(), 20)
+    _log(f"  worst rel {w:.2e}")
+
+
+def test_iterates_config1(lib, torch_cuda):
+    _log("iterates config1 (max-cut n=2000, cliques up to 673)")
+    w = _iterate_parity(lib, configs.config1(), 4)
+    _log(f"  worst rel {w:.2e}")
 
 
 def test_solve_config0_matches_oracle(lib, torch_cuda):
