@@ -35,11 +35,13 @@ int set_error(int code, const std::string& msg) {
 
 enum Phase {
   PH_R0 = 0, PH_SPMV_A, PH_TRSV, PH_SPMV_AT, PH_SCALAR1, PH_UPDATE_E, PH_UPDATE_R,
-  PH_CONE16, PH_CONE32, PH_CONE64, PH_CONE96, PH_CONE_LARGE, PH_SCALAR2, kNumPhases
+  PH_CONE16, PH_CONE32, PH_CONE64, PH_CONE96, PH_LG_GATHER, PH_LG_TRIDIAG, PH_LG_EIG, PH_LG_BACKTRANS,
+  PH_LG_RECON, PH_LG_PARTIALS, PH_SCALAR2, kNumPhases
 };
 const char* kPhaseNames[kNumPhases] = {
     "r0_scatter", "spmv_A", "trsv", "spmv_At", "scalar1", "update_x", "update_y",
-    "cone_jacobi16", "cone_jacobi32", "cone_jacobi64", "cone_jacobi96", "cone_large", "scalar2"};
+    "cone_jacobi16", "cone_jacobi32", "cone_jacobi64", "cone_jacobi96", "large_gather", "large_tridiag",
+    "large_eig", "large_backtrans", "large_recon", "large_partials", "scalar2"};
 
 }  // namespace
 
@@ -157,10 +159,11 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
       PhaseTimer t(h, PH_CONE16 + bk);
       launch_cone_jacobi(d, h->tasks[bk], h->ntasks[bk], kmaxs[bk], st);
     }
-  if (h->ntasks[4]) {
-    PhaseTimer t(h, PH_CONE_LARGE);
-    launch_cone_large(d, h->tasks[4], h->large_sizes.data(), h->ntasks[4], h->kmax_large, st);
-  }
+  if (h->ntasks[4])
+    for (int step = 0; step < kLargeSteps; ++step) {
+      PhaseTimer t(h, PH_LG_GATHER + step);
+      launch_cone_large_step(d, h->tasks[4], h->ntasks[4], h->kmax_large, step, st);
+    }
   { PhaseTimer t(h, PH_SCALAR2); launch_scalar2(d, h->set.eps_tol, h->set.max_iter, stop, st); }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));

@@ -148,8 +148,10 @@ void launch_update_r(const DevPlan& d, hipStream_t st);
 void launch_scalar2(const DevPlan& d, double eps_tol, int32_t max_iter, int32_t stop, hipStream_t st);
 // cone step: tasks are clique ids; kind selects the kernel variant
 void launch_cone_jacobi(const DevPlan& d, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st);
-void launch_cone_large(const DevPlan& d, const int32_t* tasks, const int32_t* host_sizes,
-                       int32_t ntask, int32_t kmax, hipStream_t st);
+// large cliques: gather, tridiag, eig, backtrans, recon, partials
+constexpr int kLargeSteps = 6;
+void launch_cone_large_step(const DevPlan& d, const int32_t* tasks, int32_t ntask, int32_t kmax, int step,
+                            hipStream_t st);
 // stand-alone projection of packed blocks
 void launch_psd_project(const int32_t* sizes, const int64_t* offs, const int32_t* tasks, int32_t ntask,
                         int kmax, const double* in, double* out, hipStream_t st);

@@ -24,6 +24,7 @@ namespace cdcs {
 namespace {
 
 constexpr int kLT = 1024;        // threads of the per-task kernels
+constexpr int kTT = 512;         // threads of the tridiagonalisation kernel
 constexpr int kNB = 32;          // panel width of the tridiagonalisation
 constexpr int kTile = 32;        // reconstruction tile
 constexpr int kBtCols = 16;      // eigenvector columns per back-transform workgroup
@@ -140,11 +141,12 @@ __global__ __launch_bounds__(256) void k_large_gather(LargeArgs a) {
 // 2. Householder tridiagonalisation (lower, blocked panels)
 // ---------------------------------------------------------------------------
 template <bool ADMM>
-__global__ __launch_bounds__(kLT) void k_large_tridiag(LargeArgs a) {
+__global__ __launch_bounds__(kTT) void k_large_tridiag(LargeArgs a) {
   __shared__ double vbuf[1024];
   __shared__ double ybuf[1024];
   __shared__ double t1[kNB], t2[kNB];
-  __shared__ double red[kLT / 64 + 1];
+  __shared__ double red[kTT / 64 + 1];
+  __shared__ double pr_v[kNB][64], pr_w[kNB][64], pc_v[kNB][64], pc_w[kNB][64];
   int K;
   int64_t base;
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
@@ -153,13 +155,13 @@ __global__ __launch_bounds__(kLT) void k_large_tridiag(LargeArgs a) {
   double* V = w.S;
   double* Wp = w.S + (size_t)K * kNB;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  constexpr int NW = kLT / 64;
+  constexpr int NW = kTT / 64;
   for (int j0 = 0; j0 < K - 2; j0 += kNB) {
     const int nb = min(kNB, K - 2 - j0);
     for (int i = 0; i < nb; ++i) {
       const int j = j0 + i;
       // (a) bring column j up to date with the panel's earlier reflectors
-      for (int r = j + tid; r < K; r += kLT) {
+      for (int r = j + tid; r < K; r += kTT) {
         double v = W[(size_t)j * K + r];
         for (int l = 0; l < i; ++l)
           v -= V[(size_t)l * K + r] * Wp[(size_t)l * K + j] + Wp[(size_t)l * K + r] * V[(size_t)l * K + j];
@@ -168,11 +170,11 @@ __global__ __launch_bounds__(kLT) void k_large_tridiag(LargeArgs a) {
       __syncthreads();
       // (b) reflector H = I - tau v v^T with H x = beta e_1, x = W[j+1:, j]
       double ss = 0.0;
-      for (int r = j + 2 + tid; r < K; r += kLT) {
+      for (int r = j + 2 + tid; r < K; r += kTT) {
         const double x = W[(size_t)j * K + r];
         ss += x * x;
       }
-      ss = block_sum<kLT>(ss, red);
+      ss = block_sum<kTT>(ss, red);
       const double alpha = W[(size_t)j * K + j + 1];
       double beta, tu, scale;
       if (ss == 0.0) {
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(kLT) void k_large_tridiag(LargeArgs a) {
         w.e[j] = beta;
         w.tau[j] = tu;
       }
-      for (int r = tid; r < K; r += kLT) {
+      for (int r = tid; r < K; r += kTT) {
         double vr = 0.0;
         if (r == j + 1) vr = 1.0;
         else if (r > j + 1) vr = W[(size_t)j * K + r] * scale;
@@ -197,49 +199,90 @@ __global__ __launch_bounds__(kLT) void k_large_tridiag(LargeArgs a) {
         V[(size_t)i * K + r] = vr;
       }
       __syncthreads();
-      for (int r = j + 2 + tid; r < K; r += kLT) W[(size_t)j * K + r] = vbuf[r];
+      for (int r = j + 2 + tid; r < K; r += kTT) W[(size_t)j * K + r] = vbuf[r];
       // (c) y = A22 v (A22 = trailing block before this panel's updates),
-      //     t1 = Wp^T v, t2 = V^T v for the earlier panel columns
+      //     t1 = Wp^T v, t2 = V^T v for the earlier panel columns.  Each
+      //     wave takes 4 columns at a time with 4 rows per lane in flight.
       const int ncol = K - j - 1;
-      for (int q = wid; q < ncol + 2 * i; q += NW) {
-        const double* col;
-        if (q < ncol) col = W + (size_t)(j + 1 + q) * K;
-        else if (q < ncol + i) col = Wp + (size_t)(q - ncol) * K;
-        else col = V + (size_t)(q - ncol - i) * K;
-        double acc = 0.0;
-        for (int r = j + 1 + lane; r < K; r += 64) acc += col[r] * vbuf[r];
-        acc = wave_sum(acc);
-        if (lane == 0) {
-          if (q < ncol) ybuf[j + 1 + q] = acc;
-          else if (q < ncol + i) t1[q - ncol] = acc;
-          else t2[q - ncol - i] = acc;
+      const int nq = ncol + 2 * i;
+      for (int q0 = wid * 4; q0 < nq; q0 += NW * 4) {
+        const double* col[4];
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = min(q0 + u, nq - 1);
+          if (q < ncol) col[u] = W + (size_t)(j + 1 + q) * K;
+          else if (q < ncol + i) col[u] = Wp + (size_t)(q - ncol) * K;
+          else col[u] = V + (size_t)(q - ncol - i) * K;
+        }
+        int r = j + 1 + lane;
+        for (; r + 192 < K; r += 256) {
+          const double v0 = vbuf[r], v1 = vbuf[r + 64], v2 = vbuf[r + 128], v3 = vbuf[r + 192];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc[u] += col[u][r] * v0 + col[u][r + 64] * v1 + col[u][r + 128] * v2 + col[u][r + 192] * v3;
+        }
+        for (; r < K; r += 64) {
+          const double v0 = vbuf[r];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[u] += col[u][r] * v0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double sum = wave_sum(acc[u]);
+          const int q = q0 + u;
+          if (lane == 0 && q < nq) {
+            if (q < ncol) ybuf[j + 1 + q] = sum;
+            else if (q < ncol + i) t1[q - ncol] = sum;
+            else t2[q - ncol - i] = sum;
+          }
         }
       }
       __syncthreads();
       // (d) y -= V t1 + Wp t2 ; w = tau y ; w += -tau/2 (w^T v) v
       double pw = 0.0;
-      for (int r = j + 1 + tid; r < K; r += kLT) {
+      for (int r = j + 1 + tid; r < K; r += kTT) {
         double y = ybuf[r];
         for (int l = 0; l < i; ++l) y -= V[(size_t)l * K + r] * t1[l] + Wp[(size_t)l * K + r] * t2[l];
         y *= tu;
         ybuf[r] = y;
         pw += y * vbuf[r];
       }
-      pw = block_sum<kLT>(pw, red);
+      pw = block_sum<kTT>(pw, red);
       const double al = -0.5 * tu * pw;
-      for (int r = tid; r < K; r += kLT) Wp[(size_t)i * K + r] = (r > j) ? ybuf[r] + al * vbuf[r] : 0.0;
+      for (int r = tid; r < K; r += kTT) Wp[(size_t)i * K + r] = (r > j) ? ybuf[r] + al * vbuf[r] : 0.0;
       __syncthreads();
     }
-    // trailing update A22 -= V Wp^T + Wp V^T on rows/cols >= j0 + nb
+    // trailing update A22 -= V Wp^T + Wp V^T on rows/cols >= j0 + nb, in
+    // 64 x 64 tiles with the panel rows staged in LDS
     const int jn = j0 + nb, n2 = K - jn;
-    for (int idx = tid; idx < n2 * n2; idx += kLT) {
-      const int r = jn + idx % n2, c = jn + idx / n2;
-      double v = W[(size_t)c * K + r];
-      for (int l = 0; l < nb; ++l)
-        v -= V[(size_t)l * K + r] * Wp[(size_t)l * K + c] + Wp[(size_t)l * K + r] * V[(size_t)l * K + c];
-      W[(size_t)c * K + r] = v;
+    const int nt = (n2 + 63) / 64;
+    for (int tile = 0; tile < nt * nt; ++tile) {
+      const int r0 = jn + (tile % nt) * 64, c0 = jn + (tile / nt) * 64;
+      for (int idx = tid; idx < 64 * kNB; idx += kTT) {
+        const int rr = idx & 63, l = idx >> 6;
+        const bool okr = (r0 + rr < K) && l < nb, okc = (c0 + rr < K) && l < nb;
+        pr_v[l][rr] = okr ? V[(size_t)l * K + r0 + rr] : 0.0;
+        pr_w[l][rr] = okr ? Wp[(size_t)l * K + r0 + rr] : 0.0;
+        pc_v[l][rr] = okc ? V[(size_t)l * K + c0 + rr] : 0.0;
+        pc_w[l][rr] = okc ? Wp[(size_t)l * K + c0 + rr] : 0.0;
+      }
+      __syncthreads();
+      constexpr int CPT = 64 / (kTT / 64);        // tile columns per thread
+      const int rr = tid & 63, cq = tid >> 6;
+      if (r0 + rr < K) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+          const int cc = cq * CPT + u;
+          if (c0 + cc < K) {
+            double acc = 0.0;
+            for (int l = 0; l < nb; ++l) acc += pr_v[l][rr] * pc_w[l][cc] + pr_w[l][rr] * pc_v[l][cc];
+            W[(size_t)(c0 + cc) * K + r0 + rr] -= acc;
+          }
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (tid == 0) {
     w.d[K - 2] = W[(size_t)(K - 2) * K + K - 2];
@@ -569,26 +612,33 @@ __global__ __launch_bounds__(64) void k_large_partials(LargeArgs a) {
 }
 
 template <bool ADMM>
-static void run_large(const LargeArgs& a, int32_t ntask, int32_t kmax, hipStream_t st) {
+static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, int step, hipStream_t st) {
   if (ntask <= 0) return;
-  hipLaunchKernelGGL(k_large_gather<ADMM>, dim3(ntask), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_large_tridiag<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
-  hipLaunchKernelGGL(k_large_eig<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
   const int rmax = kmax / 2 + 1;
-  hipLaunchKernelGGL(k_large_backtrans<ADMM>, dim3(ntask, (rmax + kBtCols - 1) / kBtCols), dim3(kLT), 0, st, a);
   const int T = (kmax + kTile - 1) / kTile;
-  hipLaunchKernelGGL(k_large_recon<ADMM>, dim3(ntask, T * (T + 1) / 2), dim3(256), 0, st, a);
-  if (ADMM) hipLaunchKernelGGL(k_large_partials, dim3(ntask), dim3(64), 0, st, a);
+  switch (step) {
+    case 0: hipLaunchKernelGGL(k_large_gather<ADMM>, dim3(ntask), dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL(k_large_tridiag<ADMM>, dim3(ntask), dim3(kTT), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_large_eig<ADMM>, dim3(ntask), dim3(kLT), 0, st, a); break;
+    case 3:
+      hipLaunchKernelGGL(k_large_backtrans<ADMM>, dim3(ntask, (rmax + kBtCols - 1) / kBtCols), dim3(kLT), 0, st, a);
+      break;
+    case 4: hipLaunchKernelGGL(k_large_recon<ADMM>, dim3(ntask, T * (T + 1) / 2), dim3(256), 0, st, a); break;
+    case 5:
+      if (ADMM) hipLaunchKernelGGL(k_large_partials, dim3(ntask), dim3(64), 0, st, a);
+      break;
+    default: break;
+  }
 }
 
-void launch_cone_large(const DevPlan& d, const int32_t* tasks, const int32_t* /*host_sizes*/, int32_t ntask,
-                       int32_t kmax, hipStream_t st) {
+void launch_cone_large_step(const DevPlan& d, const int32_t* tasks, int32_t ntask, int32_t kmax, int step,
+                            hipStream_t st) {
   LargeArgs a{};
   a.d = d;
   a.tasks = tasks;
   a.work = d.big_work;
   a.woff = d.big_off;
-  run_large<true>(a, ntask, kmax, st);
+  run_large_step<true>(a, ntask, kmax, step, st);
 }
 
 void launch_psd_project_large(const int32_t* sizes, const int64_t* offs, const int32_t* tasks,
@@ -602,7 +652,7 @@ void launch_psd_project_large(const int32_t* sizes, const int64_t* offs, const i
   a.pout = out;
   a.work = work;
   a.woff = work_off;
-  run_large<false>(a, ntask, kmax, st);
+  for (int step = 0; step < kLargeSteps; ++step) run_large_step<false>(a, ntask, kmax, step, st);
 }
 
 }  // namespace cdcs
