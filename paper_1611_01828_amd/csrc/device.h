@@ -110,7 +110,8 @@ struct DevPlan {
 // LU / panel scratch, tridiagonal data, tile partials)
 inline int64_t large_work_size(int K) {
   const int64_t T = (K + 31) / 32;
-  return 5LL * K * K + 4LL * K + 16 + T * (T + 1) + 64;
+  const int64_t ld = (K + 7) & ~7;
+  return 5LL * ld * ld + 4LL * ld + 16 + T * (T + 1) + 64;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

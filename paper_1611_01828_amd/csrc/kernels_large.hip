@@ -36,30 +36,34 @@ __device__ __forceinline__ int packed_index(int a, int b, int K) {
   return b * K - (b * (b - 1)) / 2 + (a - b);
 }
 
-// workspace layout of one task (doubles), see large_work_size()
+// workspace layout of one task (doubles), see large_work_size(); the
+// matrix uses the padded leading dimension ld = K rounded up to 8
 struct Ws {
-  double* W;     // K*K   matrix, then Householder vectors below the subdiagonal
-  double* Z;     // K*K   eigenvectors (first r columns)
-  double* S;     // 3*K*K panel arrays / LU scratch
-  double* d;     // K     diagonal of T
-  double* e;     // K     off-diagonal of T
-  double* tau;   // K     reflector scalars
-  double* lam;   // K     chosen eigenvalues
+  double* W;     // ld*ld matrix, then Householder vectors below the subdiagonal
+  double* Z;     // ld*ld eigenvectors (first r columns, stride K)
+  double* S;     // 3*ld*ld panel arrays / LU scratch
+  double* d;     // ld    diagonal of T
+  double* e;     // ld    off-diagonal of T
+  double* tau;   // ld    reflector scalars
+  double* lam;   // ld    chosen eigenvalues
   double* meta;  // 16    [0] r, [1] 1 = positive side
   double* tiles; // 2 * ntiles partial sums
 };
 
+__device__ __forceinline__ int lead_dim(int K) { return (K + 7) & ~7; }
+
 __device__ __forceinline__ Ws ws_of(double* base, int K) {
   Ws w;
-  const size_t K2 = (size_t)K * K;
+  const int ld = lead_dim(K);
+  const size_t L2 = (size_t)ld * ld;
   w.W = base;
-  w.Z = base + K2;
-  w.S = base + 2 * K2;
-  w.d = base + 5 * K2;
-  w.e = w.d + K;
-  w.tau = w.e + K;
-  w.lam = w.tau + K;
-  w.meta = w.lam + K;
+  w.Z = base + L2;
+  w.S = base + 2 * L2;
+  w.d = base + 5 * L2;
+  w.e = w.d + ld;
+  w.tau = w.e + ld;
+  w.lam = w.tau + ld;
+  w.meta = w.lam + ld;
   w.tiles = w.meta + 16;
   return w;
 }
@@ -115,7 +119,7 @@ __device__ __forceinline__ double yvec_of(const LargeArgs& a, int64_t base, int 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// 1. gather
+// 1. gather (full symmetric, padded rows zeroed)
 // ---------------------------------------------------------------------------
 template <bool ADMM>
 __global__ __launch_bounds__(256) void k_large_gather(LargeArgs a) {
@@ -123,37 +127,46 @@ __global__ __launch_bounds__(256) void k_large_gather(LargeArgs a) {
   int64_t base;
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
   double* W = a.work + a.woff[blockIdx.x];
-  const int nslot = K * (K + 1) / 2;
-  // walk columns so that consecutive threads read consecutive slots
+  const int ld = lead_dim(K);
   for (int b = 0; b < K; ++b) {
     const int p0 = packed_index(b, b, K);
-    for (int i = b + threadIdx.x; i < K; i += 256) {
-      double y = yvec_of<ADMM>(a, base, p0 + (i - b));
-      if (i != b) y *= kInvSqrt2;
-      W[(size_t)b * K + i] = y;
-      W[(size_t)i * K + b] = y;
+    for (int i = b + threadIdx.x; i < ld; i += 256) {
+      double y = 0.0;
+      if (i < K) {
+        y = yvec_of<ADMM>(a, base, p0 + (i - b));
+        if (i != b) y *= kInvSqrt2;
+        W[(size_t)i * ld + b] = y;
+      }
+      W[(size_t)b * ld + i] = y;
     }
   }
-  (void)nslot;
 }
 
 // ---------------------------------------------------------------------------
-// 2. Householder tridiagonalisation (lower, blocked panels)
+// 2. Householder tridiagonalisation (blocked panels, full storage)
 // ---------------------------------------------------------------------------
+// All global loads of the hot loops are unconditional and aligned (double2
+// over the padded leading dimension, zero padding rows, v zero outside its
+// support), so a wave keeps many loads in flight instead of waiting on each.
 template <bool ADMM>
 __global__ __launch_bounds__(kTT) void k_large_tridiag(LargeArgs a) {
-  __shared__ double vbuf[1024];
+  __shared__ __align__(16) double vbuf[1024];
   __shared__ double ybuf[1024];
-  __shared__ double t1[kNB], t2[kNB];
+  __shared__ double t1[kNB], t2[kNB], cwj[kNB], cvj[kNB];
   __shared__ double red[kTT / 64 + 1];
-  __shared__ double pr_v[kNB][64], pr_w[kNB][64], pc_v[kNB][64], pc_w[kNB][64];
+  __shared__ double stage[2 * kNB * 128 + 2 * kNB * 64];
+  double(*pr_v)[128] = reinterpret_cast<double(*)[128]>(stage);
+  double(*pr_w)[128] = reinterpret_cast<double(*)[128]>(stage + kNB * 128);
+  double(*pc_v)[64] = reinterpret_cast<double(*)[64]>(stage + 2 * kNB * 128);
+  double(*pc_w)[64] = reinterpret_cast<double(*)[64]>(stage + 2 * kNB * 128 + kNB * 64);
   int K;
   int64_t base;
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int ld = lead_dim(K);
   double* W = w.W;
   double* V = w.S;
-  double* Wp = w.S + (size_t)K * kNB;
+  double* Wp = w.S + (size_t)ld * kNB;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   constexpr int NW = kTT / 64;
   for (int j0 = 0; j0 < K - 2; j0 += kNB) {
@@ -161,21 +174,26 @@ __global__ __launch_bounds__(kTT) void k_large_tridiag(LargeArgs a) {
     for (int i = 0; i < nb; ++i) {
       const int j = j0 + i;
       // (a) bring column j up to date with the panel's earlier reflectors
+      if (tid < i) {
+        cwj[tid] = Wp[(size_t)tid * ld + j];
+        cvj[tid] = V[(size_t)tid * ld + j];
+      }
+      __syncthreads();
       for (int r = j + tid; r < K; r += kTT) {
-        double v = W[(size_t)j * K + r];
-        for (int l = 0; l < i; ++l)
-          v -= V[(size_t)l * K + r] * Wp[(size_t)l * K + j] + Wp[(size_t)l * K + r] * V[(size_t)l * K + j];
-        W[(size_t)j * K + r] = v;
+        double v = W[(size_t)j * ld + r];
+#pragma unroll 4
+        for (int l = 0; l < i; ++l) v -= V[(size_t)l * ld + r] * cwj[l] + Wp[(size_t)l * ld + r] * cvj[l];
+        W[(size_t)j * ld + r] = v;
       }
       __syncthreads();
       // (b) reflector H = I - tau v v^T with H x = beta e_1, x = W[j+1:, j]
       double ss = 0.0;
       for (int r = j + 2 + tid; r < K; r += kTT) {
-        const double x = W[(size_t)j * K + r];
+        const double x = W[(size_t)j * ld + r];
         ss += x * x;
       }
       ss = block_sum<kTT>(ss, red);
-      const double alpha = W[(size_t)j * K + j + 1];
+      const double alpha = W[(size_t)j * ld + j + 1];
       double beta, tu, scale;
       if (ss == 0.0) {
         beta = alpha;
@@ -187,54 +205,59 @@ __global__ __launch_bounds__(kTT) void k_large_tridiag(LargeArgs a) {
         scale = 1.0 / (alpha - beta);
       }
       if (tid == 0) {
-        w.d[j] = W[(size_t)j * K + j];
+        w.d[j] = W[(size_t)j * ld + j];
         w.e[j] = beta;
         w.tau[j] = tu;
       }
-      for (int r = tid; r < K; r += kTT) {
+      for (int r = tid; r < ld; r += kTT) {
         double vr = 0.0;
         if (r == j + 1) vr = 1.0;
-        else if (r > j + 1) vr = W[(size_t)j * K + r] * scale;
+        else if (r > j + 1 && r < K) vr = W[(size_t)j * ld + r] * scale;
         vbuf[r] = vr;
-        V[(size_t)i * K + r] = vr;
+        V[(size_t)i * ld + r] = vr;
       }
       __syncthreads();
-      for (int r = j + 2 + tid; r < K; r += kTT) W[(size_t)j * K + r] = vbuf[r];
-      // (c) y = A22 v (A22 = trailing block before this panel's updates),
-      //     t1 = Wp^T v, t2 = V^T v for the earlier panel columns.  Each
-      //     wave takes 4 columns at a time with 4 rows per lane in flight.
-      const int ncol = K - j - 1;
-      const int nq = ncol + 2 * i;
-      for (int q0 = wid * 4; q0 < nq; q0 += NW * 4) {
-        const double* col[4];
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int r = j + 2 + tid; r < K; r += kTT) W[(size_t)j * ld + r] = vbuf[r];
+      // (c) y = A22 v and t1 = Wp^T v, t2 = V^T v (the 2i panel columns
+      //     appended to the column set): 8 columns per wave round, double2
+      //     row pairs per lane, no branches around the loads
+      {
+        const int r0 = (j + 1) & ~1;
+        const int nk = (ld - r0 + 127) / 128;
+        const int ncol = K - j - 1, nall = ncol + 2 * i;
+        for (int cg = wid * 8; cg < nall; cg += NW * 8) {
+          // W, V and Wp live in one workspace: address every column by its
+          // offset from W (V = W + 2 ld^2, Wp = V + 32 ld)
+          int coff[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int q = min(q0 + u, nq - 1);
-          if (q < ncol) col[u] = W + (size_t)(j + 1 + q) * K;
-          else if (q < ncol + i) col[u] = Wp + (size_t)(q - ncol) * K;
-          else col[u] = V + (size_t)(q - ncol - i) * K;
-        }
-        int r = j + 1 + lane;
-        for (; r + 192 < K; r += 256) {
-          const double v0 = vbuf[r], v1 = vbuf[r + 64], v2 = vbuf[r + 128], v3 = vbuf[r + 192];
+          for (int u = 0; u < 8; ++u) {
+            const int q = min(cg + u, nall - 1);
+            coff[u] = (q < ncol) ? (j + 1 + q) * ld
+                                 : 2 * ld * ld + ((q < ncol + i) ? (kNB + q - ncol) * ld : (q - ncol - i) * ld);
+          }
+          double acc[8];
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            acc[u] += col[u][r] * v0 + col[u][r + 64] * v1 + col[u][r + 128] * v2 + col[u][r + 192] * v3;
-        }
-        for (; r < K; r += 64) {
-          const double v0 = vbuf[r];
+          for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+          for (int k = 0; k < nk; ++k) {
+            const int r = r0 + 2 * lane + 128 * k;
+            const int rr = min(r, ld - 2);
+            const double2 vv = *reinterpret_cast<const double2*>(vbuf + rr);
+            const double m = (r < ld) ? 1.0 : 0.0;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) acc[u] += col[u][r] * v0;
-        }
+            for (int u = 0; u < 8; ++u) {
+              const double2 av = *reinterpret_cast<const double2*>(W + coff[u] + rr);
+              acc[u] += m * (av.x * vv.x + av.y * vv.y);
+            }
+          }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double sum = wave_sum(acc[u]);
-          const int q = q0 + u;
-          if (lane == 0 && q < nq) {
-            if (q < ncol) ybuf[j + 1 + q] = sum;
-            else if (q < ncol + i) t1[q - ncol] = sum;
-            else t2[q - ncol - i] = sum;
+          for (int u = 0; u < 8; ++u) {
+            const double sum = wave_sum(acc[u]);
+            const int q = cg + u;
+            if (lane == 0 && q < nall) {
+              if (q < ncol) ybuf[j + 1 + q] = sum;
+              else if (q < ncol + i) t1[q - ncol] = sum;
+              else t2[q - ncol - i] = sum;
+            }
           }
         }
       }
@@ -243,51 +266,73 @@ __global__ __launch_bounds__(kTT) void k_large_tridiag(LargeArgs a) {
       double pw = 0.0;
       for (int r = j + 1 + tid; r < K; r += kTT) {
         double y = ybuf[r];
-        for (int l = 0; l < i; ++l) y -= V[(size_t)l * K + r] * t1[l] + Wp[(size_t)l * K + r] * t2[l];
+#pragma unroll 4
+        for (int l = 0; l < i; ++l) y -= V[(size_t)l * ld + r] * t1[l] + Wp[(size_t)l * ld + r] * t2[l];
         y *= tu;
         ybuf[r] = y;
         pw += y * vbuf[r];
       }
       pw = block_sum<kTT>(pw, red);
       const double al = -0.5 * tu * pw;
-      for (int r = tid; r < K; r += kTT) Wp[(size_t)i * K + r] = (r > j) ? ybuf[r] + al * vbuf[r] : 0.0;
+      for (int r = tid; r < ld; r += kTT) Wp[(size_t)i * ld + r] = (r > j && r < K) ? ybuf[r] + al * vbuf[r] : 0.0;
       __syncthreads();
     }
-    // trailing update A22 -= V Wp^T + Wp V^T on rows/cols >= j0 + nb, in
-    // 64 x 64 tiles with the panel rows staged in LDS
+    // trailing update A22 -= V Wp^T + Wp V^T on rows/cols >= j0 + nb (both
+    // triangles): 128 x 64 tiles, panel rows staged in LDS, 4 x 4 outputs per
+    // thread
     const int jn = j0 + nb, n2 = K - jn;
-    const int nt = (n2 + 63) / 64;
-    for (int tile = 0; tile < nt * nt; ++tile) {
-      const int r0 = jn + (tile % nt) * 64, c0 = jn + (tile / nt) * 64;
+    const int ntr = (n2 + 127) / 128, ntc = (n2 + 63) / 64;
+    for (int tile = 0; tile < ntr * ntc; ++tile) {
+      const int r0 = jn + (tile % ntr) * 128, c0 = jn + (tile / ntr) * 64;
+      for (int idx = tid; idx < 128 * kNB; idx += kTT) {
+        const int rr = idx & 127, l = idx >> 7;
+        const bool ok = (r0 + rr < K) && l < nb;
+        pr_v[l][rr] = ok ? V[(size_t)l * ld + r0 + rr] : 0.0;
+        pr_w[l][rr] = ok ? Wp[(size_t)l * ld + r0 + rr] : 0.0;
+      }
       for (int idx = tid; idx < 64 * kNB; idx += kTT) {
-        const int rr = idx & 63, l = idx >> 6;
-        const bool okr = (r0 + rr < K) && l < nb, okc = (c0 + rr < K) && l < nb;
-        pr_v[l][rr] = okr ? V[(size_t)l * K + r0 + rr] : 0.0;
-        pr_w[l][rr] = okr ? Wp[(size_t)l * K + r0 + rr] : 0.0;
-        pc_v[l][rr] = okc ? V[(size_t)l * K + c0 + rr] : 0.0;
-        pc_w[l][rr] = okc ? Wp[(size_t)l * K + c0 + rr] : 0.0;
+        const int cc = idx & 63, l = idx >> 6;
+        const bool ok = (c0 + cc < K) && l < nb;
+        pc_v[l][cc] = ok ? V[(size_t)l * ld + c0 + cc] : 0.0;
+        pc_w[l][cc] = ok ? Wp[(size_t)l * ld + c0 + cc] : 0.0;
       }
       __syncthreads();
-      constexpr int CPT = 64 / (kTT / 64);        // tile columns per thread
-      const int rr = tid & 63, cq = tid >> 6;
-      if (r0 + rr < K) {
+      const int tr = tid & 31, tc = tid >> 5;     // rows tr + 32 u, columns 4 tc + q
+      double acc[4][4];
 #pragma unroll
-        for (int u = 0; u < CPT; ++u) {
-          const int cc = cq * CPT + u;
-          if (c0 + cc < K) {
-            double acc = 0.0;
-            for (int l = 0; l < nb; ++l) acc += pr_v[l][rr] * pc_w[l][cc] + pr_w[l][rr] * pc_v[l][cc];
-            W[(size_t)(c0 + cc) * K + r0 + rr] -= acc;
-          }
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[u][q] = 0.0;
+      for (int l = 0; l < nb; ++l) {
+        double cv[4], cw[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          cv[q] = pc_v[l][4 * tc + q];
+          cw[q] = pc_w[l][4 * tc + q];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double rv = pr_v[l][tr + 32 * u], rw = pr_w[l][tr + 32 * u];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[u][q] += rv * cw[q] + rw * cv[q];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + tr + 32 * u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = c0 + 4 * tc + q;
+          if (r < K && c < K) W[(size_t)c * ld + r] -= acc[u][q];
         }
       }
       __syncthreads();
     }
   }
   if (tid == 0) {
-    w.d[K - 2] = W[(size_t)(K - 2) * K + K - 2];
-    w.d[K - 1] = W[(size_t)(K - 1) * K + K - 1];
-    w.e[K - 2] = W[(size_t)(K - 2) * K + K - 1];
+    w.d[K - 2] = W[(size_t)(K - 2) * ld + K - 2];
+    w.d[K - 1] = W[(size_t)(K - 1) * ld + K - 1];
+    w.e[K - 2] = W[(size_t)(K - 2) * ld + K - 1];
     w.e[K - 1] = 0.0;
     w.tau[K - 2] = 0.0;
     w.tau[K - 1] = 0.0;
@@ -496,7 +541,7 @@ __global__ __launch_bounds__(kLT) void k_large_backtrans(LargeArgs a) {
   for (int j = K - 3; j >= 0; --j) {
     const double tu = w.tau[j];
     if (tu == 0.0) continue;
-    const double* vcol = w.W + (size_t)j * K;   // v_{j+1} = 1, v_i = W[i, j] for i >= j+2
+    const double* vcol = w.W + (size_t)j * lead_dim(K);   // v_{j+1} = 1, v_i = W[i, j] for i >= j+2
     double acc = 0.0;
     for (int i = j + 1 + lane; i < K; i += 64) acc += ((i == j + 1) ? 1.0 : vcol[i]) * z[i];
     acc = wave_sum(acc) * tu;
