@@ -168,6 +168,20 @@ int cdcs_get_certificate(const cdcs_handle* h, int32_t inst, double* y_cert, dou
 int cdcs_get_state(const cdcs_handle* h, int32_t inst, double* u, double* vt);
 int cdcs_set_state(cdcs_handle* h, int32_t inst, const double* u, const double* vt);
 
+/* Reverse-mode derivative of the solution with respect to the data, through
+ * the fixed point of the ADMM iteration (eqs. Step1-Step3 written as
+ * z+ = T(z) with z = u - v~; implicit differentiation of z* = T(z*)).
+ * dX (NE values: per instance, svec over E' in canonical order, concatenated
+ * over instances) is dL/dX for X = x / tau.  Outputs: dC (NE values, dL/dc
+ * for c = svec(C), i.e. the gradient with respect to C as an svec) and db
+ * (sum of m values, dL/db).  The adjoint fixed-point iteration stops when
+ * ||mu+ - mu|| <= tol ||mu|| for every instance or after max_iter steps;
+ * *iters (may be NULL) receives the count.  on_device = 1: dX, dC, db are
+ * device pointers.  Every instance must be SOLVED (CDCS_E_STATE) and have
+ * cliques of at most 64 vertices (CDCS_E_ARG). */
+int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32_t on_device,
+                 int32_t max_iter, double tol, int32_t* iters);
+
 /* Accumulated HIP-event time (ms) and launch count per kernel phase since
  * setup or the last reset (timing must be enabled).  names/ms/launches may
  * be NULL; returns the number of phases. */

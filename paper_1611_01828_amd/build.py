@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcdcs.so")
 OBJ = os.path.join(HERE, "_build")
 
-SOURCES = ["setup.cpp", "api.hip", "kernels_iter.hip", "kernels_cone.hip", "kernels_large.hip"]
+SOURCES = ["setup.cpp", "api.hip", "kernels_iter.hip", "kernels_cone.hip", "kernels_large.hip",
+           "kernels_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include")]
 # packed FP32 instructions stay off in every HIP translation unit

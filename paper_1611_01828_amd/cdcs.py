@@ -53,7 +53,7 @@ EXPORTS = [
     "cdcs_default_settings", "cdcs_setup", "cdcs_setup_batch", "cdcs_iterate", "cdcs_solve",
     "cdcs_get_dims", "cdcs_get_entries", "cdcs_get_solution", "cdcs_get_certificate",
     "cdcs_get_state", "cdcs_set_state", "cdcs_get_phase_times", "cdcs_reset_phase_times",
-    "cdcs_psd_project", "cdcs_last_error", "cdcs_abi_version", "cdcs_destroy",
+    "cdcs_psd_project", "cdcs_adjoint", "cdcs_last_error", "cdcs_abi_version", "cdcs_destroy",
 ]
 
 
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
     lib.cdcs_get_phase_times.argtypes = [vp, C.POINTER(C.c_char_p), _dp, _i64p, C.c_int32]
     lib.cdcs_reset_phase_times.argtypes = [vp]
     lib.cdcs_psd_project.argtypes = [C.c_int32, _i32p, _i64p, vp, vp, vp]
+    lib.cdcs_adjoint.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_int32)]
     lib.cdcs_last_error.restype = C.c_char_p
     lib.cdcs_last_error.argtypes = []
     lib.cdcs_abi_version.restype = C.c_int
@@ -258,6 +259,27 @@ class Solver:
         X = np.full(nE, np.nan)
         _check(load().cdcs_get_certificate(self.h, i, y.ctypes.data, X.ctypes.data, 0))
         return y, X
+
+    def adjoint(self, dX, max_iter=20000, tol=1e-12):
+        """dL/dc (svec over E', all instances concatenated) and dL/db for
+        dL/dX = dX (numpy arrays on the host)."""
+        NE = sum(d[0] for d in self._dims)
+        M = sum(d[2] for d in self._dims)
+        dX = np.ascontiguousarray(dX, dtype=np.float64)
+        assert dX.shape == (NE,)
+        dc = np.empty(NE)
+        db = np.empty(M)
+        it = C.c_int32()
+        _check(load().cdcs_adjoint(self.h, dX.ctypes.data, dc.ctypes.data, db.ctypes.data, 0,
+                                   int(max_iter), float(tol), C.byref(it)))
+        return dc, db, it.value
+
+    def adjoint_device(self, dX, dc, db, max_iter=20000, tol=1e-12):
+        """As adjoint(), on torch CUDA tensors (float64)."""
+        it = C.c_int32()
+        _check(load().cdcs_adjoint(self.h, C.c_void_p(dX.data_ptr()), C.c_void_p(dc.data_ptr()),
+                                   C.c_void_p(db.data_ptr()), 1, int(max_iter), float(tol), C.byref(it)))
+        return it.value
 
     def phase_times(self):
         cap = 32

@@ -17,6 +17,31 @@
 
 using namespace cdcs;
 
+namespace cdcs {
+enum As { AS_QT = 0, AS_GT, AS_DEN2, AS_DIFF2, AS_NORM2, AS_BY, AS_EA, kNas = 8 };
+struct AdjPlan {
+  DevPlan d;
+  double* as;
+  double* mu_x;
+  double* mu_s;
+  double* mu_y;
+  double* mu_v;
+  double* mu_t;
+  double* qx;
+  const double* gx;
+  const double* phi;
+  const double* ev;
+  const double* aphi;
+  const double* eig;
+  const int64_t* eig_off;
+  double* dc;
+  double* db;
+};
+void launch_adj_eig(const AdjPlan& ap, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st);
+void launch_adj_iteration(const AdjPlan& ap, const int32_t* const* tasks, const int32_t* ntasks,
+                          int final_pass, hipStream_t st);
+}  // namespace cdcs
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -67,6 +92,9 @@ struct cdcs_handle {
   int64_t phase_n[kNumPhases] = {};
   // graphs
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  // adjoint buffers (allocated on the first cdcs_adjoint call)
+  bool adj_ready = false;
+  AdjPlan adj{};
   double setup_s = 0.0;
 };
 
@@ -744,6 +772,148 @@ int cdcs_get_certificate(const cdcs_handle* h, int32_t inst, double* y_cert, dou
     return put_out(h, X_cert, xo, on_device);
   }
   return set_error(CDCS_E_STATE, "instance is not infeasible");
+}
+
+namespace {
+
+// data of the transposed solve (I - Q) q = mu that depends only on the problem:
+// phi = F^{-1}(c + A^T b), A phi, e = c - A^T b, 1 + ||b||^2 + e^T phi
+int adjoint_prepare(cdcs_handle* h) {
+  if (h->adj_ready) return 0;
+  const int32_t B = h->B;
+  const int64_t NE = h->ent_off[B];
+  const int32_t M = h->row_off[B], P = h->clq_off[B];
+  std::vector<double> phi(NE), ev(NE), aphi(M), as((size_t)B * kNas, 0.0);
+  for (int32_t i = 0; i < B; ++i) {
+    const Instance& I = h->inst[i];
+    const int64_t eo = h->ent_off[i];
+    const int32_t ro = h->row_off[i];
+    std::vector<double> atb(I.nE, 0.0), pinv(I.nE), q(I.nE), g(I.m, 0.0);
+    for (int32_t r = 0; r < I.m; ++r)
+      for (int32_t t = I.aptr[r]; t < I.aptr[r + 1]; ++t) atb[I.acol[t]] += I.aval[t] * I.b[r];
+    for (int64_t e = 0; e < I.nE; ++e) {
+      pinv[e] = 1.0 / (1.0 + 0.5 * I.D[e]);
+      q[e] = pinv[e] * (I.c[e] + atb[e]);
+    }
+    for (int32_t r = 0; r < I.m; ++r)
+      for (int32_t t = I.aptr[r]; t < I.aptr[r + 1]; ++t) g[r] += I.aval[t] * q[I.acol[t]];
+    I.fac.solve(g);
+    std::vector<double> atw(I.nE, 0.0);
+    for (int32_t r = 0; r < I.m; ++r)
+      for (int32_t t = I.aptr[r]; t < I.aptr[r + 1]; ++t) atw[I.acol[t]] += I.aval[t] * g[r];
+    double etphi = 0.0, bb = 0.0;
+    for (int64_t e = 0; e < I.nE; ++e) {
+      phi[eo + e] = q[e] - pinv[e] * atw[e];
+      ev[eo + e] = I.c[e] - atb[e];
+      etphi += ev[eo + e] * phi[eo + e];
+    }
+    for (int32_t r = 0; r < I.m; ++r) {
+      aphi[ro + r] = g[r];
+      bb += I.b[r] * I.b[r];
+    }
+    as[(size_t)i * kNas + AS_DEN2] = 1.0 + bb + etphi;
+  }
+  AdjPlan& a = h->adj;
+  a.d = h->d;
+  int rc;
+  int32_t* zst = nullptr;
+  if ((rc = dev_zeros(h, &zst, (size_t)B * kNst))) return rc;
+  a.d.st = zst;                          // the adjoint runs on every instance
+  if ((rc = dev_upload(h, (double**)&a.phi, phi)) || (rc = dev_upload(h, (double**)&a.ev, ev)) ||
+      (rc = dev_upload(h, (double**)&a.aphi, aphi)) || (rc = dev_upload(h, &a.as, as)) ||
+      (rc = dev_zeros(h, &a.mu_x, NE)) || (rc = dev_zeros(h, &a.mu_s, h->slot_off[B])) ||
+      (rc = dev_zeros(h, &a.mu_y, M)) || (rc = dev_zeros(h, &a.mu_v, h->slot_off[B])) ||
+      (rc = dev_zeros(h, &a.mu_t, B)) || (rc = dev_zeros(h, &a.qx, NE)) ||
+      (rc = dev_zeros(h, (double**)&a.gx, NE)) || (rc = dev_zeros(h, &a.dc, NE)) || (rc = dev_zeros(h, &a.db, M)))
+    return rc;
+  std::vector<int64_t> eoff(P);
+  int64_t tot = 0;
+  for (int32_t i = 0; i < B; ++i)
+    for (int32_t k = 0; k < h->inst[i].p; ++k) {
+      const int64_t K = h->inst[i].csize[k];
+      eoff[h->clq_off[i] + k] = tot;
+      tot += K * K + K;
+    }
+  if ((rc = dev_zeros(h, (double**)&a.eig, tot)) || (rc = dev_upload(h, (int64_t**)&a.eig_off, eoff))) return rc;
+  h->adj_ready = true;
+  return 0;
+}
+
+}  // namespace
+
+int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32_t on_device, int32_t max_iter,
+                 double tol, int32_t* iters) {
+  if (!h || !dX || max_iter < 1 || !(tol > 0.0)) return set_error(CDCS_E_ARG, "bad adjoint arguments");
+  if (h->ntasks[3] || h->ntasks[4]) return set_error(CDCS_E_ARG, "the adjoint supports cliques of up to 64 vertices");
+  const int32_t B = h->B;
+  const int64_t NE = h->ent_off[B];
+  const int32_t M = h->row_off[B];
+  HIPCHK(hipStreamSynchronize(h->stream));
+  std::vector<double> sc((size_t)B * kNsc);
+  std::vector<int32_t> stv((size_t)B * kNst);
+  HIPCHK(hipMemcpy(sc.data(), h->d.sc, sc.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(stv.data(), h->d.st, stv.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int32_t i = 0; i < B; ++i)
+    if (stv[(size_t)i * kNst + ST_STATUS] != CDCS_SOLVED || !(sc[(size_t)i * kNsc + SC_TAU] > 0.0))
+      return set_error(CDCS_E_STATE, "instance " + std::to_string(i) + " is not solved");
+  int rc = adjoint_prepare(h);
+  if (rc) return rc;
+  AdjPlan& a = h->adj;
+  // g = DPi dL/du with dL/dx = w / tau, dL/dtau = -w^T x / tau^2 (X = x / tau)
+  std::vector<double> w(NE), x(NE), gx(NE);
+  if (on_device) HIPCHK(hipMemcpy(w.data(), dX, NE * sizeof(double), hipMemcpyDeviceToHost));
+  else std::memcpy(w.data(), dX, NE * sizeof(double));
+  HIPCHK(hipMemcpy(x.data(), h->d.x, NE * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> as((size_t)B * kNas);
+  HIPCHK(hipMemcpy(as.data(), a.as, as.size() * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> mut(B);
+  for (int32_t i = 0; i < B; ++i) {
+    const double tau = sc[(size_t)i * kNsc + SC_TAU];
+    double wx = 0.0;
+    for (int64_t e = h->ent_off[i]; e < h->ent_off[i + 1]; ++e) {
+      gx[e] = w[e] / tau;
+      wx += w[e] * x[e];
+    }
+    as[(size_t)i * kNas + AS_GT] = -wx / (tau * tau);
+    mut[i] = as[(size_t)i * kNas + AS_GT];
+  }
+  HIPCHK(hipMemcpy(const_cast<double*>(a.gx), gx.data(), NE * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(a.mu_x, gx.data(), NE * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(a.mu_t, mut.data(), B * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(a.as, as.data(), as.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(a.mu_s, 0, h->slot_off[B] * sizeof(double)));
+  HIPCHK(hipMemset(a.mu_v, 0, h->slot_off[B] * sizeof(double)));
+  HIPCHK(hipMemset(a.mu_y, 0, M * sizeof(double)));
+  // eigenpairs of the clique blocks at the solution
+  const int kmaxs[3] = {16, 32, 64};
+  for (int bk = 0; bk < 3; ++bk) launch_adj_eig(a, h->tasks[bk], h->ntasks[bk], kmaxs[bk], h->stream);
+  const int32_t* tl[3] = {h->tasks[0], h->tasks[1], h->tasks[2]};
+  const int32_t nt[3] = {h->ntasks[0], h->ntasks[1], h->ntasks[2]};
+  int32_t it = 0;
+  for (; it < max_iter;) {
+    const int32_t chunk = std::min<int32_t>(10, max_iter - it);
+    for (int32_t c = 0; c < chunk; ++c) launch_adj_iteration(a, tl, nt, 0, h->stream);
+    it += chunk;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("adjoint launch: ") + hipGetErrorString(e));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpy(as.data(), a.as, as.size() * sizeof(double), hipMemcpyDeviceToHost));
+    bool done = true;
+    for (int32_t i = 0; i < B; ++i) {
+      const double d2 = as[(size_t)i * kNas + AS_DIFF2], n2 = as[(size_t)i * kNas + AS_NORM2];
+      if (!(d2 <= tol * tol * std::max(n2, 1e-300))) done = false;
+    }
+    if (done) break;
+  }
+  // nu = (I - Q)^{-1} mu and the data gradients
+  launch_adj_iteration(a, tl, nt, 1, h->stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("adjoint launch: ") + hipGetErrorString(e));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (iters) *iters = it;
+  if (dC) HIPCHK(hipMemcpy(dC, a.dc, NE * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  if (db) HIPCHK(hipMemcpy(db, a.db, M * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  return 0;
 }
 
 int cdcs_get_phase_times(const cdcs_handle* h, const char** names, double* ms, int64_t* launches, int32_t cap) {

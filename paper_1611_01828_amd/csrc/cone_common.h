@@ -1,0 +1,159 @@
+// Device routines shared by the cone kernels and the adjoint kernels: packed
+// (svec) block indexing, the symmetric 2x2 Schur rotation and cyclic Jacobi
+// with round-robin parallel ordering on a block held in LDS (Golub & Van
+// Loan, Matrix Computations, Sections 8.5.2-8.5.5).
+#pragma once
+
+#include "device.h"
+
+namespace cdcs {
+
+namespace jac {
+
+constexpr double kSqrt2 = 1.4142135623730951;
+constexpr double kInvSqrt2 = 0.70710678118654752;
+
+// packed column-major lower index of (a, b), a >= b, in a K x K block
+__device__ __forceinline__ int packed_index(int a, int b, int K) {
+  return b * K - (b * (b - 1)) / 2 + (a - b);
+}
+
+// inverse of packed_index: column b is the largest with b K - b (b-1)/2 <= t
+__device__ __forceinline__ void unpack_index(int t, int K, int& a, int& b) {
+  const double k2 = 2.0 * K + 1.0;
+  int bb = (int)((k2 - sqrt(k2 * k2 - 8.0 * t)) * 0.5);
+  if (bb < 0) bb = 0;
+  if (bb > K - 1) bb = K - 1;
+  while (bb > 0 && packed_index(bb, bb, K) > t) --bb;
+  while (bb < K - 1 && packed_index(bb + 1, bb + 1, K) <= t) ++bb;
+  b = bb;
+  a = bb + (t - packed_index(bb, bb, K));
+}
+
+// Symmetric Schur 2x2: (c, s, t) with t = tan(theta) annihilating A_pq.
+__device__ __forceinline__ void schur2(double app, double aqq, double apq, double& c, double& s,
+                                      double& t) {
+  if (apq == 0.0) {
+    c = 1.0;
+    s = 0.0;
+    t = 0.0;
+    return;
+  }
+  const double theta = (aqq - app) / (2.0 * apq);
+  const double at = fabs(theta);
+  double tt;
+  if (at > 1e150) {
+    tt = 0.5 / theta;
+  } else {
+    tt = 1.0 / (at + sqrt(1.0 + at * at));
+    if (theta < 0.0) tt = -tt;
+  }
+  c = 1.0 / sqrt(1.0 + tt * tt);
+  s = tt * c;
+  t = tt;
+}
+
+}  // namespace jac
+
+using namespace jac;
+
+// Cyclic Jacobi on the KP x KP (KP even, zero padded) matrix in LDS.  On
+// return A holds the eigenvalues on its diagonal and V the eigenvectors.
+template <int KMAX, int NT>
+__device__ void jacobi_lds(double* A, double* V, int K, int KP, double* rc, double* rs, double* rt,
+                           int* rp, int* rq, double* red) {
+  const int tid = threadIdx.x;
+  const int half = KP / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int idx = tid; idx < K * K; idx += NT) {
+      const int i = idx / K, j = idx - (idx / K) * K;
+      const double a = A[i * KMAX + j];
+      tot += a * a;
+      if (i != j) off += a * a;
+    }
+    off = block_sum<NT>(off, red);
+    tot = block_sum<NT>(tot, red);
+    if (!(off > 1e-32 * tot)) break;   // off(A) <= 1e-16 ||A||_F (also stops on 0 or NaN)
+    for (int r = 0; r < KP - 1; ++r) {
+      if (tid < half) {
+        int p, q;
+        if (tid == 0) {
+          p = 0;
+          q = 1 + (r % (KP - 1));
+        } else {
+          p = 1 + ((tid + r) % (KP - 1));
+          q = 1 + ((KP - 1 - tid + r) % (KP - 1));
+        }
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        double c, s, t;
+        schur2(A[p * KMAX + p], A[q * KMAX + q], A[p * KMAX + q], c, s, t);
+        rp[tid] = p;
+        rq[tid] = q;
+        rc[tid] = c;
+        rs[tid] = s;
+        rt[tid] = t;
+      }
+      __syncthreads();
+      // A <- J^T A J on disjoint 2x2 blocks; V <- V J
+      for (int idx = tid; idx < half * half; idx += NT) {
+        const int a = idx / half, bq = idx - (idx / half) * half;
+        const int pa = rp[a], qa = rq[a], pb = rp[bq], qb = rq[bq];
+        if (a == bq) {
+          const double t = rt[a];
+          const double apq = A[pa * KMAX + qa];
+          A[pa * KMAX + pa] -= t * apq;
+          A[qa * KMAX + qa] += t * apq;
+          A[pa * KMAX + qa] = 0.0;
+          A[qa * KMAX + pa] = 0.0;
+        } else {
+          const double ca = rc[a], sa = rs[a], cb = rc[bq], sb = rs[bq];
+          const double x00 = A[pa * KMAX + pb], x01 = A[pa * KMAX + qb];
+          const double x10 = A[qa * KMAX + pb], x11 = A[qa * KMAX + qb];
+          const double y00 = ca * x00 - sa * x10, y01 = ca * x01 - sa * x11;
+          const double y10 = sa * x00 + ca * x10, y11 = sa * x01 + ca * x11;
+          A[pa * KMAX + pb] = y00 * cb - y01 * sb;
+          A[pa * KMAX + qb] = y00 * sb + y01 * cb;
+          A[qa * KMAX + pb] = y10 * cb - y11 * sb;
+          A[qa * KMAX + qb] = y10 * sb + y11 * cb;
+        }
+      }
+      for (int idx = tid; idx < KP * half; idx += NT) {
+        const int i = idx / half, bq = idx - (idx / half) * half;
+        const int pb = rp[bq], qb = rq[bq];
+        const double cb = rc[bq], sb = rs[bq];
+        const double vp = V[i * KMAX + pb], vq = V[i * KMAX + qb];
+        V[i * KMAX + pb] = cb * vp - sb * vq;
+        V[i * KMAX + qb] = sb * vp + cb * vq;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Select the cheaper side of the spectrum: Pi_+(Y) = sum_{l>0} lam_l v v^T
+// = Y - sum_{l<0} lam_l v v^T.  Fills sel[0..nsel) and returns sign flag
+// (1 = positive side).  Runs on thread 0 only; result broadcast via LDS.
+template <int NT>
+__device__ void choose_side(const double* A, int K, int KMAX_, int* sel, int* meta) {
+  if (threadIdx.x == 0) {
+    int npos = 0;
+    for (int l = 0; l < K; ++l) npos += (A[l * KMAX_ + l] > 0.0);
+    const int pos = (npos <= K - npos) ? 1 : 0;
+    int n = 0;
+    for (int l = 0; l < K; ++l) {
+      const double lam = A[l * KMAX_ + l];
+      if (pos ? (lam > 0.0) : (lam < 0.0)) sel[n++] = l;
+    }
+    meta[0] = n;
+    meta[1] = pos;
+  }
+  __syncthreads();
+}
+
+
+}  // namespace cdcs

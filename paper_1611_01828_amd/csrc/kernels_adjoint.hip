@@ -1,0 +1,355 @@
+// Reverse-mode derivative of a solved SDP through the ADMM fixed point.
+//
+// With z = u - v~ the iteration (Step1)-(Step3) is z+ = T(z) =
+// z + R(2 Pi(z) - z) - Pi(z), R = (I + Q)^{-1}.  At a fixed point z*, for a
+// loss with g = DPi dL/du, the adjoint mu solves mu = T'^T mu + g, i.e.
+//   mu <- mu - q + DPi(2 q - mu) + g,   q = (I - Q)^{-1} mu,
+// and with nu = (I - Q)^{-1} mu the data gradients are
+//   dL/dc = -(tau nu_x - nu_tau x),   dL/db = tau nu_y - nu_tau y.
+//
+// (I - Q) q = mu is solved with the same cached factor as step 1:
+//   t   = mu_x - A^T mu_y - H^T(mu_v - mu_s)/2
+//   a   = F^{-1} t  (F = I + D/2 + A^T A, matrix inversion lemma:
+//         p = P^{-1} t, w = K^{-1} A p, a = p - P^{-1} A^T w, and A a = w)
+//   q_tau = (mu_tau + b^T mu_y - e^T a) / (1 + ||b||^2 + e^T phi),
+//           e = c - A^T b, phi = F^{-1}(c + A^T b)
+//   q_x = a + q_tau phi,  q_y = mu_y + w + q_tau A phi - b q_tau,
+//   q_s = (mu_s + mu_v + H q_x)/2,  q_v = (mu_v - mu_s + H q_x)/2.
+// DPi on a PSD block at Y = V diag(lam) V^T maps dY to V (B o (V^T dY V)) V^T
+// (Daleckii-Krein divided differences B).  Free blocks pass through; the tau
+// block passes iff tau > 0.
+#include "cone_common.h"
+
+namespace cdcs {
+
+// per-instance adjoint scalars (double as[B * kNas])
+enum As { AS_QT = 0, AS_GT, AS_DEN2, AS_DIFF2, AS_NORM2, AS_BY, AS_EA, kNas = 8 };
+
+struct AdjPlan {
+  DevPlan d;                 // forward data (state at the solution is read only)
+  double* as;                // B * kNas
+  double* mu_x;
+  double* mu_s;
+  double* mu_y;
+  double* mu_v;
+  double* mu_t;              // B
+  double* qx;                // NE
+  const double* gx;          // NE: dL/dx = w / tau
+  const double* phi;         // NE
+  const double* ev;          // NE: c - A^T b
+  const double* aphi;        // M: A phi
+  const double* eig;         // cached eigenpairs per clique
+  const int64_t* eig_off;    // P
+  double* dc;                // NE output
+  double* db;                // M output
+};
+
+// 1. eigenpairs of the s-block of z* = u* - v~* (Y = smat(s - z)) per clique
+template <int KMAX, int NT>
+__global__ __launch_bounds__(NT) void k_adj_eig(AdjPlan ap, const int32_t* tasks) {
+  __shared__ double A[KMAX * KMAX];
+  __shared__ double V[KMAX * KMAX];
+  __shared__ double rc[KMAX / 2], rs[KMAX / 2], rt[KMAX / 2];
+  __shared__ int rp[KMAX / 2], rq[KMAX / 2];
+  __shared__ double red[NT / 64 + 1];
+  const DevPlan& d = ap.d;
+  const int k = tasks[blockIdx.x];
+  const int K = d.clq_size[k];
+  const int KP = K + (K & 1);
+  const int64_t s0 = d.clq_slot[k];
+  for (int idx = threadIdx.x; idx < KP * KP; idx += NT) {
+    const int i = idx / KP, j = idx - (idx / KP) * KP;
+    double yv = 0.0;
+    if (i < K && j < K) {
+      const int a = i > j ? i : j, bq = i > j ? j : i;
+      const int64_t sl = s0 + packed_index(a, bq, K);
+      yv = d.s[sl] - d.z[sl];
+      if (a != bq) yv *= kInvSqrt2;
+    }
+    A[i * KMAX + j] = yv;
+    V[i * KMAX + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  jacobi_lds<KMAX, NT>(A, V, K, KP, rc, rs, rt, rp, rq, red);
+  double* out = const_cast<double*>(ap.eig) + ap.eig_off[k];
+  for (int idx = threadIdx.x; idx < K * K; idx += NT) {
+    const int i = idx / K, l = idx - (idx / K) * K;
+    out[idx] = V[i * KMAX + l];                 // out[i*K + l] = V_il (eigenvector l)
+  }
+  for (int l = threadIdx.x; l < K; l += NT) out[K * K + l] = A[l * KMAX + l];
+}
+
+// 2. t and p = P^{-1} t
+__global__ __launch_bounds__(kThreads) void k_adj_rhs(AdjPlan ap) {
+  const DevPlan& d = ap.d;
+  const int4 bd = d.eblk[blockIdx.x];
+  for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
+    double aty = 0.0;
+    for (int q = d.at_ptr[e]; q < d.at_ptr[e + 1]; ++q) aty += d.at_val[q] * ap.mu_y[d.at_row[q]];
+    double hs = 0.0;
+    for (int k = d.ent_sptr[e]; k < d.ent_sptr[e + 1]; ++k) {
+      const int sl = d.ent_slots[k];
+      hs += ap.mu_v[sl] - ap.mu_s[sl];
+    }
+    const double t = ap.mu_x[e] - aty - 0.5 * hs;
+    d.q[e] = d.pinv[e] * t;
+  }
+}
+
+// 3. g = A p ; partial b^T mu_y
+__global__ __launch_bounds__(kThreads) void k_adj_ap(AdjPlan ap) {
+  __shared__ double red[kThreads / 64 + 1];
+  const DevPlan& d = ap.d;
+  const int4 bd = d.rblk[blockIdx.x];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int r = bd.y + wid; r < bd.z; r += kThreads / 64) {
+    double acc = 0.0;
+    for (int q = d.a_ptr[r] + lane; q < d.a_ptr[r + 1]; q += 64) acc += d.a_val[q] * d.q[d.a_col[q]];
+    acc = wave_sum(acc);
+    if (lane == 0) d.g[r] = acc;
+  }
+  double by = 0.0;
+  for (int r = bd.y + threadIdx.x; r < bd.z; r += kThreads) by += d.b[r] * ap.mu_y[r];
+  by = block_sum<kThreads>(by, red);
+  if (threadIdx.x == 0) d.part_r[blockIdx.x * 4 + 3] = by;
+}
+
+// 5. a = p - P^{-1} A^T w ; partial e^T a
+__global__ __launch_bounds__(kThreads) void k_adj_a(AdjPlan ap) {
+  __shared__ double red[kThreads / 64 + 1];
+  const DevPlan& d = ap.d;
+  const int4 bd = d.eblk[blockIdx.x];
+  double ea = 0.0;
+  for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
+    double acc = 0.0;
+    for (int q = d.at_ptr[e]; q < d.at_ptr[e + 1]; ++q) acc += d.at_val[q] * d.w[d.at_row[q]];
+    const double a = d.q[e] - d.pinv[e] * acc;
+    d.px[e] = a;
+    ea += ap.ev[e] * a;
+  }
+  ea = block_sum<kThreads>(ea, red);
+  if (threadIdx.x == 0) d.part_e[blockIdx.x * 4 + 0] = ea;
+}
+
+// 6. q_tau
+__global__ __launch_bounds__(64) void k_adj_s1(AdjPlan ap) {
+  const DevPlan& d = ap.d;
+  const int inst = blockIdx.x;
+  double ea = 0.0, by = 0.0;
+  for (int b = d.eblk_off[inst] + threadIdx.x; b < d.eblk_off[inst + 1]; b += 64) ea += d.part_e[b * 4 + 0];
+  for (int b = d.rblk_off[inst] + threadIdx.x; b < d.rblk_off[inst + 1]; b += 64) by += d.part_r[b * 4 + 3];
+  ea = wave_sum(ea);
+  by = wave_sum(by);
+  if (threadIdx.x == 0) {
+    double* as = ap.as + inst * kNas;
+    as[AS_EA] = ea;
+    as[AS_BY] = by;
+    as[AS_QT] = (ap.mu_t[inst] + by - ea) / as[AS_DEN2];
+  }
+}
+
+// 7. q_x and the x block of mu (final = 1: dL/dc instead)
+__global__ __launch_bounds__(kThreads) void k_adj_ue(AdjPlan ap, int final_pass) {
+  __shared__ double red[kThreads / 64 + 1];
+  const DevPlan& d = ap.d;
+  const int4 bd = d.eblk[blockIdx.x];
+  const int inst = bd.x;
+  const double qt = ap.as[inst * kNas + AS_QT];
+  const double tau = d.sc[inst * kNsc + SC_TAU];
+  double df = 0.0, nm = 0.0;
+  for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
+    const double qx = d.px[e] + qt * ap.phi[e];
+    if (final_pass) {
+      ap.dc[e] = -(tau * qx - qt * d.x[e]);
+    } else {
+      ap.qx[e] = qx;
+      const double mn = qx + ap.gx[e];
+      const double dd = mn - ap.mu_x[e];
+      ap.mu_x[e] = mn;
+      df += dd * dd;
+      nm += mn * mn;
+    }
+  }
+  if (final_pass) return;
+  df = block_sum<kThreads>(df, red);
+  nm = block_sum<kThreads>(nm, red);
+  if (threadIdx.x == 0) {
+    d.part_e[blockIdx.x * 4 + 1] = df;
+    d.part_e[blockIdx.x * 4 + 2] = nm;
+  }
+}
+
+// 8. q_y and the y block of mu (final = 1: dL/db instead)
+__global__ __launch_bounds__(kThreads) void k_adj_ur(AdjPlan ap, int final_pass) {
+  __shared__ double red[kThreads / 64 + 1];
+  const DevPlan& d = ap.d;
+  const int4 bd = d.rblk[blockIdx.x];
+  const int inst = bd.x;
+  const double qt = ap.as[inst * kNas + AS_QT];
+  const double tau = d.sc[inst * kNsc + SC_TAU];
+  double df = 0.0, nm = 0.0;
+  for (int r = bd.y + threadIdx.x; r < bd.z; r += kThreads) {
+    const double qy = ap.mu_y[r] + d.w[r] + qt * ap.aphi[r] - d.b[r] * qt;
+    if (final_pass) {
+      ap.db[r] = tau * qy - qt * d.y[r];
+    } else {
+      const double dd = qy - ap.mu_y[r];
+      ap.mu_y[r] = qy;
+      df += dd * dd;
+      nm += qy * qy;
+    }
+  }
+  if (final_pass) return;
+  df = block_sum<kThreads>(df, red);
+  nm = block_sum<kThreads>(nm, red);
+  if (threadIdx.x == 0) {
+    d.part_r[blockIdx.x * 4 + 1] = df;
+    d.part_r[blockIdx.x * 4 + 2] = nm;
+  }
+}
+
+// 9. s and v blocks of mu: q_s, q_v from H q_x, then DPi on the clique block
+template <int KMAX, int NT>
+__global__ __launch_bounds__(NT) void k_adj_cone(AdjPlan ap, const int32_t* tasks) {
+  __shared__ double Vs[KMAX * KMAX];
+  __shared__ double M[KMAX * KMAX];
+  __shared__ double T[KMAX * KMAX];
+  __shared__ double lam[KMAX];
+  __shared__ double red[NT / 64 + 1];
+  const DevPlan& d = ap.d;
+  const int k = tasks[blockIdx.x];
+  const int K = d.clq_size[k];
+  const int64_t s0 = d.clq_slot[k];
+  const double* eg = ap.eig + ap.eig_off[k];
+  const int tid = threadIdx.x;
+  const int nslot = K * (K + 1) / 2;
+  for (int idx = tid; idx < K * K; idx += NT) Vs[idx] = eg[idx];
+  for (int l = tid; l < K; l += NT) lam[l] = eg[K * K + l];
+  // D = smat(2 q_s - mu_s) into M (full symmetric)
+  for (int t = tid; t < nslot; t += NT) {
+    int a, bq;
+    unpack_index(t, K, a, bq);
+    const int64_t sl = s0 + t;
+    const double hq = ap.qx[d.slot2ent[sl]];
+    const double qs = 0.5 * (ap.mu_s[sl] + ap.mu_v[sl] + hq);
+    double dv = 2.0 * qs - ap.mu_s[sl];
+    if (a != bq) dv *= kInvSqrt2;
+    M[a * K + bq] = dv;
+    M[bq * K + a] = dv;
+  }
+  __syncthreads();
+  // T = D V ; M = V^T T
+  for (int idx = tid; idx < K * K; idx += NT) {
+    const int i = idx / K, l = idx - (idx / K) * K;
+    double acc = 0.0;
+    for (int j = 0; j < K; ++j) acc += M[i * K + j] * Vs[j * K + l];
+    T[idx] = acc;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < K * K; idx += NT) {
+    const int p = idx / K, l = idx - (idx / K) * K;
+    double acc = 0.0;
+    for (int i = 0; i < K; ++i) acc += Vs[i * K + p] * T[i * K + l];
+    // divided differences of max(lambda, 0)
+    const double lp = lam[p], ll = lam[l];
+    double bw;
+    if (lp > 0.0 && ll > 0.0) bw = 1.0;
+    else if (lp <= 0.0 && ll <= 0.0) bw = 0.0;
+    else bw = (fmax(lp, 0.0) - fmax(ll, 0.0)) / (lp - ll);
+    M[idx] = bw * acc;
+  }
+  __syncthreads();
+  // T = M V^T ; result = V T
+  for (int idx = tid; idx < K * K; idx += NT) {
+    const int p = idx / K, j = idx - (idx / K) * K;
+    double acc = 0.0;
+    for (int l = 0; l < K; ++l) acc += M[p * K + l] * Vs[j * K + l];
+    T[idx] = acc;
+  }
+  __syncthreads();
+  double df = 0.0, nm = 0.0;
+  for (int t = tid; t < nslot; t += NT) {
+    int a, bq;
+    unpack_index(t, K, a, bq);
+    double r = 0.0;
+    for (int p = 0; p < K; ++p) r += Vs[a * K + p] * T[p * K + bq];
+    if (a != bq) r *= kSqrt2;
+    const int64_t sl = s0 + t;
+    const double hq = ap.qx[d.slot2ent[sl]];
+    const double ms = ap.mu_s[sl], mv = ap.mu_v[sl];
+    const double qs = 0.5 * (ms + mv + hq);
+    const double qv = 0.5 * (mv - ms + hq);
+    const double ns = ms - qs + r;
+    ap.mu_s[sl] = ns;
+    ap.mu_v[sl] = qv;
+    df += (ns - ms) * (ns - ms) + (qv - mv) * (qv - mv);
+    nm += ns * ns + qv * qv;
+  }
+  df = block_sum<NT>(df, red);
+  nm = block_sum<NT>(nm, red);
+  if (tid == 0) {
+    d.part_c[2 * k] = df;
+    d.part_c[2 * k + 1] = nm;
+  }
+}
+
+// 10. tau block of mu and the convergence measures
+__global__ __launch_bounds__(64) void k_adj_s2(AdjPlan ap) {
+  const DevPlan& d = ap.d;
+  const int inst = blockIdx.x;
+  double df = 0.0, nm = 0.0;
+  for (int b = d.eblk_off[inst] + threadIdx.x; b < d.eblk_off[inst + 1]; b += 64) {
+    df += d.part_e[b * 4 + 1];
+    nm += d.part_e[b * 4 + 2];
+  }
+  for (int b = d.rblk_off[inst] + threadIdx.x; b < d.rblk_off[inst + 1]; b += 64) {
+    df += d.part_r[b * 4 + 1];
+    nm += d.part_r[b * 4 + 2];
+  }
+  for (int k = d.clq_off[inst] + threadIdx.x; k < d.clq_off[inst + 1]; k += 64) {
+    df += d.part_c[2 * k];
+    nm += d.part_c[2 * k + 1];
+  }
+  df = wave_sum(df);
+  nm = wave_sum(nm);
+  if (threadIdx.x == 0) {
+    double* as = ap.as + inst * kNas;
+    const double qt = as[AS_QT], gt = as[AS_GT], mt = ap.mu_t[inst];
+    const double tau = d.sc[inst * kNsc + SC_TAU];
+    const double mn = (tau > 0.0) ? qt + gt : mt - qt + gt;
+    ap.mu_t[inst] = mn;
+    as[AS_DIFF2] = df + (mn - mt) * (mn - mt);
+    as[AS_NORM2] = nm + mn * mn;
+  }
+}
+
+void launch_adj_eig(const AdjPlan& ap, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st);
+void launch_adj_iteration(const AdjPlan& ap, const int32_t* const* tasks, const int32_t* ntasks,
+                          int final_pass, hipStream_t st);
+
+void launch_adj_eig(const AdjPlan& ap, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st) {
+  if (ntask <= 0) return;
+  if (kmax <= 16) hipLaunchKernelGGL((k_adj_eig<16, 64>), dim3(ntask), dim3(64), 0, st, ap, tasks);
+  else if (kmax <= 32) hipLaunchKernelGGL((k_adj_eig<32, 128>), dim3(ntask), dim3(128), 0, st, ap, tasks);
+  else hipLaunchKernelGGL((k_adj_eig<64, 256>), dim3(ntask), dim3(256), 0, st, ap, tasks);
+}
+
+// tasks[0..2]: clique lists for K <= 16, <= 32, <= 64
+void launch_adj_iteration(const AdjPlan& ap, const int32_t* const* tasks, const int32_t* ntasks,
+                          int final_pass, hipStream_t st) {
+  const DevPlan& d = ap.d;
+  hipLaunchKernelGGL(k_adj_rhs, dim3(d.n_eblk), dim3(kThreads), 0, st, ap);
+  hipLaunchKernelGGL(k_adj_ap, dim3(d.n_rblk), dim3(kThreads), 0, st, ap);
+  launch_trsv(d, st);
+  hipLaunchKernelGGL(k_adj_a, dim3(d.n_eblk), dim3(kThreads), 0, st, ap);
+  hipLaunchKernelGGL(k_adj_s1, dim3(d.B), dim3(64), 0, st, ap);
+  hipLaunchKernelGGL(k_adj_ue, dim3(d.n_eblk), dim3(kThreads), 0, st, ap, final_pass);
+  hipLaunchKernelGGL(k_adj_ur, dim3(d.n_rblk), dim3(kThreads), 0, st, ap, final_pass);
+  if (final_pass) return;
+  if (ntasks[0]) hipLaunchKernelGGL((k_adj_cone<16, 64>), dim3(ntasks[0]), dim3(64), 0, st, ap, tasks[0]);
+  if (ntasks[1]) hipLaunchKernelGGL((k_adj_cone<32, 128>), dim3(ntasks[1]), dim3(128), 0, st, ap, tasks[1]);
+  if (ntasks[2]) hipLaunchKernelGGL((k_adj_cone<64, 256>), dim3(ntasks[2]), dim3(256), 0, st, ap, tasks[2]);
+  hipLaunchKernelGGL(k_adj_s2, dim3(d.B), dim3(64), 0, st, ap);
+}
+
+}  // namespace cdcs

@@ -1,0 +1,62 @@
+"""GPU implicit gradient (cdcs_adjoint through the C-ABI) against the oracle's
+dense adjoint on tightly solved instances; batched == single."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import grad, hsde  # noqa: E402
+from sdpgen import configs  # noqa: E402
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1611_01828_amd import cdcs
+    cdcs.load()
+    return cdcs
+
+
+def _gpu_grad(lib, insts, ws, eps=1e-11):
+    s = lib.Solver(insts, eps_tol=eps, max_iter=400000, check_every=50)
+    infos = s.solve()
+    assert all(i["status"] == 1 for i in infos), infos
+    dc, db, it = s.adjoint(np.concatenate(ws), max_iter=200000, tol=1e-11)
+    return s, dc, db, it
+
+
+@pytest.mark.parametrize("shape", [dict(n=10, block=3, arrow=2, m=4), dict(n=30, block=6, arrow=3, m=10)])
+def test_adjoint_matches_dense_oracle(lib, shape):
+    _log(f"adjoint vs dense oracle {shape}")
+    inst = configs.small_block_arrow(21, **shape)
+    prob = hsde.build_problem(inst)
+    w = np.random.default_rng(4).standard_normal(prob.nE)
+    _, res = grad.objective_weight_loss(inst, w, eps_tol=1e-11)
+    gc, gb = grad.adjoint_gradient_dense(res, w)
+    s, dc, db, it = _gpu_grad(lib, [inst], [w])
+    rc = np.linalg.norm(dc - gc) / np.linalg.norm(gc)
+    rb = np.linalg.norm(db - gb) / max(np.linalg.norm(gb), 1e-12)
+    _log(f"  adjoint iterations {it}, rel err dc {rc:.2e} db {rb:.2e}")
+    assert rc <= 1e-6 and rb <= 1e-6
+
+
+def test_adjoint_batch_equals_single(lib):
+    _log("adjoint batch == single")
+    insts = [configs.small_block_arrow(30 + i, n=12 + 2 * i, block=3, arrow=2, m=4 + i) for i in range(3)]
+    ws = [np.random.default_rng(i).standard_normal(hsde.build_problem(x).nE) for i, x in enumerate(insts)]
+    _, dcb, dbb, _ = _gpu_grad(lib, insts, ws)
+    oe = or_ = 0
+    for i, x in enumerate(insts):
+        _, dc, db, _ = _gpu_grad(lib, [x], [ws[i]])
+        assert np.linalg.norm(dcb[oe:oe + len(dc)] - dc) <= 1e-9 * np.linalg.norm(dc)
+        assert np.linalg.norm(dbb[or_:or_ + len(db)] - db) <= 1e-9 * max(np.linalg.norm(db), 1e-12)
+        oe += len(dc)
+        or_ += len(db)
