@@ -60,3 +60,33 @@ def test_adjoint_batch_equals_single(lib):
         assert np.linalg.norm(dbb[or_:or_ + len(db)] - db) <= 1e-9 * max(np.linalg.norm(db), 1e-12)
         oe += len(dc)
         or_ += len(db)
+
+
+def test_torch_layer_gradient_matches_finite_differences(lib):
+    """autograd through SDPLayer vs central differences of the GPU solve."""
+    import torch
+    from paper_1611_01828_amd.layer import SDPLayer
+    _log("torch layer vs FD")
+    insts = [configs.small_block_arrow(40 + i, n=14, block=4, arrow=2, m=5) for i in range(2)]
+    layer = SDPLayer(insts, eps_tol=1e-11, adjoint_tol=1e-11)
+    c0 = np.concatenate([layer.svec_of(i, x.C) for i, x in enumerate(insts)])
+    b0 = np.concatenate([x.b for x in insts])
+    rng = np.random.default_rng(9)
+    W = torch.tensor(rng.standard_normal(sum(layer.nE)), dtype=torch.float64, device="cuda")
+    c = torch.tensor(c0, dtype=torch.float64, device="cuda", requires_grad=True)
+    b = torch.tensor(b0, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = (W * layer(c, b)).sum()
+    L.backward()
+    gc = c.grad.cpu().numpy()
+    gb = b.grad.cpu().numpy()
+    h = 1e-5
+    for _ in range(3):
+        dc = rng.standard_normal(len(c0))
+        db = rng.standard_normal(len(b0))
+        with torch.no_grad():
+            Lp = float((W * layer(torch.tensor(c0 + h * dc, device="cuda"), torch.tensor(b0 + h * db, device="cuda"))).sum())
+            Lm = float((W * layer(torch.tensor(c0 - h * dc, device="cuda"), torch.tensor(b0 - h * db, device="cuda"))).sum())
+        fd = (Lp - Lm) / (2 * h)
+        an = float(gc @ dc + gb @ db)
+        _log(f"  fd {fd:.10f} autograd {an:.10f}")
+        assert abs(fd - an) <= 1e-4 * (abs(an) + np.linalg.norm(gc) + np.linalg.norm(gb))
