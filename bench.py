@@ -10,6 +10,12 @@ with HIP events on the solver's stream), time to the 1e-4 residual, and the
 CPU oracle timed on a bounded sample of the same workload.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-solve]
+
+Secondary measurements (their own JSON line, not the headline):
+  --workload batch   256 block-arrow SDPs in one batched solve vs the plain
+                     path run instance by instance
+  --workload grad    64 block-arrow SDPs: forward solve + implicit gradient
+                     vs forward only
 """
 from __future__ import annotations
 
@@ -50,6 +56,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-4 solve")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--workload", choices=["maxcut", "batch", "grad"], default="maxcut")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -61,6 +68,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     from paper_1611_01828_amd import cdcs
     from sdpgen import configs
+
+    if args.workload == "batch":
+        return bench_batch(args, cdcs, configs)
+    if args.workload == "grad":
+        return bench_grad(args, cdcs, configs)
 
     t0 = time.perf_counter()
     inst = configs.config1()
@@ -166,6 +178,94 @@ def main():
         "time_to_1e-4": tol,
         "phases_ms_per_launch": {k: round(v, 4) for k, v in per_launch.items() if phases[k][1]},
     }
+    print(json.dumps(out))
+
+
+def bench_batch(args, cdcs, configs):
+    """Config 3: one batched handle for all instances vs one handle per instance."""
+    import numpy as np
+    import torch
+    t0 = time.perf_counter()
+    insts = configs.config3()
+    print(f"[bench] 256 block-arrow instances generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    s = cdcs.Solver(insts, timing=1)
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] batched setup {setup_s:.1f}s", file=sys.stderr, flush=True)
+    s.iterate(args.warmup)
+    s.reset_phase_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(args.steps)
+    dt = time.perf_counter() - t0
+    phases = s.phase_times()
+    batched = len(insts) * args.steps / dt
+    print(f"[bench] batched: {batched:.0f} instance-iterations/s", file=sys.stderr, flush=True)
+    # plain path: a sample of instances, one handle each, same number of steps
+    sample = insts[::16]
+    plain_t = 0.0
+    for inst in sample:
+        p = cdcs.Solver(inst)
+        p.iterate(args.warmup)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p.iterate(args.steps)
+        plain_t += time.perf_counter() - t1
+        p.close()
+    plain = len(sample) * args.steps / plain_t
+    print(f"[bench] plain per instance: {plain:.0f} instance-iterations/s", file=sys.stderr, flush=True)
+    fresh = cdcs.Solver(insts, check_every=10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = fresh.solve()
+    tsolve = time.perf_counter() - t0
+    st = {}
+    for f in infos:
+        st[cdcs.STATUS_NAMES[f["status"]]] = st.get(cdcs.STATUS_NAMES[f["status"]], 0) + 1
+    per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()}
+    out = {"metric": "batched instance-iterations/s (256 block-arrow SDPs)", "value": round(batched, 1),
+           "unit": "instance-iter/s", "plain_value": round(plain, 1), "speedup_vs_plain": round(batched / plain, 2),
+           "steps": args.steps, "ms_per_step": round(1e3 * dt / args.steps, 4), "dtype": "f64",
+           "time_to_1e-4": {"seconds": round(tsolve, 3), "max_iterations": max(f["iter"] for f in infos),
+                            "status_counts": st},
+           "setup_s": round(setup_s, 2),
+           "phases_ms_per_launch": {k: round(v, 4) for k, v in per_launch.items() if phases[k][1]}}
+    print(json.dumps(out))
+
+
+def bench_grad(args, cdcs, configs):
+    """Config 4: forward (solve) + backward (implicit adjoint) vs forward only."""
+    import numpy as np
+    import torch
+    insts = configs.config4()
+    W = np.concatenate([i.meta["W"][2] for i in insts])
+    # W is drawn on the lower pattern entries; map to svec over each instance's E'
+    s = cdcs.Solver(insts, check_every=10)
+    dX = []
+    for i, inst in enumerate(insts):
+        rows, cols = s.entries(i)
+        wr, wc, wv = inst.meta["W"]
+        key = {(int(r), int(c)): e for e, (r, c) in enumerate(zip(rows, cols))}
+        v = np.zeros(len(rows))
+        for r, c, x in zip(wr, wc, wv):
+            v[key[(int(r), int(c))]] = x * (1.0 if r == c else np.sqrt(2.0))
+        dX.append(v)
+    dX = np.concatenate(dX)
+    s.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f = cdcs.Solver(insts, check_every=10)
+    infos = f.solve()
+    tf = time.perf_counter() - t0
+    nsolved = sum(1 for x in infos if x["status"] == cdcs.SOLVED)
+    t0 = time.perf_counter()
+    dc, db, it = f.adjoint(dX, max_iter=20000, tol=1e-8)
+    tb = time.perf_counter() - t0
+    out = {"metric": "differentiated batch (64 SDPs): forward+backward per second vs forward only",
+           "value": round(1.0 / (tf + tb), 4), "unit": "batches/s", "forward_only": round(1.0 / tf, 4),
+           "forward_s": round(tf, 3), "backward_s": round(tb, 3), "adjoint_iterations": it,
+           "forward_iterations_max": max(x["iter"] for x in infos), "solved": nsolved, "dtype": "f64",
+           "grad_norm_c": float(np.linalg.norm(dc)), "grad_norm_b": float(np.linalg.norm(db))}
     print(json.dumps(out))
 
 
