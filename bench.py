@@ -259,7 +259,7 @@ def bench_grad(args, cdcs, configs):
     tf = time.perf_counter() - t0
     nsolved = sum(1 for x in infos if x["status"] == cdcs.SOLVED)
     t0 = time.perf_counter()
-    dc, db, it = f.adjoint(dX, max_iter=20000, tol=1e-8)
+    dc, db, it = f.adjoint(dX, max_iter=20000, tol=1e-10)
     tb = time.perf_counter() - t0
     out = {"metric": "differentiated batch (64 SDPs): forward+backward per second vs forward only",
            "value": round(1.0 / (tf + tb), 4), "unit": "batches/s", "forward_only": round(1.0 / tf, 4),

@@ -174,11 +174,16 @@ int cdcs_set_state(cdcs_handle* h, int32_t inst, const double* u, const double* 
  * dX (NE values: per instance, svec over E' in canonical order, concatenated
  * over instances) is dL/dX for X = x / tau.  Outputs: dC (NE values, dL/dc
  * for c = svec(C), i.e. the gradient with respect to C as an svec) and db
- * (sum of m values, dL/db).  The adjoint fixed-point iteration stops when
- * ||mu+ - mu|| <= tol ||mu|| for every instance or after max_iter steps;
- * *iters (may be NULL) receives the count.  on_device = 1: dX, dC, db are
- * device pointers.  Every instance must be SOLVED (CDCS_E_STATE) and have
- * cliques of at most 64 vertices (CDCS_E_ARG). */
+ * (sum of m values, dL/db).  The adjoint system (I - T'^T) mu = g is solved
+ * by restarted GMRES(20), one Krylov basis per instance.  An instance stops
+ * when ||g - (I - T'^T) mu|| <= tol ||g||, or when that residual has fallen
+ * by less than 10% over 5 restarts (the system is singular and consistent
+ * only to the accuracy of the forward solve, so the gradient's accuracy
+ * follows eps_tol of the solve, not tol); all stop after max_iter operator
+ * applications.  *iters (may be NULL) receives the number of applications.
+ * on_device = 1: dX, dC, db are device pointers.  Every instance must be
+ * SOLVED (CDCS_E_STATE) and have cliques of at most 64 vertices
+ * (CDCS_E_ARG). */
 int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32_t on_device,
                  int32_t max_iter, double tol, int32_t* iters);
 

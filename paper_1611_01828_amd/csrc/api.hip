@@ -39,7 +39,14 @@ struct AdjPlan {
 };
 void launch_adj_eig(const AdjPlan& ap, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st);
 void launch_adj_iteration(const AdjPlan& ap, const int32_t* const* tasks, const int32_t* ntasks,
-                          int final_pass, hipStream_t st);
+                          int final_pass, int use_g, hipStream_t st);
+void launch_seg_dots(const double* w, const double* Vb, int64_t NF, int nk, const int64_t* seg, double* out,
+                     int B, hipStream_t st);
+void launch_flat_axpy_multi(double* w, const double* Vb, int64_t NF, int nk, const double* coef,
+                            const int32_t* inst_of, int B, double sign, hipStream_t st);
+void launch_flat_scale(double* out, const double* w, const double* sc, const int32_t* inst_of, int64_t NF,
+                       hipStream_t st);
+void launch_flat_sub(double* out, const double* a, const double* b, int64_t NF, hipStream_t st);
 }  // namespace cdcs
 
 namespace {
@@ -95,6 +102,17 @@ struct cdcs_handle {
   // adjoint buffers (allocated on the first cdcs_adjoint call)
   bool adj_ready = false;
   AdjPlan adj{};
+  // batched GMRES workspace over flat vectors [x | s | y | v | tau]
+  int64_t nf = 0;
+  double* gm_V = nullptr;      // (kRestart + 1) * nf basis
+  double* gm_w = nullptr;      // nf
+  double* gm_mu = nullptr;     // nf
+  double* gm_g = nullptr;      // nf
+  double* gm_coef = nullptr;   // (kRestart + 1) * B
+  double* gm_dots = nullptr;   // (kRestart + 1) * B
+  double* gm_scale = nullptr;  // B
+  int64_t* gm_seg = nullptr;   // 10 * B
+  int32_t* gm_inst = nullptr;  // nf
   double setup_s = 0.0;
 };
 
@@ -776,6 +794,20 @@ int cdcs_get_certificate(const cdcs_handle* h, int32_t inst, double* y_cert, dou
 
 namespace {
 
+constexpr int kRestart = 20;
+
+// point the adjoint plan's mu blocks at a flat vector
+void adj_point(cdcs_handle* h, double* flat) {
+  const int32_t B = h->B;
+  const int64_t NE = h->ent_off[B], NS = h->slot_off[B];
+  const int32_t M = h->row_off[B];
+  h->adj.mu_x = flat;
+  h->adj.mu_s = flat + NE;
+  h->adj.mu_y = flat + NE + NS;
+  h->adj.mu_v = flat + NE + NS + M;
+  h->adj.mu_t = flat + NE + 2 * NS + M;
+}
+
 // data of the transposed solve (I - Q) q = mu that depends only on the problem:
 // phi = F^{-1}(c + A^T b), A phi, e = c - A^T b, 1 + ||b||^2 + e^T phi
 int adjoint_prepare(cdcs_handle* h) {
@@ -835,6 +867,29 @@ int adjoint_prepare(cdcs_handle* h) {
       tot += K * K + K;
     }
   if ((rc = dev_zeros(h, (double**)&a.eig, tot)) || (rc = dev_upload(h, (int64_t**)&a.eig_off, eoff))) return rc;
+  const int64_t NS = h->slot_off[B];
+  const int64_t nf = NE + 2 * NS + M + B;
+  h->nf = nf;
+  std::vector<int64_t> seg((size_t)10 * B);
+  std::vector<int32_t> inst_of(nf);
+  for (int32_t i = 0; i < B; ++i) {
+    const int64_t lo[5] = {h->ent_off[i], NE + h->slot_off[i], NE + NS + h->row_off[i],
+                           NE + NS + M + h->slot_off[i], NE + 2 * NS + M + i};
+    const int64_t hi[5] = {h->ent_off[i + 1], NE + h->slot_off[i + 1], NE + NS + h->row_off[i + 1],
+                           NE + NS + M + h->slot_off[i + 1], NE + 2 * NS + M + i + 1};
+    for (int q = 0; q < 5; ++q) {
+      seg[10 * i + 2 * q] = lo[q];
+      seg[10 * i + 2 * q + 1] = hi[q];
+      for (int64_t e = lo[q]; e < hi[q]; ++e) inst_of[e] = i;
+    }
+  }
+  if ((rc = dev_zeros(h, &h->gm_V, (size_t)(kRestart + 1) * nf)) || (rc = dev_zeros(h, &h->gm_w, nf)) ||
+      (rc = dev_zeros(h, &h->gm_mu, nf)) || (rc = dev_zeros(h, &h->gm_g, nf)) ||
+      (rc = dev_zeros(h, &h->gm_coef, (size_t)(kRestart + 1) * B)) ||
+      (rc = dev_zeros(h, &h->gm_dots, (size_t)(kRestart + 1) * B)) || (rc = dev_zeros(h, &h->gm_scale, B)) ||
+      (rc = dev_upload(h, &h->gm_seg, seg)) || (rc = dev_upload(h, &h->gm_inst, inst_of)))
+    return rc;
+  HIPCHK(hipDeviceSynchronize());
   h->adj_ready = true;
   return 0;
 }
@@ -878,35 +933,150 @@ int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32
     mut[i] = as[(size_t)i * kNas + AS_GT];
   }
   HIPCHK(hipMemcpy(const_cast<double*>(a.gx), gx.data(), NE * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(a.mu_x, gx.data(), NE * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(a.mu_t, mut.data(), B * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(a.as, as.data(), as.size() * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(hipMemset(a.mu_s, 0, h->slot_off[B] * sizeof(double)));
-  HIPCHK(hipMemset(a.mu_v, 0, h->slot_off[B] * sizeof(double)));
-  HIPCHK(hipMemset(a.mu_y, 0, M * sizeof(double)));
   // eigenpairs of the clique blocks at the solution
   const int kmaxs[3] = {16, 32, 64};
   for (int bk = 0; bk < 3; ++bk) launch_adj_eig(a, h->tasks[bk], h->ntasks[bk], kmaxs[bk], h->stream);
   const int32_t* tl[3] = {h->tasks[0], h->tasks[1], h->tasks[2]};
   const int32_t nt[3] = {h->ntasks[0], h->ntasks[1], h->ntasks[2]};
+  hipStream_t st = h->stream;
+  const int64_t nf = h->nf;
+  const int64_t NS = h->slot_off[B];
+  // right-hand side g = DPi dL/du (x block: w/tau, tau block: -w^T x/tau^2), mu = 0
+  {
+    std::vector<double> gflat(nf, 0.0);
+    for (int64_t e = 0; e < NE; ++e) gflat[e] = gx[e];
+    for (int32_t i = 0; i < B; ++i) gflat[NE + 2 * NS + M + i] = mut[i];
+    HIPCHK(hipMemcpy(h->gm_g, gflat.data(), nf * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemsetAsync(h->gm_mu, 0, nf * sizeof(double), st));
+  }
+  // w = (I - T'^T) v : one operator application with g switched off leaves
+  // v - (I - T'^T) v in w
+  auto apply_op = [&](const double* v, double* w) -> int {
+    HIPCHK(hipMemcpyAsync(w, v, nf * sizeof(double), hipMemcpyDeviceToDevice, st));
+    adj_point(h, w);
+    launch_adj_iteration(a, tl, nt, 0, 0, st);
+    launch_flat_sub(w, v, w, nf, st);
+    return 0;
+  };
+  auto seg_dots = [&](const double* w, const double* Vb, int nk, std::vector<double>& out) -> int {
+    launch_seg_dots(w, Vb, nf, nk, h->gm_seg, h->gm_dots, B, st);
+    out.resize((size_t)nk * B);
+    HIPCHK(hipMemcpyAsync(out.data(), h->gm_dots, out.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+  };
+  std::vector<double> gnorm;
+  if ((rc = seg_dots(h->gm_g, h->gm_g, 1, gnorm))) return rc;
+  for (auto& v : gnorm) v = std::sqrt(v);
+  // Restarted GMRES on (I - T'^T) mu = g, one Krylov basis per instance.
+  // The system is singular (the fixed points of the iteration form a cone,
+  // not a single ray, when the clique decomposition of Z is not unique) and
+  // consistent only up to the forward solve's accuracy, so an instance also
+  // stops once its true residual has stalled: less than kStall reduction over
+  // the last kWindow restarts.  A stopped instance keeps its mu (zero update
+  // coefficients), so batched and single runs follow the same arithmetic.
+  constexpr int kWindow = 5;
+  constexpr double kStall = 0.9;
   int32_t it = 0;
-  for (; it < max_iter;) {
-    const int32_t chunk = std::min<int32_t>(10, max_iter - it);
-    for (int32_t c = 0; c < chunk; ++c) launch_adj_iteration(a, tl, nt, 0, h->stream);
-    it += chunk;
+  std::vector<double> Hm((size_t)B * (kRestart + 1) * kRestart), cs((size_t)B * kRestart), sn((size_t)B * kRestart),
+      gam((size_t)B * (kRestart + 1)), dots, dots2, nrm, coef, scl(B);
+  std::vector<char> done(B, 0);
+  std::vector<int> jlim(B);
+  std::vector<std::vector<double>> hist(B);
+  while (it < max_iter) {
+    // r = g - A mu into V_0 (mu = 0 on the first cycle)
+    double* V0 = h->gm_V;
+    if ((rc = apply_op(h->gm_mu, h->gm_w))) return rc;
+    launch_flat_sub(V0, h->gm_g, h->gm_w, nf, st);
+    if ((rc = seg_dots(V0, V0, 1, nrm))) return rc;
+    bool all_done = true;
+    for (int32_t i = 0; i < B; ++i) {
+      const double beta = std::sqrt(nrm[i]);
+      if (!done[i]) {
+        auto& hh = hist[i];
+        if (beta <= tol * std::max(gnorm[i], 1e-300) ||
+            ((int)hh.size() >= kWindow && beta > kStall * hh[hh.size() - kWindow]))
+          done[i] = 1;
+        hh.push_back(beta);
+      }
+      all_done = all_done && done[i];
+      gam[(size_t)i * (kRestart + 1)] = beta;
+      scl[i] = beta > 0.0 ? 1.0 / beta : 0.0;
+      jlim[i] = done[i] ? 0 : -1;   // -1: uses every column of this cycle
+    }
+    if (all_done) break;
+    HIPCHK(hipMemcpyAsync(h->gm_scale, scl.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_flat_scale(V0, V0, h->gm_scale, h->gm_inst, nf, st);
+    int jdone = 0;
+    for (int j = 0; j < kRestart && it < max_iter; ++j) {
+      ++it;
+      double* Vj = h->gm_V + (size_t)j * nf;
+      double* Vn = h->gm_V + (size_t)(j + 1) * nf;
+      if ((rc = apply_op(Vj, h->gm_w))) return rc;
+      // classical Gram-Schmidt, twice
+      if ((rc = seg_dots(h->gm_w, h->gm_V, j + 1, dots))) return rc;
+      HIPCHK(hipMemcpyAsync(h->gm_coef, dots.data(), dots.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      launch_flat_axpy_multi(h->gm_w, h->gm_V, nf, j + 1, h->gm_coef, h->gm_inst, B, -1.0, st);
+      if ((rc = seg_dots(h->gm_w, h->gm_V, j + 1, dots2))) return rc;
+      HIPCHK(hipMemcpyAsync(h->gm_coef, dots2.data(), dots2.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      launch_flat_axpy_multi(h->gm_w, h->gm_V, nf, j + 1, h->gm_coef, h->gm_inst, B, -1.0, st);
+      if ((rc = seg_dots(h->gm_w, h->gm_w, 1, nrm))) return rc;
+      bool cycle_done = true;
+      for (int32_t i = 0; i < B; ++i) {
+        double* Hc = &Hm[((size_t)i * (kRestart + 1)) * kRestart];   // column-major (kRestart+1) x kRestart
+        for (int k = 0; k <= j; ++k) Hc[(size_t)j * (kRestart + 1) + k] = dots[(size_t)k * B + i] + dots2[(size_t)k * B + i];
+        const double hn = std::sqrt(nrm[i]);
+        Hc[(size_t)j * (kRestart + 1) + j + 1] = hn;
+        scl[i] = hn > 1e-300 ? 1.0 / hn : 0.0;
+        // apply the previous Givens rotations, then a new one
+        double* c_ = &cs[(size_t)i * kRestart];
+        double* s_ = &sn[(size_t)i * kRestart];
+        for (int k = 0; k < j; ++k) {
+          const double h0 = Hc[(size_t)j * (kRestart + 1) + k], h1 = Hc[(size_t)j * (kRestart + 1) + k + 1];
+          Hc[(size_t)j * (kRestart + 1) + k] = c_[k] * h0 + s_[k] * h1;
+          Hc[(size_t)j * (kRestart + 1) + k + 1] = -s_[k] * h0 + c_[k] * h1;
+        }
+        const double h0 = Hc[(size_t)j * (kRestart + 1) + j], h1 = Hc[(size_t)j * (kRestart + 1) + j + 1];
+        const double r = std::hypot(h0, h1);
+        c_[j] = r > 0.0 ? h0 / r : 1.0;
+        s_[j] = r > 0.0 ? h1 / r : 0.0;
+        Hc[(size_t)j * (kRestart + 1) + j] = r;
+        Hc[(size_t)j * (kRestart + 1) + j + 1] = 0.0;
+        double* gi = &gam[(size_t)i * (kRestart + 1)];
+        gi[j + 1] = -s_[j] * gi[j];
+        gi[j] = c_[j] * gi[j];
+        if (jlim[i] < 0 && std::fabs(gi[j + 1]) <= tol * std::max(gnorm[i], 1e-300)) jlim[i] = j + 1;
+        cycle_done = cycle_done && jlim[i] >= 0;
+      }
+      HIPCHK(hipMemcpyAsync(h->gm_scale, scl.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+      launch_flat_scale(Vn, h->gm_w, h->gm_scale, h->gm_inst, nf, st);
+      jdone = j + 1;
+      if (cycle_done) break;
+    }
+    // mu += V y with H y = gamma over the instance's columns (back substitution)
+    coef.assign((size_t)(kRestart + 1) * B, 0.0);
+    for (int32_t i = 0; i < B; ++i) {
+      const int ji = jlim[i] < 0 ? jdone : jlim[i];
+      const double* Hc = &Hm[((size_t)i * (kRestart + 1)) * kRestart];
+      const double* gi = &gam[(size_t)i * (kRestart + 1)];
+      std::vector<double> y(ji, 0.0);
+      for (int k = ji - 1; k >= 0; --k) {
+        double t = gi[k];
+        for (int l = k + 1; l < ji; ++l) t -= Hc[(size_t)l * (kRestart + 1) + k] * y[l];
+        const double dkk = Hc[(size_t)k * (kRestart + 1) + k];
+        y[k] = dkk != 0.0 ? t / dkk : 0.0;
+      }
+      for (int k = 0; k < ji; ++k) coef[(size_t)k * B + i] = y[k];
+    }
+    HIPCHK(hipMemcpyAsync(h->gm_coef, coef.data(), (size_t)jdone * B * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_flat_axpy_multi(h->gm_mu, h->gm_V, nf, jdone, h->gm_coef, h->gm_inst, B, 1.0, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("adjoint launch: ") + hipGetErrorString(e));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    HIPCHK(hipMemcpy(as.data(), a.as, as.size() * sizeof(double), hipMemcpyDeviceToHost));
-    bool done = true;
-    for (int32_t i = 0; i < B; ++i) {
-      const double d2 = as[(size_t)i * kNas + AS_DIFF2], n2 = as[(size_t)i * kNas + AS_NORM2];
-      if (!(d2 <= tol * tol * std::max(n2, 1e-300))) done = false;
-    }
-    if (done) break;
   }
   // nu = (I - Q)^{-1} mu and the data gradients
-  launch_adj_iteration(a, tl, nt, 1, h->stream);
+  adj_point(h, h->gm_mu);
+  launch_adj_iteration(a, tl, nt, 1, 0, h->stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("adjoint launch: ") + hipGetErrorString(e));
   HIPCHK(hipStreamSynchronize(h->stream));

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(64) void k_adj_s1(AdjPlan ap) {
 }
 
 // 7. q_x and the x block of mu (final = 1: dL/dc instead)
-__global__ __launch_bounds__(kThreads) void k_adj_ue(AdjPlan ap, int final_pass) {
+__global__ __launch_bounds__(kThreads) void k_adj_ue(AdjPlan ap, int final_pass, int use_g) {
   __shared__ double red[kThreads / 64 + 1];
   const DevPlan& d = ap.d;
   const int4 bd = d.eblk[blockIdx.x];
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_ue(AdjPlan ap, int final_pass)
       ap.dc[e] = -(tau * qx - qt * d.x[e]);
     } else {
       ap.qx[e] = qx;
-      const double mn = qx + ap.gx[e];
+      const double mn = qx + (use_g ? ap.gx[e] : 0.0);
       const double dd = mn - ap.mu_x[e];
       ap.mu_x[e] = mn;
       df += dd * dd;
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(NT) void k_adj_cone(AdjPlan ap, const int32_t* task
 }
 
 // 10. tau block of mu and the convergence measures
-__global__ __launch_bounds__(64) void k_adj_s2(AdjPlan ap) {
+__global__ __launch_bounds__(64) void k_adj_s2(AdjPlan ap, int use_g) {
   const DevPlan& d = ap.d;
   const int inst = blockIdx.x;
   double df = 0.0, nm = 0.0;
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(64) void k_adj_s2(AdjPlan ap) {
   nm = wave_sum(nm);
   if (threadIdx.x == 0) {
     double* as = ap.as + inst * kNas;
-    const double qt = as[AS_QT], gt = as[AS_GT], mt = ap.mu_t[inst];
+    const double qt = as[AS_QT], gt = use_g ? as[AS_GT] : 0.0, mt = ap.mu_t[inst];
     const double tau = d.sc[inst * kNsc + SC_TAU];
     const double mn = (tau > 0.0) ? qt + gt : mt - qt + gt;
     ap.mu_t[inst] = mn;
@@ -323,9 +323,70 @@ __global__ __launch_bounds__(64) void k_adj_s2(AdjPlan ap) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched restarted GMRES on (I - T'^T) mu = g.  Vectors are flat:
+// [x (NE) | s (NS) | y (M) | v (NS) | tau (B)]; seg[10 i .. 10 i + 9] holds
+// the five [lo, hi) ranges of instance i, inst_of maps an element to its
+// instance.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_seg_dots(const double* w, const double* Vb, int64_t NF,
+                                                  const int64_t* seg, double* out, int B) {
+  __shared__ double red[256 / 64 + 1];
+  const int i = blockIdx.x, k = blockIdx.y;
+  const double* v = Vb + (size_t)k * NF;
+  double acc = 0.0;
+  for (int q = 0; q < 5; ++q) {
+    const int64_t lo = seg[10 * i + 2 * q], hi = seg[10 * i + 2 * q + 1];
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) acc += w[e] * v[e];
+  }
+  acc = block_sum<256>(acc, red);
+  if (threadIdx.x == 0) out[k * B + i] = acc;
+}
+
+// w += sign * sum_k coef[k, inst(e)] V_k
+__global__ __launch_bounds__(256) void k_flat_axpy_multi(double* w, const double* Vb, int64_t NF, int nk,
+                                                         const double* coef, const int32_t* inst_of, int B,
+                                                         double sign) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= NF) return;
+  const int i = inst_of[e];
+  double acc = 0.0;
+  for (int k = 0; k < nk; ++k) acc += coef[k * B + i] * Vb[(size_t)k * NF + e];
+  w[e] += sign * acc;
+}
+
+__global__ __launch_bounds__(256) void k_flat_scale(double* out, const double* w, const double* sc,
+                                                    const int32_t* inst_of, int64_t NF) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < NF) out[e] = w[e] * sc[inst_of[e]];
+}
+
+// out = a - b
+__global__ __launch_bounds__(256) void k_flat_sub(double* out, const double* a, const double* b, int64_t NF) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < NF) out[e] = a[e] - b[e];
+}
+
+void launch_seg_dots(const double* w, const double* Vb, int64_t NF, int nk, const int64_t* seg, double* out,
+                     int B, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_dots, dim3(B, nk), dim3(256), 0, st, w, Vb, NF, seg, out, B);
+}
+void launch_flat_axpy_multi(double* w, const double* Vb, int64_t NF, int nk, const double* coef,
+                            const int32_t* inst_of, int B, double sign, hipStream_t st) {
+  hipLaunchKernelGGL(k_flat_axpy_multi, dim3((NF + 255) / 256), dim3(256), 0, st, w, Vb, NF, nk, coef, inst_of, B,
+                     sign);
+}
+void launch_flat_scale(double* out, const double* w, const double* sc, const int32_t* inst_of, int64_t NF,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_flat_scale, dim3((NF + 255) / 256), dim3(256), 0, st, out, w, sc, inst_of, NF);
+}
+void launch_flat_sub(double* out, const double* a, const double* b, int64_t NF, hipStream_t st) {
+  hipLaunchKernelGGL(k_flat_sub, dim3((NF + 255) / 256), dim3(256), 0, st, out, a, b, NF);
+}
+
 void launch_adj_eig(const AdjPlan& ap, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st);
 void launch_adj_iteration(const AdjPlan& ap, const int32_t* const* tasks, const int32_t* ntasks,
-                          int final_pass, hipStream_t st);
+                          int final_pass, int use_g, hipStream_t st);
 
 void launch_adj_eig(const AdjPlan& ap, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st) {
   if (ntask <= 0) return;
@@ -336,20 +397,20 @@ void launch_adj_eig(const AdjPlan& ap, const int32_t* tasks, int32_t ntask, int 
 
 // tasks[0..2]: clique lists for K <= 16, <= 32, <= 64
 void launch_adj_iteration(const AdjPlan& ap, const int32_t* const* tasks, const int32_t* ntasks,
-                          int final_pass, hipStream_t st) {
+                          int final_pass, int use_g, hipStream_t st) {
   const DevPlan& d = ap.d;
   hipLaunchKernelGGL(k_adj_rhs, dim3(d.n_eblk), dim3(kThreads), 0, st, ap);
   hipLaunchKernelGGL(k_adj_ap, dim3(d.n_rblk), dim3(kThreads), 0, st, ap);
   launch_trsv(d, st);
   hipLaunchKernelGGL(k_adj_a, dim3(d.n_eblk), dim3(kThreads), 0, st, ap);
   hipLaunchKernelGGL(k_adj_s1, dim3(d.B), dim3(64), 0, st, ap);
-  hipLaunchKernelGGL(k_adj_ue, dim3(d.n_eblk), dim3(kThreads), 0, st, ap, final_pass);
+  hipLaunchKernelGGL(k_adj_ue, dim3(d.n_eblk), dim3(kThreads), 0, st, ap, final_pass, use_g);
   hipLaunchKernelGGL(k_adj_ur, dim3(d.n_rblk), dim3(kThreads), 0, st, ap, final_pass);
   if (final_pass) return;
   if (ntasks[0]) hipLaunchKernelGGL((k_adj_cone<16, 64>), dim3(ntasks[0]), dim3(64), 0, st, ap, tasks[0]);
   if (ntasks[1]) hipLaunchKernelGGL((k_adj_cone<32, 128>), dim3(ntasks[1]), dim3(128), 0, st, ap, tasks[1]);
   if (ntasks[2]) hipLaunchKernelGGL((k_adj_cone<64, 256>), dim3(ntasks[2]), dim3(256), 0, st, ap, tasks[2]);
-  hipLaunchKernelGGL(k_adj_s2, dim3(d.B), dim3(64), 0, st, ap);
+  hipLaunchKernelGGL(k_adj_s2, dim3(d.B), dim3(64), 0, st, ap, use_g);
 }
 
 }  // namespace cdcs
