@@ -80,6 +80,10 @@ const char* kPhaseNames[kNumPhases] = {
 struct cdcs_handle {
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // second stream (default priority) for the large-clique eigensolver, which
+  // runs beside the small-clique Jacobi kernels: both write disjoint cliques
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   cdcs_settings set{};
   int32_t B = 0;
   std::vector<Instance> inst;
@@ -160,7 +164,9 @@ struct PhaseTimer {
   int ph;
   size_t slot = 0;
   bool on;
-  PhaseTimer(cdcs_handle* hh, int p) : h(hh), ph(p), on(hh->set.timing != 0) {
+  hipStream_t sm;
+  PhaseTimer(cdcs_handle* hh, int p, hipStream_t s = nullptr)
+      : h(hh), ph(p), on(hh->set.timing != 0), sm(s ? s : hh->stream) {
     if (!on) return;
     if (h->ev_used.size() >= h->ev_pool.size()) {
       hipEvent_t a, b;
@@ -169,11 +175,11 @@ struct PhaseTimer {
       h->ev_pool.push_back({a, b});
     }
     slot = h->ev_used.size();
-    (void)hipEventRecord(h->ev_pool[slot].first, h->stream);
+    (void)hipEventRecord(h->ev_pool[slot].first, sm);
   }
   ~PhaseTimer() {
     if (!on) return;
-    (void)hipEventRecord(h->ev_pool[slot].second, h->stream);
+    (void)hipEventRecord(h->ev_pool[slot].second, sm);
     h->ev_used.push_back({ph, slot});
   }
 };
@@ -200,16 +206,28 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
   { PhaseTimer t(h, PH_UPDATE_E); launch_update_e(d, st); }
   { PhaseTimer t(h, PH_UPDATE_R); launch_update_r(d, st); }
   const int kmaxs[4] = {16, 32, 64, kJacobiMax};
+  const bool small = h->ntasks[0] || h->ntasks[1] || h->ntasks[2] || h->ntasks[3];
+  const bool fork = h->ntasks[4] && small;
+  hipStream_t lst = st;
+  if (fork) {
+    lst = h->aux;
+    HIPCHK(hipEventRecord(h->ev_fork, st));
+    HIPCHK(hipStreamWaitEvent(lst, h->ev_fork, 0));
+  }
+  if (h->ntasks[4])
+    for (int step = 0; step < kLargeSteps; ++step) {
+      PhaseTimer t(h, PH_LG_GATHER + step, lst);
+      launch_cone_large_step(d, h->tasks[4], h->ntasks[4], h->kmax_large, step, lst);
+    }
   for (int bk = 0; bk < 4; ++bk)
     if (h->ntasks[bk]) {
       PhaseTimer t(h, PH_CONE16 + bk);
       launch_cone_jacobi(d, h->tasks[bk], h->ntasks[bk], kmaxs[bk], st);
     }
-  if (h->ntasks[4])
-    for (int step = 0; step < kLargeSteps; ++step) {
-      PhaseTimer t(h, PH_LG_GATHER + step);
-      launch_cone_large_step(d, h->tasks[4], h->ntasks[4], h->kmax_large, step, st);
-    }
+  if (fork) {
+    HIPCHK(hipEventRecord(h->ev_join, lst));
+    HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
+  }
   { PhaseTimer t(h, PH_SCALAR2); launch_scalar2(d, h->set.eps_tol, h->set.max_iter, stop, st); }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
@@ -511,6 +529,7 @@ const char* cdcs_last_error(void) { return g_last_error.c_str(); }
 
 void cdcs_destroy(cdcs_handle* h) {
   if (!h) return;
+  if (h->aux) (void)hipStreamSynchronize(h->aux);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
   for (int i = 0; i < 2; ++i)
@@ -520,6 +539,9 @@ void cdcs_destroy(cdcs_handle* h) {
     (void)hipEventDestroy(e.second);
   }
   for (void* p : h->allocs) (void)hipFree(p);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
   if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
@@ -544,6 +566,12 @@ int cdcs_setup_batch(int32_t count, const cdcs_problem* prob, const cdcs_setting
       return set_error(CDCS_E_DEVICE, "hipStreamCreateWithFlags failed");
     }
     h->own_stream = true;
+  }
+  if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+    cdcs_destroy(h);
+    return set_error(CDCS_E_DEVICE, "stream/event creation failed");
   }
   h->set = set;
   h->B = count;
