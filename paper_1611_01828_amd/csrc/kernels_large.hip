@@ -356,6 +356,70 @@ __device__ __forceinline__ int sturm_count(const double* d, const double* e2, in
   return cnt;
 }
 
+// LU of T - lambda I with partial pivoting (T tridiagonal: diagonal d,
+// off-diagonal e).  Row i of U holds (U0, U1, U2) on columns i, i+1, i+2;
+// stored: L multiplier, pivot flag, 1 / U0, U1, U2, arrays a = 0..4 at
+// f[a * KR + i * st].  Pivots below tiny are raised to +-tiny.
+__device__ __forceinline__ void tri_factor(const double* d, const double* e, int K, double lam, double tiny,
+                                           double* f, int st, size_t KR) {
+  double al = d[0] - lam, be = (K > 1) ? e[0] : 0.0;
+  for (int i = 0; i < K - 1; ++i) {
+    const double cc = e[i], an = d[i + 1] - lam, bn = (i + 1 < K - 1) ? e[i + 1] : 0.0;
+    const bool piv = fabs(al) < fabs(cc);
+    double a0 = al;
+    if (!piv && fabs(a0) < tiny) a0 = (a0 < 0.0) ? -tiny : tiny;
+    const double u0 = piv ? cc : a0;
+    const double r0 = 1.0 / u0;
+    const double l = (piv ? al : cc) * r0;
+    const size_t o = (size_t)i * st;
+    f[o] = l;
+    f[KR + o] = piv ? 1.0 : 0.0;
+    f[2 * KR + o] = r0;
+    f[3 * KR + o] = piv ? an : be;
+    f[4 * KR + o] = piv ? bn : 0.0;
+    const double nal = piv ? (be - l * an) : (an - l * be);
+    const double nbe = piv ? (-l * bn) : bn;
+    al = nal;
+    be = nbe;
+  }
+  if (fabs(al) < tiny) al = (al < 0.0) ? -tiny : tiny;
+  const size_t o = (size_t)(K - 1) * st;
+  f[o] = 0.0;
+  f[KR + o] = 0.0;
+  f[2 * KR + o] = 1.0 / al;
+  f[3 * KR + o] = 0.0;
+  f[4 * KR + o] = 0.0;
+}
+
+// One inverse-iteration solve (T - lambda I) z_new = sc * z in place (z at
+// stride zs); returns 1 / ||z_new||.
+__device__ __forceinline__ double tri_solve(const double* f, int st, size_t KR, int K, double* z, int zs,
+                                            double sc) {
+  // forward: P and the unit lower bidiagonal L, carried value in a register
+  double cur = z[0] * sc;
+  for (int i = 0; i < K - 1; ++i) {
+    const size_t o = (size_t)i * st;
+    const double raw = z[(size_t)(i + 1) * zs] * sc;
+    const bool p = f[KR + o] != 0.0;
+    const double out = p ? raw : cur;
+    const double oth = p ? cur : raw;
+    z[(size_t)i * zs] = out;
+    cur = oth - f[o] * out;
+  }
+  z[(size_t)(K - 1) * zs] = cur;
+  // backward: upper triangular with two superdiagonals
+  double z1 = 0.0, z2 = 0.0, nn = 0.0;
+  for (int i = K - 1; i >= 0; --i) {
+    const size_t o = (size_t)i * st;
+    const double zi = (z[(size_t)i * zs] - f[3 * KR + o] * z1 - f[4 * KR + o] * z2) * f[2 * KR + o];
+    z[(size_t)i * zs] = zi;
+    nn += zi * zi;
+    z2 = z1;
+    z1 = zi;
+  }
+  return 1.0 / sqrt(nn);
+}
+
 template <bool ADMM>
 __global__ __launch_bounds__(kLT) void k_large_eig(LargeArgs a) {
   __shared__ double sd[1024], se[1024], se2[1024];
@@ -420,18 +484,40 @@ __global__ __launch_bounds__(kLT) void k_large_eig(LargeArgs a) {
   const double pivmin = red[0];
   const int r = info[0], pos = info[1], first = info[2];
   const double tnorm = fmax(tn, 2.2250738585072014e-308);
-  // Gershgorin interval
-  const double glo = -tnorm * (1.0 + 4.0 * kEps) - pivmin, ghi = tnorm * (1.0 + 4.0 * kEps) + pivmin;
-  for (int t = tid; t < r; t += kLT) {
-    const int k = first + t;
-    double lo = glo, hi = ghi;
-    for (int it = 0; it < 128; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin) break;
-      if (sturm_count(sd, se2, K, mid, pivmin) > k) hi = mid;
-      else lo = mid;
+  // Bisection by groups of g lanes per eigenvalue (multisection: the g lanes
+  // evaluate the Sturm count at g interior points and the interval shrinks
+  // by g + 1 per round).  The chosen side lies in [Gershgorin low, 0] or
+  // [0, Gershgorin high]; the count at 0 is the nneg found above, so the
+  // invariant count(lo) <= k < count(hi) holds from the start.  Intervals are
+  // refined to an absolute width of about eps * ||T||, which is the accuracy
+  // inverse iteration and the low-rank update below can use.
+  {
+    int g = 64;
+    while (g > 1 && r * g > kLT) g >>= 1;
+    const int ngroups = kLT / g;
+    const int grp = tid / g, gl = tid % g;
+    const int lane = tid & 63, gbase = lane - gl;
+    const uint64_t gmask = (g == 64) ? ~0ull : ((1ull << g) - 1ull);
+    const double glo = -tnorm * (1.0 + 4.0 * kEps) - pivmin, ghi = tnorm * (1.0 + 4.0 * kEps) + pivmin;
+    const double wtol = 2.0 * kEps * tnorm + 4.0 * pivmin;
+    for (int t = grp; t < r; t += ngroups) {
+      const int k = first + t;
+      double lo = pos ? 0.0 : glo, hi = pos ? ghi : 0.0;
+      for (int round = 0; round < 200; ++round) {
+        const double width = hi - lo;
+        if (width <= fmax(wtol, 2.0 * kEps * fmax(fabs(lo), fabs(hi)))) break;
+        const double step = width / (double)(g + 1);
+        const double x = lo + step * (double)(gl + 1);
+        const bool above = sturm_count(sd, se2, K, x, pivmin) > k;
+        const uint64_t m = (__ballot(above) >> gbase) & gmask;
+        const int j0 = m ? __builtin_ctzll(m) : g;   // first point with count > k
+        const double nlo = (j0 == 0) ? lo : lo + step * (double)j0;
+        const double nhi = (j0 == g) ? hi : lo + step * (double)(j0 + 1);
+        lo = nlo;
+        hi = fmax(nhi, nlo);
+      }
+      if (gl == 0) slam[t] = 0.5 * (lo + hi);
     }
-    slam[t] = 0.5 * (lo + hi);
   }
   __syncthreads();
   // clusters of close eigenvalues (consecutive gaps below the threshold)
@@ -446,69 +532,63 @@ __global__ __launch_bounds__(kLT) void k_large_eig(LargeArgs a) {
   __syncthreads();
   const int ncl = info[3];
   const double tiny = kEps * tnorm;
-  // one thread per cluster: inverse iteration with a partially pivoted LU
-  // of T - lambda I, orthogonalised against the cluster's earlier vectors
-  for (int c = tid; c < ncl; c += kLT) {
-    double* S = w.S + (size_t)c * 5 * K;
-    double* L = S;
-    double* U0 = S + K;
-    double* U1 = S + 2 * K;
-    double* U2 = S + 3 * K;
-    double* P = S + 4 * K;
-    for (int t = cls[c]; t < cls[c + 1]; ++t) {
-      const double lamb = slam[t];
-      // factor
-      double al = sd[0] - lamb, be = (K > 1) ? se[0] : 0.0;
-      for (int i = 0; i < K - 1; ++i) {
-        const double cc = se[i], an = sd[i + 1] - lamb, bn = (i + 1 < K - 1) ? se[i + 1] : 0.0;
-        if (fabs(al) >= fabs(cc)) {
-          if (fabs(al) < tiny) al = (al < 0.0) ? -tiny : tiny;
-          const double l = cc / al;
-          U0[i] = al;
-          U1[i] = be;
-          U2[i] = 0.0;
-          P[i] = 0.0;
-          L[i] = l;
-          al = an - l * be;
-          be = bn;
-        } else {
-          const double l = al / cc;
-          U0[i] = cc;
-          U1[i] = an;
-          U2[i] = bn;
-          P[i] = 1.0;
-          L[i] = l;
-          al = be - l * an;
-          be = -l * bn;
-        }
+  // Inverse iteration with a partially pivoted LU of T - lambda I.  The
+  // factors of eigenvalue t live in the scratch area element-major
+  // (entry i of array a at ((a * K + i) * r + t)), so lanes that work on
+  // consecutive eigenvalues touch consecutive addresses; 6 K r <= 3 K^2
+  // since r <= K / 2.
+  double* X = w.S;
+  const size_t KR = (size_t)K * r;
+  // (a) isolated eigenvalues: one lane each, three solves, the vector kept in
+  //     the scratch area and normalised lazily
+  for (int t = tid; t < r; t += kLT) {
+    int c = 0;
+    {
+      int lo = 0, hi = ncl;   // cluster of t: largest c with cls[c] <= t
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cls[mid] <= t) lo = mid;
+        else hi = mid;
       }
-      if (fabs(al) < tiny) al = (al < 0.0) ? -tiny : tiny;
-      U0[K - 1] = al;
-      double* z = w.Z + (size_t)t * K;
-      for (int i = 0; i < K; ++i) z[i] = hash_unit((uint32_t)t, (uint32_t)i);
-      for (int it = 0; it < 3; ++it) {
-        for (int i = 0; i < K - 1; ++i) {
-          if (P[i] != 0.0) {
-            const double tmp = z[i];
-            z[i] = z[i + 1];
-            z[i + 1] = tmp;
-          }
-          z[i + 1] -= L[i] * z[i];
+      c = lo;
+    }
+    if (cls[c + 1] - cls[c] != 1) continue;
+    double* zt = X + 5 * KR + t;
+    tri_factor(sd, se, K, slam[t], tiny, X + t, r, KR);
+    for (int i = 0; i < K; ++i) zt[(size_t)i * r] = hash_unit((uint32_t)t, (uint32_t)i);
+    double sc = 1.0;
+    for (int it = 0; it < 3; ++it) sc = tri_solve(X + t, r, KR, K, zt, r, sc);
+    double* zo = w.Z + (size_t)t * K;
+    for (int i = 0; i < K; ++i) zo[i] = zt[(size_t)i * r] * sc;
+  }
+  // (b) clusters: one wave each; lane 0 runs the sequential solves on the
+  //     member's column of Z, the wave orthogonalises it against the
+  //     cluster's earlier members (twice) and normalises it
+  {
+    const int wid = tid >> 6, lane = tid & 63;
+    for (int c = wid; c < ncl; c += kLT / 64) {
+      if (cls[c + 1] - cls[c] < 2) continue;
+      for (int t = cls[c]; t < cls[c + 1]; ++t) {
+        double* z = w.Z + (size_t)t * K;
+        if (lane == 0) tri_factor(sd, se, K, slam[t], tiny, X + t, r, KR);
+        for (int i = lane; i < K; i += 64) z[i] = hash_unit((uint32_t)t, (uint32_t)i);
+        for (int it = 0; it < 3; ++it) {
+          __threadfence_block();
+          if (lane == 0) (void)tri_solve(X + t, r, KR, K, z, 1, 1.0);
+          __threadfence_block();
+          for (int pass = 0; pass < 2; ++pass)
+            for (int p = cls[c]; p < t; ++p) {
+              const double* q = w.Z + (size_t)p * K;
+              double dot = 0.0;
+              for (int i = lane; i < K; i += 64) dot += q[i] * z[i];
+              dot = wave_sum(dot);
+              for (int i = lane; i < K; i += 64) z[i] -= dot * q[i];
+            }
+          double nn = 0.0;
+          for (int i = lane; i < K; i += 64) nn += z[i] * z[i];
+          const double sc = 1.0 / sqrt(wave_sum(nn));
+          for (int i = lane; i < K; i += 64) z[i] *= sc;
         }
-        z[K - 1] /= U0[K - 1];
-        if (K > 1) z[K - 2] = (z[K - 2] - U1[K - 2] * z[K - 1]) / U0[K - 2];
-        for (int i = K - 3; i >= 0; --i) z[i] = (z[i] - U1[i] * z[i + 1] - U2[i] * z[i + 2]) / U0[i];
-        for (int pass = 0; pass < 2; ++pass)
-          for (int p = cls[c]; p < t; ++p) {
-            const double* q = w.Z + (size_t)p * K;
-            double dot = 0.0;
-            for (int i = 0; i < K; ++i) dot += q[i] * z[i];
-            for (int i = 0; i < K; ++i) z[i] -= dot * q[i];
-          }
-        double nn = 0.0;
-        for (int i = 0; i < K; ++i) nn += z[i] * z[i];
-        const double sc = 1.0 / sqrt(nn);
-        for (int i = 0; i < K; ++i) z[i] *= sc;
       }
     }
   }
