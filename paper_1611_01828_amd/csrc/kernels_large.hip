@@ -392,30 +392,61 @@ __device__ __forceinline__ void tri_factor(const double* d, const double* e, int
 }
 
 // One inverse-iteration solve (T - lambda I) z_new = sc * z in place (z at
-// stride zs); returns 1 / ||z_new||.
-__device__ __forceinline__ double tri_solve(const double* f, int st, size_t KR, int K, double* z, int zs,
-                                            double sc) {
-  // forward: P and the unit lower bidiagonal L, carried value in a register
+// stride zs); returns 1 / ||z_new||.  Both sweeps are recurrences carried in
+// registers; the operands of 8 consecutive steps are loaded ahead (clamped
+// indices, no predicated loads) so that one lane's chain does not wait on
+// every load.
+__device__ __forceinline__ double tri_solve(const double* __restrict__ f, int st, size_t KR, int K,
+                                            double* __restrict__ z, int zs, double sc) {
+  constexpr int C = 8;
+  // forward: P and the unit lower bidiagonal L
   double cur = z[0] * sc;
-  for (int i = 0; i < K - 1; ++i) {
-    const size_t o = (size_t)i * st;
-    const double raw = z[(size_t)(i + 1) * zs] * sc;
-    const bool p = f[KR + o] != 0.0;
-    const double out = p ? raw : cur;
-    const double oth = p ? cur : raw;
-    z[(size_t)i * zs] = out;
-    cur = oth - f[o] * out;
+  for (int i0 = 0; i0 < K - 1; i0 += C) {
+    double raw[C], lv[C], pv[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int i = min(i0 + j, K - 2);
+      raw[j] = z[(size_t)(i + 1) * zs];
+      lv[j] = f[(size_t)i * st];
+      pv[j] = f[KR + (size_t)i * st];
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int i = i0 + j;
+      if (i < K - 1) {
+        const double rw = raw[j] * sc;
+        const bool p = pv[j] != 0.0;
+        const double out = p ? rw : cur;
+        const double oth = p ? cur : rw;
+        z[(size_t)i * zs] = out;
+        cur = oth - lv[j] * out;
+      }
+    }
   }
   z[(size_t)(K - 1) * zs] = cur;
   // backward: upper triangular with two superdiagonals
   double z1 = 0.0, z2 = 0.0, nn = 0.0;
-  for (int i = K - 1; i >= 0; --i) {
-    const size_t o = (size_t)i * st;
-    const double zi = (z[(size_t)i * zs] - f[3 * KR + o] * z1 - f[4 * KR + o] * z2) * f[2 * KR + o];
-    z[(size_t)i * zs] = zi;
-    nn += zi * zi;
-    z2 = z1;
-    z1 = zi;
+  for (int i0 = K - 1; i0 >= 0; i0 -= C) {
+    double zv[C], u1[C], u2[C], r0[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const size_t o = (size_t)max(i0 - j, 0);
+      zv[j] = z[o * zs];
+      u1[j] = f[3 * KR + o * st];
+      u2[j] = f[4 * KR + o * st];
+      r0[j] = f[2 * KR + o * st];
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int i = i0 - j;
+      if (i >= 0) {
+        const double zi = (zv[j] - u1[j] * z1 - u2[j] * z2) * r0[j];
+        z[(size_t)i * zs] = zi;
+        nn += zi * zi;
+        z2 = z1;
+        z1 = zi;
+      }
+    }
   }
   return 1.0 / sqrt(nn);
 }
