@@ -17,6 +17,8 @@
 //                  s+, z+ = s+ - Y, v+ and the residual partial sums (ADMM
 //                  mode) or written to the output blocks (projection mode)
 //   6. partials    per-clique sum of the tile partials (fixed order)
+#include <algorithm>
+
 #include "device.h"
 
 namespace cdcs {
@@ -143,17 +145,216 @@ __global__ __launch_bounds__(256) void k_large_gather(LargeArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// 2. Householder tridiagonalisation (blocked panels, full storage)
+// 2. Householder tridiagonalisation (blocked panels of kNB columns, full
+//    storage).  Column j of panel p (position i) is one pair of launches over
+//    all tasks, so that each column step of a large clique is spread over
+//    many workgroups (the step is a latency-bound matrix-vector product; one
+//    workgroup per clique would leave most of the chip idle):
+//      symv:   every workgroup forms the reflector of column j from the
+//              column itself (H x = beta e_1, x = A(j+1:K, j)), then
+//              y = A22 v on a chunk of 32 columns; the chunks past the
+//              trailing columns give the panel dots t1 = Wp^T v, t2 = V^T v,
+//              and each chunk leaves its share of y^T v
+//      update: w = tau (y - V t1 - Wp t2) and Wp(:, i) = w + alpha v with
+//              alpha = -tau/2 w^T v, where w^T v = tau (y^T v - 2 t1^T t2);
+//              the Householder vector goes to column j, and column j + 1 is
+//              brought up to date with the panel's reflectors 0..i
+//      trail:  A22 -= V Wp^T + Wp V^T after the panel's last column
+//    Kernel boundaries are the only synchronisation.  All global loads of
+//    the symv are unconditional and aligned (double2 over the padded
+//    leading dimension, zero padding rows, v zero outside its support).
 // ---------------------------------------------------------------------------
-// All global loads of the hot loops are unconditional and aligned (double2
-// over the padded leading dimension, zero padding rows, v zero outside its
-// support), so a wave keeps many loads in flight instead of waiting on each.
+constexpr int kSymvCols = 32;   // columns per symv workgroup (4 waves x 8)
+constexpr int kUpdRows = 64;    // rows per update workgroup (one wave)
+
+struct TrdBufs {
+  double* V;    // ld x kNB reflectors of the panel
+  double* Wp;   // ld x kNB
+  double* y;    // ld      A22 v
+  double* t;    // 2 kNB   t1, t2
+  double* yv;   // per symv chunk share of y^T v
+};
+
+__device__ __forceinline__ TrdBufs trd_bufs(const Ws& w, int ld) {
+  TrdBufs b;
+  b.V = w.S;
+  b.Wp = w.S + (size_t)ld * kNB;
+  b.y = w.S + (size_t)2 * ld * kNB;
+  b.t = b.y + ld;
+  b.yv = b.t + 2 * kNB;
+  return b;
+}
+
+// column j = p kNB + i of a task with K vertices, nb = columns of its panel
+__device__ __forceinline__ bool trd_col(int K, int p, int i, int& j, int& nb) {
+  const int j0 = p * kNB;
+  if (j0 >= K - 2) return false;
+  nb = min(kNB, K - 2 - j0);
+  if (i >= nb) return false;
+  j = j0 + i;
+  return true;
+}
+
 template <bool ADMM>
-__global__ __launch_bounds__(kTT) void k_large_tridiag(LargeArgs a) {
+__global__ __launch_bounds__(256) void k_trd_symv(LargeArgs a, int p, int i) {
   __shared__ __align__(16) double vbuf[1024];
-  __shared__ double ybuf[1024];
-  __shared__ double t1[kNB], t2[kNB], cwj[kNB], cvj[kNB];
-  __shared__ double red[kTT / 64 + 1];
+  __shared__ double red[256 / 64 + 1];
+  __shared__ double part[4];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  int j, nb;
+  if (!trd_col(K, p, i, j, nb)) return;
+  const int ncol = K - j - 1, nall = ncol + 2 * i;
+  const int cbase = blockIdx.y * kSymvCols;
+  if (cbase >= nall) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int ld = lead_dim(K);
+  const TrdBufs b = trd_bufs(w, ld);
+  const double* W = w.W;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // reflector of column j (every workgroup forms the same one)
+  double ss = 0.0;
+  for (int r = j + 2 + tid; r < K; r += 256) {
+    const double x = W[(size_t)j * ld + r];
+    ss += x * x;
+  }
+  ss = block_sum<256>(ss, red);
+  const double alpha = W[(size_t)j * ld + j + 1];
+  double beta, tu, scale;
+  if (ss == 0.0) {
+    beta = alpha;
+    tu = 0.0;
+    scale = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+    tu = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  for (int r = tid; r < ld; r += 256) {
+    double vr = 0.0;
+    if (r == j + 1) vr = 1.0;
+    else if (r > j + 1 && r < K) vr = W[(size_t)j * ld + r] * scale;
+    vbuf[r] = vr;
+    if (blockIdx.y == 0) b.V[(size_t)i * ld + r] = vr;
+  }
+  if (blockIdx.y == 0 && tid == 0) {
+    w.d[j] = W[(size_t)j * ld + j];
+    w.e[j] = beta;
+    w.tau[j] = tu;
+  }
+  __syncthreads();
+  // columns cbase + 8 wid + u of [A22 | Wp(:, 0:i) | V(:, 0:i)]; W, V and Wp
+  // live in one workspace, every column addressed by its offset from W
+  // (V = W + 2 ld^2, Wp = V + kNB ld)
+  const int r0 = (j + 1) & ~1;
+  const int nk = (ld - r0 + 127) / 128;
+  const int cg = cbase + wid * 8;
+  double yv = 0.0;
+  if (cg < nall) {
+    int coff[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = min(cg + u, nall - 1);
+      coff[u] = (q < ncol) ? (j + 1 + q) * ld
+                           : 2 * ld * ld + ((q < ncol + i) ? (kNB + q - ncol) * ld : (q - ncol - i) * ld);
+    }
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+    for (int k = 0; k < nk; ++k) {
+      const int r = r0 + 2 * lane + 128 * k;
+      const int rr = min(r, ld - 2);
+      const double2 vv = *reinterpret_cast<const double2*>(vbuf + rr);
+      const double m = (r < ld) ? 1.0 : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double2 av = *reinterpret_cast<const double2*>(W + coff[u] + rr);
+        acc[u] += m * (av.x * vv.x + av.y * vv.y);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double sum = wave_sum(acc[u]);
+      const int q = cg + u;
+      if (q < ncol) {
+        if (lane == 0) b.y[j + 1 + q] = sum;
+        yv += sum * vbuf[j + 1 + q];
+      } else if (q < nall && lane == 0) {
+        if (q < ncol + i) b.t[q - ncol] = sum;
+        else b.t[kNB + q - ncol - i] = sum;
+      }
+    }
+  }
+  if (lane == 0) part[wid] = yv;
+  __syncthreads();
+  if (tid == 0) b.yv[blockIdx.y] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+template <bool ADMM>
+__global__ __launch_bounds__(kUpdRows) void k_trd_update(LargeArgs a, int p, int i) {
+  __shared__ double t1[kNB], t2[kNB], cvj[kNB + 1], cwj[kNB + 1];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  int j, nb;
+  if (!trd_col(K, p, i, j, nb)) return;
+  const int ld = lead_dim(K);
+  const int r = blockIdx.y * kUpdRows + threadIdx.x;
+  if (blockIdx.y * kUpdRows >= ld) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const TrdBufs b = trd_bufs(w, ld);
+  const int tid = threadIdx.x;
+  const bool next = i + 1 < nb;   // column j + 1 belongs to this panel
+  const int jc = j + 1;
+  if (tid < i) {
+    t1[tid] = b.t[tid];
+    t2[tid] = b.t[kNB + tid];
+  }
+  if (tid <= i) {
+    cvj[tid] = b.V[(size_t)tid * ld + jc];
+    cwj[tid] = b.Wp[(size_t)tid * ld + jc];
+  }
+  __syncthreads();
+  const int ncol = K - j - 1, nall = ncol + 2 * i;
+  const int nch = (nall + kSymvCols - 1) / kSymvCols;
+  double yv = 0.0;
+  for (int c = 0; c < nch; ++c) yv += b.yv[c];
+  double tt = 0.0;
+  for (int l = 0; l < i; ++l) tt += t1[l] * t2[l];
+  const double tu = w.tau[j];
+  const double al = -0.5 * tu * (tu * (yv - 2.0 * tt));
+  // Wp(jc, i), computed by every workgroup the way the owner of row jc does
+  double wpj = 0.0;
+  {
+    double y = b.y[jc];
+    for (int l = 0; l < i; ++l) y -= cvj[l] * t1[l] + cwj[l] * t2[l];
+    wpj = tu * y + al * cvj[i];
+  }
+  if (r >= ld) return;   // whole-lane exits; no barriers below
+  double wr = 0.0;
+  if (r > j && r < K) {
+    double y = b.y[r];
+    double v = next ? w.W[(size_t)jc * ld + r] : 0.0;
+#pragma unroll 8
+    for (int l = 0; l < i; ++l) {
+      const double Vr = b.V[(size_t)l * ld + r], Wr = b.Wp[(size_t)l * ld + r];
+      y -= Vr * t1[l] + Wr * t2[l];
+      v -= Vr * cwj[l] + Wr * cvj[l];
+    }
+    const double vi = b.V[(size_t)i * ld + r];
+    wr = tu * y + al * vi;
+    if (next && r >= jc) {
+      v -= vi * wpj + wr * cvj[i];
+      w.W[(size_t)jc * ld + r] = v;
+    }
+    if (r >= j + 2) w.W[(size_t)j * ld + r] = vi;   // Householder vector below the subdiagonal
+  }
+  b.Wp[(size_t)i * ld + r] = wr;
+}
+
+template <bool ADMM>
+__global__ __launch_bounds__(kTT) void k_trd_trail(LargeArgs a, int p) {
   __shared__ double stage[2 * kNB * 128 + 2 * kNB * 64];
   double(*pr_v)[128] = reinterpret_cast<double(*)[128]>(stage);
   double(*pr_w)[128] = reinterpret_cast<double(*)[128]>(stage + kNB * 128);
@@ -162,180 +363,74 @@ __global__ __launch_bounds__(kTT) void k_large_tridiag(LargeArgs a) {
   int K;
   int64_t base;
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  const int j0 = p * kNB;
+  if (j0 >= K - 2) return;
+  const int nb = min(kNB, K - 2 - j0);
+  const int jn = j0 + nb, n2 = K - jn;
+  const int ntr = (n2 + 127) / 128, ntc = (n2 + 63) / 64;
+  const int tile = blockIdx.y;
+  if (tile >= ntr * ntc) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const int ld = lead_dim(K);
+  const TrdBufs b = trd_bufs(w, ld);
   double* W = w.W;
-  double* V = w.S;
-  double* Wp = w.S + (size_t)ld * kNB;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  constexpr int NW = kTT / 64;
-  for (int j0 = 0; j0 < K - 2; j0 += kNB) {
-    const int nb = min(kNB, K - 2 - j0);
-    for (int i = 0; i < nb; ++i) {
-      const int j = j0 + i;
-      // (a) bring column j up to date with the panel's earlier reflectors
-      if (tid < i) {
-        cwj[tid] = Wp[(size_t)tid * ld + j];
-        cvj[tid] = V[(size_t)tid * ld + j];
-      }
-      __syncthreads();
-      for (int r = j + tid; r < K; r += kTT) {
-        double v = W[(size_t)j * ld + r];
-#pragma unroll 4
-        for (int l = 0; l < i; ++l) v -= V[(size_t)l * ld + r] * cwj[l] + Wp[(size_t)l * ld + r] * cvj[l];
-        W[(size_t)j * ld + r] = v;
-      }
-      __syncthreads();
-      // (b) reflector H = I - tau v v^T with H x = beta e_1, x = W[j+1:, j]
-      double ss = 0.0;
-      for (int r = j + 2 + tid; r < K; r += kTT) {
-        const double x = W[(size_t)j * ld + r];
-        ss += x * x;
-      }
-      ss = block_sum<kTT>(ss, red);
-      const double alpha = W[(size_t)j * ld + j + 1];
-      double beta, tu, scale;
-      if (ss == 0.0) {
-        beta = alpha;
-        tu = 0.0;
-        scale = 0.0;
-      } else {
-        beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-        tu = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      if (tid == 0) {
-        w.d[j] = W[(size_t)j * ld + j];
-        w.e[j] = beta;
-        w.tau[j] = tu;
-      }
-      for (int r = tid; r < ld; r += kTT) {
-        double vr = 0.0;
-        if (r == j + 1) vr = 1.0;
-        else if (r > j + 1 && r < K) vr = W[(size_t)j * ld + r] * scale;
-        vbuf[r] = vr;
-        V[(size_t)i * ld + r] = vr;
-      }
-      __syncthreads();
-      for (int r = j + 2 + tid; r < K; r += kTT) W[(size_t)j * ld + r] = vbuf[r];
-      // (c) y = A22 v and t1 = Wp^T v, t2 = V^T v (the 2i panel columns
-      //     appended to the column set): 8 columns per wave round, double2
-      //     row pairs per lane, no branches around the loads
-      {
-        const int r0 = (j + 1) & ~1;
-        const int nk = (ld - r0 + 127) / 128;
-        const int ncol = K - j - 1, nall = ncol + 2 * i;
-        for (int cg = wid * 8; cg < nall; cg += NW * 8) {
-          // W, V and Wp live in one workspace: address every column by its
-          // offset from W (V = W + 2 ld^2, Wp = V + 32 ld)
-          int coff[8];
+  const int tid = threadIdx.x;
+  // A22 -= V Wp^T + Wp V^T on a 128 x 64 tile (both triangles), panel rows
+  // staged in LDS, 4 x 4 outputs per thread
+  const int r0 = jn + (tile % ntr) * 128, c0 = jn + (tile / ntr) * 64;
+  for (int idx = tid; idx < 128 * kNB; idx += kTT) {
+    const int rr = idx & 127, l = idx >> 7;
+    const bool ok = (r0 + rr < K) && l < nb;
+    pr_v[l][rr] = ok ? b.V[(size_t)l * ld + r0 + rr] : 0.0;
+    pr_w[l][rr] = ok ? b.Wp[(size_t)l * ld + r0 + rr] : 0.0;
+  }
+  for (int idx = tid; idx < 64 * kNB; idx += kTT) {
+    const int cc = idx & 63, l = idx >> 6;
+    const bool ok = (c0 + cc < K) && l < nb;
+    pc_v[l][cc] = ok ? b.V[(size_t)l * ld + c0 + cc] : 0.0;
+    pc_w[l][cc] = ok ? b.Wp[(size_t)l * ld + c0 + cc] : 0.0;
+  }
+  __syncthreads();
+  const int tr = tid & 31, tc = tid >> 5;     // rows tr + 32 u, columns 4 tc + q
+  double acc[4][4];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int q = min(cg + u, nall - 1);
-            coff[u] = (q < ncol) ? (j + 1 + q) * ld
-                                 : 2 * ld * ld + ((q < ncol + i) ? (kNB + q - ncol) * ld : (q - ncol - i) * ld);
-          }
-          double acc[8];
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-          for (int k = 0; k < nk; ++k) {
-            const int r = r0 + 2 * lane + 128 * k;
-            const int rr = min(r, ld - 2);
-            const double2 vv = *reinterpret_cast<const double2*>(vbuf + rr);
-            const double m = (r < ld) ? 1.0 : 0.0;
+    for (int q = 0; q < 4; ++q) acc[u][q] = 0.0;
+  for (int l = 0; l < nb; ++l) {
+    double cv[4], cw[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const double2 av = *reinterpret_cast<const double2*>(W + coff[u] + rr);
-              acc[u] += m * (av.x * vv.x + av.y * vv.y);
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const double sum = wave_sum(acc[u]);
-            const int q = cg + u;
-            if (lane == 0 && q < nall) {
-              if (q < ncol) ybuf[j + 1 + q] = sum;
-              else if (q < ncol + i) t1[q - ncol] = sum;
-              else t2[q - ncol - i] = sum;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      // (d) y -= V t1 + Wp t2 ; w = tau y ; w += -tau/2 (w^T v) v
-      double pw = 0.0;
-      for (int r = j + 1 + tid; r < K; r += kTT) {
-        double y = ybuf[r];
-#pragma unroll 4
-        for (int l = 0; l < i; ++l) y -= V[(size_t)l * ld + r] * t1[l] + Wp[(size_t)l * ld + r] * t2[l];
-        y *= tu;
-        ybuf[r] = y;
-        pw += y * vbuf[r];
-      }
-      pw = block_sum<kTT>(pw, red);
-      const double al = -0.5 * tu * pw;
-      for (int r = tid; r < ld; r += kTT) Wp[(size_t)i * ld + r] = (r > j && r < K) ? ybuf[r] + al * vbuf[r] : 0.0;
-      __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      cv[q] = pc_v[l][4 * tc + q];
+      cw[q] = pc_w[l][4 * tc + q];
     }
-    // trailing update A22 -= V Wp^T + Wp V^T on rows/cols >= j0 + nb (both
-    // triangles): 128 x 64 tiles, panel rows staged in LDS, 4 x 4 outputs per
-    // thread
-    const int jn = j0 + nb, n2 = K - jn;
-    const int ntr = (n2 + 127) / 128, ntc = (n2 + 63) / 64;
-    for (int tile = 0; tile < ntr * ntc; ++tile) {
-      const int r0 = jn + (tile % ntr) * 128, c0 = jn + (tile / ntr) * 64;
-      for (int idx = tid; idx < 128 * kNB; idx += kTT) {
-        const int rr = idx & 127, l = idx >> 7;
-        const bool ok = (r0 + rr < K) && l < nb;
-        pr_v[l][rr] = ok ? V[(size_t)l * ld + r0 + rr] : 0.0;
-        pr_w[l][rr] = ok ? Wp[(size_t)l * ld + r0 + rr] : 0.0;
-      }
-      for (int idx = tid; idx < 64 * kNB; idx += kTT) {
-        const int cc = idx & 63, l = idx >> 6;
-        const bool ok = (c0 + cc < K) && l < nb;
-        pc_v[l][cc] = ok ? V[(size_t)l * ld + c0 + cc] : 0.0;
-        pc_w[l][cc] = ok ? Wp[(size_t)l * ld + c0 + cc] : 0.0;
-      }
-      __syncthreads();
-      const int tr = tid & 31, tc = tid >> 5;     // rows tr + 32 u, columns 4 tc + q
-      double acc[4][4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 4; ++u) {
+      const double rv = pr_v[l][tr + 32 * u], rw = pr_w[l][tr + 32 * u];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[u][q] = 0.0;
-      for (int l = 0; l < nb; ++l) {
-        double cv[4], cw[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          cv[q] = pc_v[l][4 * tc + q];
-          cw[q] = pc_w[l][4 * tc + q];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double rv = pr_v[l][tr + 32 * u], rw = pr_w[l][tr + 32 * u];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[u][q] += rv * cw[q] + rw * cv[q];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = r0 + tr + 32 * u;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int c = c0 + 4 * tc + q;
-          if (r < K && c < K) W[(size_t)c * ld + r] -= acc[u][q];
-        }
-      }
-      __syncthreads();
+      for (int q = 0; q < 4; ++q) acc[u][q] += rv * cw[q] + rw * cv[q];
     }
   }
-  if (tid == 0) {
-    w.d[K - 2] = W[(size_t)(K - 2) * ld + K - 2];
-    w.d[K - 1] = W[(size_t)(K - 1) * ld + K - 1];
-    w.e[K - 2] = W[(size_t)(K - 2) * ld + K - 1];
-    w.e[K - 1] = 0.0;
-    w.tau[K - 2] = 0.0;
-    w.tau[K - 1] = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = r0 + tr + 32 * u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + 4 * tc + q;
+      if (r < K && c < K) W[(size_t)c * ld + r] -= acc[u][q];
+    }
+  }
+  if (jn == K - 2) {
+    // the last panel leaves the trailing 2 x 2 block, which completes T
+    __syncthreads();
+    if (tid == 0) {
+      w.d[K - 2] = W[(size_t)(K - 2) * ld + K - 2];
+      w.d[K - 1] = W[(size_t)(K - 1) * ld + K - 1];
+      w.e[K - 2] = W[(size_t)(K - 2) * ld + K - 1];
+      w.e[K - 1] = 0.0;
+      w.tau[K - 2] = 0.0;
+      w.tau[K - 1] = 0.0;
+    }
   }
 }
 
@@ -774,7 +869,26 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, int 
   const int T = (kmax + kTile - 1) / kTile;
   switch (step) {
     case 0: hipLaunchKernelGGL(k_large_gather<ADMM>, dim3(ntask), dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL(k_large_tridiag<ADMM>, dim3(ntask), dim3(kTT), 0, st, a); break;
+    case 1: {
+      // the column steps of all tasks in lockstep; tasks with fewer columns
+      // return at once from launches past their last column
+      const int np = (kmax - 2 + kNB - 1) / kNB;
+      const int ldm = (kmax + 7) & ~7;
+      for (int p = 0; p < np; ++p) {
+        const int nbm = std::min(kNB, kmax - 2 - p * kNB);
+        for (int i = 0; i < nbm; ++i) {
+          const int nallm = kmax - p * kNB - 1 + i;
+          hipLaunchKernelGGL(k_trd_symv<ADMM>, dim3(ntask, (nallm + kSymvCols - 1) / kSymvCols), dim3(256), 0, st, a,
+                             p, i);
+          hipLaunchKernelGGL(k_trd_update<ADMM>, dim3(ntask, (ldm + kUpdRows - 1) / kUpdRows), dim3(kUpdRows), 0, st,
+                             a, p, i);
+        }
+        const int n2 = kmax - p * kNB - nbm;
+        hipLaunchKernelGGL(k_trd_trail<ADMM>, dim3(ntask, ((n2 + 127) / 128) * ((n2 + 63) / 64)), dim3(kTT), 0, st,
+                           a, p);
+      }
+      break;
+    }
     case 2: hipLaunchKernelGGL(k_large_eig<ADMM>, dim3(ntask), dim3(kLT), 0, st, a); break;
     case 3:
       hipLaunchKernelGGL(k_large_backtrans<ADMM>, dim3(ntask, (rmax + kBtCols - 1) / kBtCols), dim3(kLT), 0, st, a);
