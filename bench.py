@@ -34,18 +34,48 @@ PEAK_HBM_GBS = 8000.0
 
 
 def phase_work(inst_sizes, prob_dims):
-    """Algorithmic work per launch of each phase (flops or bytes)."""
+    """Algorithmic work of one average launch of each kernel phase.
+
+    Returns {phase: (bound, amount, unit)}; amount is bytes for memory-bound
+    phases and flops for arithmetic ones.  The tridiagonalisation runs one
+    symv and one update launch per column step of the largest clique (all
+    large cliques in lockstep) and one trailing update per panel of 32."""
     large = [k for k in inst_sizes if k > 96]
     small = [k for k in inst_sizes if k <= 96]
     nE, ns, m, p = prob_dims
-    return {
-        # Householder tridiagonalisation: 4/3 K^3 flops per block (Golub & Van Loan 8.3.1)
-        "large_tridiag": ("alu", sum(4.0 / 3.0 * k ** 3 for k in large), "TFLOP/s"),
-        # Jacobi blocks: counted with the same 10 K^3 eigen-decomposition convention
-        "cone_jacobi16": ("alu", sum(10.0 * k ** 3 for k in small if k <= 16), "TFLOP/s"),
-        # scatter H^T(s+z+v): read s,z,v (3 ns doubles) + slot ids + x, c, pinv; write hsum, q
-        "r0_scatter": ("hbm", 8.0 * 3 * ns + 4.0 * ns + 4.0 * (nE + 1) + 8.0 * 3 * nE + 8.0 * 2 * nE, "GB/s"),
-    }
+    out = {}
+    if large:
+        kmax, nbp = max(large), 32
+        npan = (kmax - 2 + nbp - 1) // nbp
+        symv_b = upd_b = trail_f = 0.0
+        n_cols = 0
+        for pp in range(npan):
+            nbm = min(nbp, kmax - 2 - pp * nbp)
+            n_cols += nbm
+            for K in large:
+                j0 = pp * nbp
+                if j0 >= K - 2:
+                    continue
+                nb = min(nbp, K - 2 - j0)
+                n2 = K - j0 - nb
+                # trailing update A22 -= V Wp^T + Wp V^T, both triangles: 4 nb flops per entry
+                trail_f += 4.0 * nb * n2 * n2
+                for i in range(nb):
+                    n1 = K - (j0 + i) - 1
+                    # y = A22 v plus the 2i panel dots: each operand read once
+                    symv_b += 8.0 * (n1 * n1 + 2 * i * n1)
+                    # w and the column update: y, 2i panel entries, v, column j+1 per row; Wp, W writes
+                    upd_b += 8.0 * n1 * (2 * i + 6)
+        out["trd_symv"] = ("hbm", symv_b / n_cols, "GB/s")
+        out["trd_update"] = ("hbm", upd_b / n_cols, "GB/s")
+        out["trd_trail"] = ("alu", trail_f / npan, "TFLOP/s")
+    # Jacobi blocks: counted with the 10 K^3 eigen-decomposition convention
+    for kmax, name in ((16, "cone_jacobi16"), (32, "cone_jacobi32"), (64, "cone_jacobi64"), (96, "cone_jacobi96")):
+        lo = {16: 0, 32: 16, 64: 32, 96: 64}[kmax]
+        out[name] = ("alu", sum(10.0 * k ** 3 for k in small if lo < k <= kmax), "TFLOP/s")
+    # scatter H^T(s+z+v): read s,z,v (3 ns doubles) + slot ids + x, c, pinv; write hsum, q
+    out["r0_scatter"] = ("hbm", 8.0 * 3 * ns + 4.0 * ns + 4.0 * (nE + 1) + 8.0 * 3 * nE + 8.0 * 2 * nE, "GB/s")
+    return out
 
 
 def main():
@@ -81,22 +111,35 @@ def main():
     print(f"[bench] workload: {inst.name}, p={len(sizes)}, max clique {max(sizes)}, "
           f"generation {gen_s:.1f}s", file=sys.stderr, flush=True)
 
+    # timed region: the iteration replayed from a captured HIP graph
     t0 = time.perf_counter()
-    solver = cdcs.Solver(inst, timing=1)
+    solver = cdcs.Solver(inst, use_graph=1)
     setup_s = time.perf_counter() - t0
     dims = solver.dims()
     print(f"[bench] setup {setup_s:.2f}s dims(nE, ns, m, p)={dims}", file=sys.stderr, flush=True)
-
     solver.iterate(args.warmup)
-    solver.reset_phase_times()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = solver.iterate(args.steps)
+    solver.iterate(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    phases = solver.phase_times()
     its = args.steps / dt
-    print(f"[bench] {args.steps} iterations in {dt:.3f}s -> {its:.1f} it/s", file=sys.stderr, flush=True)
+    print(f"[bench] {args.steps} iterations in {dt:.3f}s -> {its:.1f} it/s (graph replay)", file=sys.stderr, flush=True)
+    solver.close()
+
+    # per-kernel times: the same iterations launched one by one with a HIP
+    # event pair around every launch on the stream it runs on
+    timed = cdcs.Solver(inst, timing=1)
+    timed.iterate(args.warmup)
+    timed.reset_phase_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    timed.iterate(args.steps)
+    torch.cuda.synchronize()
+    dt_ev = time.perf_counter() - t0
+    phases = timed.phase_times()
+    timed.close()
+    print(f"[bench] event-timed pass: {1e3 * dt_ev / args.steps:.2f} ms/iteration", file=sys.stderr, flush=True)
 
     # dominant kernel and its roofline position (per-launch averages from HIP events)
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()}
@@ -114,12 +157,14 @@ def main():
             peak = PEAK_HBM_GBS
         roof = {"kernel": dom, "bound": bound, "achieved": round(ach, 4), "peak": peak, "unit": unit,
                 "frac": round(ach / peak, 6), "traffic": None,
-                "work_per_launch": amount, "avg_launch_ms": round(per_launch[dom], 4)}
+                "work_per_launch": amount, "avg_launch_ms": round(per_launch[dom], 5),
+                "launches_per_step": phases[dom][1] / args.steps,
+                "ms_per_step_in_kernel": round(phases[dom][0] / args.steps, 4)}
 
     tol = None
     if not args.no_solve:
         import threading
-        fresh = cdcs.Solver(inst, check_every=10)
+        fresh = cdcs.Solver(inst, check_every=10, use_graph=1)
         torch.cuda.synchronize()
         box = {}
         t0 = time.perf_counter()
@@ -176,7 +221,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "time_to_1e-4": tol,
-        "phases_ms_per_launch": {k: round(v, 4) for k, v in per_launch.items() if phases[k][1]},
+        "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1]},
+        "event_timed_ms_per_step": round(1e3 * dt_ev / args.steps, 4),
     }
     print(json.dumps(out))
 

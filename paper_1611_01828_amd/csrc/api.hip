@@ -67,13 +67,15 @@ int set_error(int code, const std::string& msg) {
 
 enum Phase {
   PH_R0 = 0, PH_SPMV_A, PH_TRSV, PH_SPMV_AT, PH_SCALAR1, PH_UPDATE_E, PH_UPDATE_R,
-  PH_CONE16, PH_CONE32, PH_CONE64, PH_CONE96, PH_LG_GATHER, PH_LG_TRIDIAG, PH_LG_EIG, PH_LG_BACKTRANS,
-  PH_LG_RECON, PH_LG_PARTIALS, PH_SCALAR2, kNumPhases
+  PH_CONE16, PH_CONE32, PH_CONE64, PH_CONE96, PH_LG_GATHER, PH_LG_TRD_SYMV, PH_LG_TRD_UPDATE, PH_LG_TRD_TRAIL,
+  PH_LG_TRD_TAIL, PH_LG_EIG, PH_LG_BACKTRANS, PH_LG_RECON, PH_LG_PARTIALS, PH_SCALAR2, kNumPhases
 };
 const char* kPhaseNames[kNumPhases] = {
     "r0_scatter", "spmv_A", "trsv", "spmv_At", "scalar1", "update_x", "update_y",
-    "cone_jacobi16", "cone_jacobi32", "cone_jacobi64", "cone_jacobi96", "large_gather", "large_tridiag",
-    "large_eig", "large_backtrans", "large_recon", "large_partials", "scalar2"};
+    "cone_jacobi16", "cone_jacobi32", "cone_jacobi64", "cone_jacobi96", "large_gather", "trd_symv",
+    "trd_update", "trd_trail", "trd_tail", "large_eig", "large_backtrans", "large_recon", "large_partials", "scalar2"};
+// phase of each large-clique step (the tridiagonalisation is timed per launch kind)
+const int kLargeStepPhase[kLargeSteps] = {PH_LG_GATHER, -1, PH_LG_EIG, PH_LG_BACKTRANS, PH_LG_RECON, PH_LG_PARTIALS};
 
 }  // namespace
 
@@ -99,6 +101,7 @@ struct cdcs_handle {
   // timing
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   std::vector<std::pair<int, size_t>> ev_used;   // (phase, pool index) since last harvest
+  size_t ev_open = 0;                             // timers begun and not yet ended
   double phase_ms[kNumPhases] = {};
   int64_t phase_n[kNumPhases] = {};
   // graphs
@@ -159,6 +162,26 @@ int bucket_of(int K) {
 }
 
 // record a phase launch between two events when timing is on
+// event pair from the pool, start recorded on s
+size_t timer_begin(cdcs_handle* h, hipStream_t s) {
+  const size_t slot = h->ev_used.size() + h->ev_open;
+  while (slot >= h->ev_pool.size()) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    h->ev_pool.push_back({a, b});
+  }
+  ++h->ev_open;
+  (void)hipEventRecord(h->ev_pool[slot].first, s);
+  return slot;
+}
+
+void timer_end(cdcs_handle* h, size_t slot, int ph, hipStream_t s) {
+  (void)hipEventRecord(h->ev_pool[slot].second, s);
+  --h->ev_open;
+  h->ev_used.push_back({ph, slot});
+}
+
 struct PhaseTimer {
   cdcs_handle* h;
   int ph;
@@ -166,21 +189,26 @@ struct PhaseTimer {
   bool on;
   hipStream_t sm;
   PhaseTimer(cdcs_handle* hh, int p, hipStream_t s = nullptr)
-      : h(hh), ph(p), on(hh->set.timing != 0), sm(s ? s : hh->stream) {
-    if (!on) return;
-    if (h->ev_used.size() >= h->ev_pool.size()) {
-      hipEvent_t a, b;
-      (void)hipEventCreate(&a);
-      (void)hipEventCreate(&b);
-      h->ev_pool.push_back({a, b});
-    }
-    slot = h->ev_used.size();
-    (void)hipEventRecord(h->ev_pool[slot].first, sm);
+      : h(hh), ph(p), on(hh->set.timing != 0 && p >= 0), sm(s ? s : hh->stream) {
+    if (on) slot = timer_begin(h, sm);
   }
   ~PhaseTimer() {
-    if (!on) return;
-    (void)hipEventRecord(h->ev_pool[slot].second, sm);
-    h->ev_used.push_back({ph, slot});
+    if (on) timer_end(h, slot, ph, sm);
+  }
+};
+
+// times every launch of the tridiagonalisation step in its own phase
+struct TrdTimer {
+  cdcs_handle* h;
+  hipStream_t s;
+  size_t slot;
+  static void before(void* c, int) {
+    auto* t = static_cast<TrdTimer*>(c);
+    t->slot = timer_begin(t->h, t->s);
+  }
+  static void after(void* c, int kind) {
+    auto* t = static_cast<TrdTimer*>(c);
+    timer_end(t->h, t->slot, PH_LG_TRD_SYMV + kind, t->s);
   }
 };
 
@@ -214,11 +242,15 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
     HIPCHK(hipEventRecord(h->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(lst, h->ev_fork, 0));
   }
-  if (h->ntasks[4])
+  if (h->ntasks[4]) {
+    TrdTimer tt{h, lst, 0};
+    const LaunchHook hook{&TrdTimer::before, &TrdTimer::after, &tt};
     for (int step = 0; step < kLargeSteps; ++step) {
-      PhaseTimer t(h, PH_LG_GATHER + step, lst);
-      launch_cone_large_step(d, h->tasks[4], h->ntasks[4], h->kmax_large, step, lst);
+      PhaseTimer t(h, kLargeStepPhase[step], lst);
+      launch_cone_large_step(d, h->tasks[4], h->ntasks[4], h->kmax_large, h->large_sizes.data(), step, lst,
+                             h->set.timing ? &hook : nullptr);
     }
+  }
   for (int bk = 0; bk < 4; ++bk)
     if (h->ntasks[bk]) {
       PhaseTimer t(h, PH_CONE16 + bk);
@@ -491,7 +523,9 @@ int pack_and_upload(cdcs_handle* h) {
     btot += large_work_size((int)K);
   }
   boff.push_back(btot);
-  if ((rc = dev_zeros(h, &d.big_work, (size_t)btot)) || (rc = dev_upload(h, (int64_t**)&d.big_off, boff))) return rc;
+  if ((rc = dev_zeros(h, &d.big_work, (size_t)btot)) || (rc = dev_upload(h, (int64_t**)&d.big_off, boff)) ||
+      (rc = dev_upload(h, (int32_t**)&d.big_size, h->large_sizes)))
+    return rc;
   // scalars and status
   std::vector<double> sc((size_t)B * kNsc, 0.0);
   for (int32_t i = 0; i < B; ++i) {
@@ -1150,6 +1184,7 @@ int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets
     if (sizes[k] < 1 || sizes[k] > 1024 || offsets[k] < 0) return set_error(CDCS_E_ARG, "block size must be 1..1024");
     bk[bucket_of(sizes[k])].push_back(k);
   }
+  std::stable_sort(bk[4].begin(), bk[4].end(), [&](int32_t x, int32_t y) { return sizes[x] > sizes[y]; });
   for (int32_t k : bk[4]) {
     large_sizes.push_back(sizes[k]);
     kmax_large = std::max(kmax_large, sizes[k]);
@@ -1173,7 +1208,7 @@ int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets
     return 0;
   };
   int rc = 0;
-  void *dsz, *doff, *dtask[5], *dwork = nullptr, *dwoff = nullptr;
+  void *dsz, *doff, *dtask[5], *dwork = nullptr, *dwoff = nullptr, *dlsz = nullptr;
   auto cleanup = [&]() {
     for (void* p : tmp) (void)hipFree(p);
   };
@@ -1187,7 +1222,8 @@ int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets
       return rc;
     }
   if (!bk[4].empty()) {
-    if ((rc = up(nullptr, (size_t)wtot * 8, &dwork)) || (rc = up(woff.data(), woff.size() * 8, &dwoff))) {
+    if ((rc = up(nullptr, (size_t)wtot * 8, &dwork)) || (rc = up(woff.data(), woff.size() * 8, &dwoff)) ||
+        (rc = up(large_sizes.data(), large_sizes.size() * 4, &dlsz))) {
       cleanup();
       return rc;
     }
@@ -1197,7 +1233,7 @@ int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets
     launch_psd_project((int32_t*)dsz, (int64_t*)doff, (int32_t*)dtask[b], (int32_t)bk[b].size(), kmaxs[b], in, out,
                        st);
   if (!bk[4].empty())
-    launch_psd_project_large((int32_t*)dsz, (int64_t*)doff, (int32_t*)dtask[4], large_sizes.data(),
+    launch_psd_project_large((int32_t*)dsz, (int64_t*)doff, (int32_t*)dtask[4], (int32_t*)dlsz, large_sizes.data(),
                              (int32_t)bk[4].size(), kmax_large, in, out, (double*)dwork, (int64_t*)dwoff, st);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);

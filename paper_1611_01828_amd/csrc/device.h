@@ -104,6 +104,7 @@ struct DevPlan {
   // large-clique workspace
   double* big_work;
   const int64_t* big_off;     // per large task: offset into big_work
+  const int32_t* big_size;    // per large task: clique order (tasks sorted by it, descending)
 };
 
 // doubles of workspace one large-clique task needs (matrix, eigenvectors,
@@ -151,13 +152,23 @@ void launch_scalar2(const DevPlan& d, double eps_tol, int32_t max_iter, int32_t 
 void launch_cone_jacobi(const DevPlan& d, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st);
 // large cliques: gather, tridiag, eig, backtrans, recon, partials
 constexpr int kLargeSteps = 6;
-void launch_cone_large_step(const DevPlan& d, const int32_t* tasks, int32_t ntask, int32_t kmax, int step,
-                            hipStream_t st);
+// called around every launch of the tridiagonalisation step (kind 0 symv,
+// 1 update, 2 trailing update, 3 tail in LDS), e.g. to time them
+struct LaunchHook {
+  void (*before)(void* ctx, int kind);
+  void (*after)(void* ctx, int kind);
+  void* ctx;
+};
+// host_sizes: the tasks' clique orders on the host, sorted descending
+void launch_cone_large_step(const DevPlan& d, const int32_t* tasks, int32_t ntask, int32_t kmax,
+                            const int32_t* host_sizes, int step, hipStream_t st, const LaunchHook* hook = nullptr);
 // stand-alone projection of packed blocks
 void launch_psd_project(const int32_t* sizes, const int64_t* offs, const int32_t* tasks, int32_t ntask,
                         int kmax, const double* in, double* out, hipStream_t st);
+// tasks sorted by block order, descending; task_sizes (device) and
+// host_sizes (host) hold those orders
 void launch_psd_project_large(const int32_t* sizes, const int64_t* offs, const int32_t* tasks,
-                              const int32_t* host_sizes, int32_t ntask, int32_t kmax, const double* in,
-                              double* out, double* work, const int64_t* work_off, hipStream_t st);
+                              const int32_t* task_sizes, const int32_t* host_sizes, int32_t ntask, int32_t kmax,
+                              const double* in, double* out, double* work, const int64_t* work_off, hipStream_t st);
 
 }  // namespace cdcs

@@ -92,6 +92,7 @@ struct LargeArgs {
   // both
   double* work;
   const int64_t* woff;        // per task
+  const int32_t* tsize;       // per task: order K of its block
 };
 
 template <bool ADMM>
@@ -165,62 +166,129 @@ __global__ __launch_bounds__(256) void k_large_gather(LargeArgs a) {
 //    leading dimension, zero padding rows, v zero outside its support).
 // ---------------------------------------------------------------------------
 constexpr int kSymvCols = 32;   // columns per symv workgroup (4 waves x 8)
-constexpr int kUpdRows = 64;    // rows per update workgroup (one wave)
+constexpr int kSymvRows = 256;  // rows per symv workgroup (2 steps of 128 per lane pair)
+constexpr int kMaxRB = 1024 / kSymvRows;
+constexpr int kUpdRows = 64;    // rows per update workgroup (4 waves split the panel sums)
+
+constexpr int kMaxCB = (1024 + 2 * kNB + kSymvCols - 1) / kSymvCols;   // symv column chunks
 
 struct TrdBufs {
-  double* V;    // ld x kNB reflectors of the panel
-  double* Wp;   // ld x kNB
-  double* y;    // ld      A22 v
-  double* t;    // 2 kNB   t1, t2
-  double* yv;   // per symv chunk share of y^T v
+  double* V;       // ld x kNB reflectors of the panel
+  double* Wp;      // ld x kNB
+  double* ypart;   // kMaxRB x ld   row-block partial sums of A22 v
+  double* tpart;   // kMaxRB x 2 kNB partial panel dots t1, t2
+  double* yvp;     // kMaxRB x kMaxCB  shares of y^T v per symv workgroup
+  double* sspart;  // 1024 / kUpdRows  shares of ||x||^2 of the next column per update workgroup
+  double* scl;     // 1      v = x / (alpha - beta) below row j + 1
 };
 
 __device__ __forceinline__ TrdBufs trd_bufs(const Ws& w, int ld) {
   TrdBufs b;
   b.V = w.S;
   b.Wp = w.S + (size_t)ld * kNB;
-  b.y = w.S + (size_t)2 * ld * kNB;
-  b.t = b.y + ld;
-  b.yv = b.t + 2 * kNB;
+  b.ypart = w.S + (size_t)2 * ld * kNB;
+  b.tpart = b.ypart + (size_t)kMaxRB * ld;
+  b.yvp = b.tpart + kMaxRB * 2 * kNB;
+  b.sspart = b.yvp + kMaxRB * kMaxCB;
+  b.scl = b.sspart + 1024 / kUpdRows;
   return b;
+}
+
+// Once the trailing matrix has at most kTail columns it fits in LDS, and one
+// workgroup per task finishes the reduction there (k_trd_tail).  The panel
+// launches cover columns [0, trd_tail_start(K)), whole panels only.
+constexpr int kTail = 128;
+__host__ __device__ __forceinline__ int trd_tail_start(int K) {
+  return (K > kTail) ? ((K - kTail + kNB - 1) / kNB) * kNB : 0;
 }
 
 // column j = p kNB + i of a task with K vertices, nb = columns of its panel
 __device__ __forceinline__ bool trd_col(int K, int p, int i, int& j, int& nb) {
   const int j0 = p * kNB;
-  if (j0 >= K - 2) return false;
+  if (j0 >= trd_tail_start(K)) return false;
   nb = min(kNB, K - 2 - j0);
   if (i >= nb) return false;
   j = j0 + i;
   return true;
 }
 
+// rows of the symv: from r0 = (j + 1) rounded down to even, in blocks of kSymvRows
+__device__ __forceinline__ int trd_r0(int j) { return (j + 1) & ~1; }
+__device__ __forceinline__ int trd_nrb(int j, int ld) { return (ld - trd_r0(j) + kSymvRows - 1) / kSymvRows; }
+
+// The tridiagonalisation kernels only read and write the task's workspace,
+// so they skip the frozen-instance test of task_info (a frozen instance's
+// result is never reconstructed) and read the task's order from tsize: each
+// of these launches is short, and every dependent global round trip before
+// the first useful load shows in its duration.  For the same reason both
+// kernels issue all their global loads before the first barrier.
 template <bool ADMM>
-__global__ __launch_bounds__(256) void k_trd_symv(LargeArgs a, int p, int i) {
+__global__ __launch_bounds__(256) void k_trd_symv(LargeArgs a, int p, int i, int ncy) {
   __shared__ __align__(16) double vbuf[1024];
   __shared__ double red[256 / 64 + 1];
   __shared__ double part[4];
-  int K;
-  int64_t base;
-  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  const int K = a.tsize[blockIdx.x];
   int j, nb;
   if (!trd_col(K, p, i, j, nb)) return;
-  const int ncol = K - j - 1, nall = ncol + 2 * i;
-  const int cbase = blockIdx.y * kSymvCols;
-  if (cbase >= nall) return;
-  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const int ld = lead_dim(K);
+  const int ncol = K - j - 1, nall = ncol + 2 * i;
+  const int cb = blockIdx.y % ncy, rb = blockIdx.y / ncy;
+  const int cbase = cb * kSymvCols;
+  if (cbase >= nall || rb >= trd_nrb(j, ld)) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const TrdBufs b = trd_bufs(w, ld);
   const double* W = w.W;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  // reflector of column j (every workgroup forms the same one)
-  double ss = 0.0;
-  for (int r = j + 2 + tid; r < K; r += 256) {
-    const double x = W[(size_t)j * ld + r];
-    ss += x * x;
+  const bool lead = blockIdx.y == 0;
+  // (1) this wave's operands: columns cbase + 8 wid + u of
+  //     [A22 | Wp(:, 0:i) | V(:, 0:i)] on rows rbase + [0, kSymvRows); W, V
+  //     and Wp live in one workspace, every column addressed by its offset
+  //     from W (V = W + 2 ld^2, Wp = V + kNB ld).  They do not depend on v.
+  const int rbase = trd_r0(j) + rb * kSymvRows;
+  const int cg = cbase + wid * 8;
+  int coff[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int q = min(cg + u, nall - 1);
+    coff[u] = (q < ncol) ? (j + 1 + q) * ld
+                         : 2 * ld * ld + ((q < ncol + i) ? (kNB + q - ncol) * ld : (q - ncol - i) * ld);
   }
-  ss = block_sum<256>(ss, red);
+  constexpr int NK = kSymvRows / 128;
+  double2 av[NK][8];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int rr = min(rbase + 2 * lane + 128 * k, ld - 2);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) av[k][u] = *reinterpret_cast<const double2*>(W + coff[u] + rr);
+  }
+  // (2) column j: this workgroup's rows and columns of v, and ||x||^2 for
+  //     x = A(j+1:K, j) (left in shares by the update of column j - 1, or
+  //     summed here at the first column of a panel)
   const double alpha = W[(size_t)j * ld + j + 1];
+  const double djj = W[(size_t)j * ld + j];
+  const int rown = rbase + tid;
+  const double xrow = W[(size_t)j * ld + min(rown, K - 1)];
+  double xcol[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) xcol[u] = W[(size_t)j * ld + min(j + 1 + cg + u, K - 1)];
+  double ss = 0.0;
+  if (i == 0) {
+    for (int r = j + 2 + tid; r < K; r += 256) {
+      const double x = W[(size_t)j * ld + r];
+      ss += x * x;
+    }
+  }
+  if (i == 0) {
+    ss = block_sum<256>(ss, red);
+  } else {
+    // every wave sums the shares itself: one load per lane, no loop of
+    // dependent loads
+    const int nuc = (ld + kUpdRows - 1) / kUpdRows;
+    const double t = b.sspart[min(lane, nuc - 1)];
+    ss = wave_sum(lane < nuc ? t : 0.0);
+  }
+  // (3) reflector H = I - tau v v^T with H x = beta e_1 (every workgroup
+  //     forms the same one)
   double beta, tu, scale;
   if (ss == 0.0) {
     beta = alpha;
@@ -231,126 +299,164 @@ __global__ __launch_bounds__(256) void k_trd_symv(LargeArgs a, int p, int i) {
     tu = (beta - alpha) / beta;
     scale = 1.0 / (alpha - beta);
   }
-  for (int r = tid; r < ld; r += 256) {
-    double vr = 0.0;
-    if (r == j + 1) vr = 1.0;
-    else if (r > j + 1 && r < K) vr = W[(size_t)j * ld + r] * scale;
-    vbuf[r] = vr;
-    if (blockIdx.y == 0) b.V[(size_t)i * ld + r] = vr;
-  }
-  if (blockIdx.y == 0 && tid == 0) {
-    w.d[j] = W[(size_t)j * ld + j];
+  auto vof = [&](int r, double x) { return (r == j + 1) ? 1.0 : ((r > j + 1 && r < K) ? x * scale : 0.0); };
+  if (rown < ld) vbuf[rown] = vof(rown, xrow);
+  if (lead && tid == 0) {   // V(:, i) itself is written by the update launch
+    w.d[j] = djj;
     w.e[j] = beta;
     w.tau[j] = tu;
+    b.scl[0] = scale;
   }
   __syncthreads();
-  // columns cbase + 8 wid + u of [A22 | Wp(:, 0:i) | V(:, 0:i)]; W, V and Wp
-  // live in one workspace, every column addressed by its offset from W
-  // (V = W + 2 ld^2, Wp = V + kNB ld)
-  const int r0 = (j + 1) & ~1;
-  const int nk = (ld - r0 + 127) / 128;
-  const int cg = cbase + wid * 8;
   double yv = 0.0;
   if (cg < nall) {
-    int coff[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int q = min(cg + u, nall - 1);
-      coff[u] = (q < ncol) ? (j + 1 + q) * ld
-                           : 2 * ld * ld + ((q < ncol + i) ? (kNB + q - ncol) * ld : (q - ncol - i) * ld);
-    }
+    // (4) y = A22 v and the panel dots on this block of rows
     double acc[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-    for (int k = 0; k < nk; ++k) {
-      const int r = r0 + 2 * lane + 128 * k;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int r = rbase + 2 * lane + 128 * k;
       const int rr = min(r, ld - 2);
       const double2 vv = *reinterpret_cast<const double2*>(vbuf + rr);
       const double m = (r < ld) ? 1.0 : 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const double2 av = *reinterpret_cast<const double2*>(W + coff[u] + rr);
-        acc[u] += m * (av.x * vv.x + av.y * vv.y);
-      }
+      for (int u = 0; u < 8; ++u) acc[u] += m * (av[k][u].x * vv.x + av[k][u].y * vv.y);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const double sum = wave_sum(acc[u]);
       const int q = cg + u;
-      if (q < ncol) {
-        if (lane == 0) b.y[j + 1 + q] = sum;
-        yv += sum * vbuf[j + 1 + q];
-      } else if (q < nall && lane == 0) {
-        if (q < ncol + i) b.t[q - ncol] = sum;
-        else b.t[kNB + q - ncol - i] = sum;
+      if (q < ncol) yv += sum * vof(j + 1 + q, xcol[u]);
+      if (lane == 0 && q < nall) {
+        if (q < ncol) b.ypart[(size_t)rb * ld + j + 1 + q] = sum;
+        else if (q < ncol + i) b.tpart[rb * 2 * kNB + q - ncol] = sum;
+        else b.tpart[rb * 2 * kNB + kNB + q - ncol - i] = sum;
       }
     }
   }
   if (lane == 0) part[wid] = yv;
   __syncthreads();
-  if (tid == 0) b.yv[blockIdx.y] = (part[0] + part[1]) + (part[2] + part[3]);
+  if (tid == 0) b.yvp[rb * kMaxCB + cb] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 template <bool ADMM>
-__global__ __launch_bounds__(kUpdRows) void k_trd_update(LargeArgs a, int p, int i) {
+__global__ __launch_bounds__(256) void k_trd_update(LargeArgs a, int p, int i) {
   __shared__ double t1[kNB], t2[kNB], cvj[kNB + 1], cwj[kNB + 1];
-  int K;
-  int64_t base;
-  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  __shared__ double red[256 / 64 + 1];
+  __shared__ double py[4][kUpdRows], pv[4][kUpdRows];
+  const int K = a.tsize[blockIdx.x];
   int j, nb;
   if (!trd_col(K, p, i, j, nb)) return;
   const int ld = lead_dim(K);
-  const int r = blockIdx.y * kUpdRows + threadIdx.x;
   if (blockIdx.y * kUpdRows >= ld) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const TrdBufs b = trd_bufs(w, ld);
   const int tid = threadIdx.x;
   const bool next = i + 1 < nb;   // column j + 1 belongs to this panel
   const int jc = j + 1;
-  if (tid < i) {
-    t1[tid] = b.t[tid];
-    t2[tid] = b.t[kNB + tid];
+  const int nrb = trd_nrb(j, ld);
+  const int nch = (K - j - 1 + 2 * i + kSymvCols - 1) / kSymvCols;
+  // rows blockIdx.y * 64 + (tid & 63); the four waves split the panel sums
+  const int rl = tid & 63, g = tid >> 6;
+  const int r = blockIdx.y * kUpdRows + rl;
+  const int rcl = min(r, ld - 1);
+  const bool live = r > j && r < K;
+  // global loads first
+  constexpr int NM = kNB / 4;
+  double Vr[NM], Wr[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    const int l = g + 4 * m;
+    if (l < i) {
+      Vr[m] = b.V[(size_t)l * ld + rcl];
+      Wr[m] = b.Wp[(size_t)l * ld + rcl];
+    } else {
+      Vr[m] = 0.0;
+      Wr[m] = 0.0;
+    }
   }
-  if (tid <= i) {
+  // fixed-count loops with clamped indices: the loads issue together
+  double yrow = 0.0, yjc = 0.0;
+#pragma unroll
+  for (int q = 0; q < kMaxRB; ++q) {
+    const size_t o = (size_t)min(q, nrb - 1) * ld;
+    const double a0 = b.ypart[o + rcl], a1 = b.ypart[o + jc];
+    yrow += (q < nrb) ? a0 : 0.0;
+    yjc += (q < nrb) ? a1 : 0.0;
+  }
+  const double wjr = w.W[(size_t)jc * ld + rcl];
+  const double xjr = w.W[(size_t)j * ld + rcl];
+  const double scale = b.scl[0];
+  double yv = 0.0;
+  if (tid < nrb * nch) yv = b.yvp[(tid / nch) * kMaxCB + tid % nch];
+  if (tid < i) {
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxRB; ++q) {
+      const int o = min(q, nrb - 1) * 2 * kNB + tid;
+      const double a1 = b.tpart[o], a2 = b.tpart[o + kNB];
+      s1 += (q < nrb) ? a1 : 0.0;
+      s2 += (q < nrb) ? a2 : 0.0;
+    }
+    t1[tid] = s1;
+    t2[tid] = s2;
+  }
+  if (tid < i) {
     cvj[tid] = b.V[(size_t)tid * ld + jc];
     cwj[tid] = b.Wp[(size_t)tid * ld + jc];
   }
-  __syncthreads();
-  const int ncol = K - j - 1, nall = ncol + 2 * i;
-  const int nch = (nall + kSymvCols - 1) / kSymvCols;
-  double yv = 0.0;
-  for (int c = 0; c < nch; ++c) yv += b.yv[c];
+  if (tid == i) cvj[i] = 1.0;   // v(j + 1) = 1
+  // y^T v (every workgroup forms the same sum); the barriers of the block
+  // sum also publish t1, t2, cvj, cwj
+  yv = block_sum<256>(yv, red);
   double tt = 0.0;
   for (int l = 0; l < i; ++l) tt += t1[l] * t2[l];
   const double tu = w.tau[j];
   const double al = -0.5 * tu * (tu * (yv - 2.0 * tt));
-  // Wp(jc, i), computed by every workgroup the way the owner of row jc does
-  double wpj = 0.0;
+  // Wp(jc, i) as every workgroup forms it
+  double wpj;
   {
-    double y = b.y[jc];
+    double y = yjc;
     for (int l = 0; l < i; ++l) y -= cvj[l] * t1[l] + cwj[l] * t2[l];
     wpj = tu * y + al * cvj[i];
   }
-  if (r >= ld) return;   // whole-lane exits; no barriers below
-  double wr = 0.0;
-  if (r > j && r < K) {
-    double y = b.y[r];
-    double v = next ? w.W[(size_t)jc * ld + r] : 0.0;
-#pragma unroll 8
-    for (int l = 0; l < i; ++l) {
-      const double Vr = b.V[(size_t)l * ld + r], Wr = b.Wp[(size_t)l * ld + r];
-      y -= Vr * t1[l] + Wr * t2[l];
-      v -= Vr * cwj[l] + Wr * cvj[l];
+  double sy = 0.0, sv = 0.0;
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    const int l = g + 4 * m;
+    if (l < i) {
+      sy += Vr[m] * t1[l] + Wr[m] * t2[l];
+      sv += Vr[m] * cwj[l] + Wr[m] * cvj[l];
     }
-    const double vi = b.V[(size_t)i * ld + r];
-    wr = tu * y + al * vi;
-    if (next && r >= jc) {
-      v -= vi * wpj + wr * cvj[i];
-      w.W[(size_t)jc * ld + r] = v;
-    }
-    if (r >= j + 2) w.W[(size_t)j * ld + r] = vi;   // Householder vector below the subdiagonal
   }
-  b.Wp[(size_t)i * ld + r] = wr;
+  py[g][rl] = sy;
+  pv[g][rl] = sv;
+  __syncthreads();
+  double xx = 0.0;   // share of ||A(jc+2:K, jc)||^2 for the next reflector
+  if (g == 0 && r < ld) {
+    // v of column j on this row: V(:, i) and the Householder vector below
+    // the subdiagonal
+    const double vir = (r == j + 1) ? 1.0 : ((r > j + 1 && r < K) ? xjr * scale : 0.0);
+    b.V[(size_t)i * ld + r] = vir;
+    double wr = 0.0;
+    if (live) {
+      const double y = yrow - ((py[0][rl] + py[1][rl]) + (py[2][rl] + py[3][rl]));
+      wr = tu * y + al * vir;
+      if (next && r >= jc) {
+        double v = wjr - ((pv[0][rl] + pv[1][rl]) + (pv[2][rl] + pv[3][rl]));
+        v -= vir * wpj + wr * cvj[i];
+        w.W[(size_t)jc * ld + r] = v;
+        if (r >= jc + 2) xx = v * v;
+      }
+      if (r >= j + 2) w.W[(size_t)j * ld + r] = vir;   // Householder vector below the subdiagonal
+    }
+    b.Wp[(size_t)i * ld + r] = wr;
+  }
+  if (next) {
+    xx = wave_sum(xx);   // wave 0 holds the workgroup's 64 rows
+    if (tid == 0) b.sspart[blockIdx.y] = xx;
+  }
 }
 
 template <bool ADMM>
@@ -360,12 +466,10 @@ __global__ __launch_bounds__(kTT) void k_trd_trail(LargeArgs a, int p) {
   double(*pr_w)[128] = reinterpret_cast<double(*)[128]>(stage + kNB * 128);
   double(*pc_v)[64] = reinterpret_cast<double(*)[64]>(stage + 2 * kNB * 128);
   double(*pc_w)[64] = reinterpret_cast<double(*)[64]>(stage + 2 * kNB * 128 + kNB * 64);
-  int K;
-  int64_t base;
-  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  const int K = a.tsize[blockIdx.x];
   const int j0 = p * kNB;
-  if (j0 >= K - 2) return;
-  const int nb = min(kNB, K - 2 - j0);
+  if (j0 >= trd_tail_start(K)) return;
+  const int nb = kNB;
   const int jn = j0 + nb, n2 = K - jn;
   const int ntr = (n2 + 127) / 128, ntc = (n2 + 63) / 64;
   const int tile = blockIdx.y;
@@ -420,17 +524,89 @@ __global__ __launch_bounds__(kTT) void k_trd_trail(LargeArgs a, int p) {
       if (r < K && c < K) W[(size_t)c * ld + r] -= acc[u][q];
     }
   }
-  if (jn == K - 2) {
-    // the last panel leaves the trailing 2 x 2 block, which completes T
-    __syncthreads();
-    if (tid == 0) {
-      w.d[K - 2] = W[(size_t)(K - 2) * ld + K - 2];
-      w.d[K - 1] = W[(size_t)(K - 1) * ld + K - 1];
-      w.e[K - 2] = W[(size_t)(K - 2) * ld + K - 1];
-      w.e[K - 1] = 0.0;
-      w.tau[K - 2] = 0.0;
-      w.tau[K - 1] = 0.0;
+}
+
+// The last columns [j0, K) of a task in LDS (full n x n storage, n <= kTail),
+// reduced column by column: x = A(c+1:n, c) gives the reflector, then
+// p = tau A22 v, w = p - tau/2 (p^T v) v and A22 -= v w^T + w v^T
+// (Golub & Van Loan Algorithm 8.3.1).  Thread (r, h) owns row r and the
+// columns q = h mod kTailG.
+constexpr int kTailT = 1024;
+constexpr int kTailG = kTailT / kTail;
+template <bool ADMM>
+__global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
+  __shared__ double A[kTail * kTail];
+  __shared__ double vb[kTail], wb[kTail], ph[kTailG][kTail];
+  __shared__ double red[kTailT / 64 + 1];
+  const int K = a.tsize[blockIdx.x];
+  const int j0 = trd_tail_start(K), n = K - j0;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int ld = lead_dim(K);
+  double* W = w.W;
+  const int tid = threadIdx.x;
+  const int r = tid & (kTail - 1), h = tid / kTail;
+  for (int idx = tid; idx < n * n; idx += kTailT) {
+    const int c = idx / n, rr = idx - c * n;
+    A[c * n + rr] = W[(size_t)(j0 + c) * ld + j0 + rr];
+  }
+  __syncthreads();
+  for (int c = 0; c < n - 2; ++c) {
+    const int j = j0 + c;
+    double ss = 0.0;
+    if (h == 0 && r >= c + 2 && r < n) ss = A[c * n + r] * A[c * n + r];
+    ss = block_sum<kTailT>(ss, red);
+    const double alpha = A[c * n + c + 1];
+    double beta, tu, scale;
+    if (ss == 0.0) {
+      beta = alpha;
+      tu = 0.0;
+      scale = 0.0;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+      tu = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
     }
+    if (h == 0 && r < n) {
+      const double vr = (r == c + 1) ? 1.0 : ((r > c + 1) ? A[c * n + r] * scale : 0.0);
+      vb[r] = vr;
+      if (r >= c + 2) W[(size_t)j * ld + j0 + r] = vr;   // Householder vector below the subdiagonal
+    }
+    if (tid == 0) {
+      w.d[j] = A[c * n + c];
+      w.e[j] = beta;
+      w.tau[j] = tu;
+    }
+    __syncthreads();
+    // p = tau A22 v on rows and columns > c
+    double acc = 0.0;
+    if (r > c && r < n)
+      for (int q = c + 1 + h; q < n; q += kTailG) acc += A[q * n + r] * vb[q];
+    ph[h][r] = acc;
+    __syncthreads();
+    double pr = 0.0, pv = 0.0;
+    if (h == 0 && r > c && r < n) {
+      double t = 0.0;
+#pragma unroll
+      for (int g = 0; g < kTailG; ++g) t += ph[g][r];
+      pr = tu * t;
+      pv = pr * vb[r];
+    }
+    pv = block_sum<kTailT>(pv, red);
+    if (h == 0 && r < n) wb[r] = (r > c) ? pr - 0.5 * tu * pv * vb[r] : 0.0;
+    __syncthreads();
+    if (r > c && r < n) {
+      const double vr = vb[r], wr = wb[r];
+      for (int q = c + 1 + h; q < n; q += kTailG) A[q * n + r] -= vr * wb[q] + wr * vb[q];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    w.d[K - 2] = A[(n - 2) * n + n - 2];
+    w.d[K - 1] = A[(n - 1) * n + n - 1];
+    w.e[K - 2] = A[(n - 2) * n + n - 1];
+    w.e[K - 1] = 0.0;
+    w.tau[K - 2] = 0.0;
+    w.tau[K - 1] = 0.0;
   }
 }
 
@@ -863,30 +1039,48 @@ __global__ __launch_bounds__(64) void k_large_partials(LargeArgs a) {
 }
 
 template <bool ADMM>
-static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, int step, hipStream_t st) {
+static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, const int32_t* host_sizes, int step,
+                           hipStream_t st, const LaunchHook* hook = nullptr) {
   if (ntask <= 0) return;
   const int rmax = kmax / 2 + 1;
   const int T = (kmax + kTile - 1) / kTile;
   switch (step) {
     case 0: hipLaunchKernelGGL(k_large_gather<ADMM>, dim3(ntask), dim3(256), 0, st, a); break;
     case 1: {
-      // the column steps of all tasks in lockstep; tasks with fewer columns
-      // return at once from launches past their last column
-      const int np = (kmax - 2 + kNB - 1) / kNB;
+      // the panel steps of all tasks in lockstep; tasks are sorted by order
+      // (descending), so the tasks that still have panel p form a prefix;
+      // then one launch finishes every task in LDS
+      auto active = [&](int j0) {
+        int n = 0;
+        while (n < ntask && trd_tail_start(host_sizes[n]) > j0) ++n;
+        return n;
+      };
+      const int np = trd_tail_start(kmax) / kNB;
       const int ldm = (kmax + 7) & ~7;
       for (int p = 0; p < np; ++p) {
-        const int nbm = std::min(kNB, kmax - 2 - p * kNB);
-        for (int i = 0; i < nbm; ++i) {
-          const int nallm = kmax - p * kNB - 1 + i;
-          hipLaunchKernelGGL(k_trd_symv<ADMM>, dim3(ntask, (nallm + kSymvCols - 1) / kSymvCols), dim3(256), 0, st, a,
+        const int na = active(p * kNB);
+        for (int i = 0; i < kNB; ++i) {
+          const int j = p * kNB + i;
+          const int nallm = kmax - j - 1 + 2 * i;
+          const int ncy = (nallm + kSymvCols - 1) / kSymvCols;
+          const int nrbm = (ldm - ((j + 1) & ~1) + kSymvRows - 1) / kSymvRows;
+          if (hook) hook->before(hook->ctx, 0);
+          hipLaunchKernelGGL(k_trd_symv<ADMM>, dim3(na, ncy * nrbm), dim3(256), 0, st, a, p, i, ncy);
+          if (hook) hook->after(hook->ctx, 0);
+          if (hook) hook->before(hook->ctx, 1);
+          hipLaunchKernelGGL(k_trd_update<ADMM>, dim3(na, (ldm + kUpdRows - 1) / kUpdRows), dim3(256), 0, st, a,
                              p, i);
-          hipLaunchKernelGGL(k_trd_update<ADMM>, dim3(ntask, (ldm + kUpdRows - 1) / kUpdRows), dim3(kUpdRows), 0, st,
-                             a, p, i);
+          if (hook) hook->after(hook->ctx, 1);
         }
-        const int n2 = kmax - p * kNB - nbm;
-        hipLaunchKernelGGL(k_trd_trail<ADMM>, dim3(ntask, ((n2 + 127) / 128) * ((n2 + 63) / 64)), dim3(kTT), 0, st,
+        const int n2 = kmax - p * kNB - kNB;
+        if (hook) hook->before(hook->ctx, 2);
+        hipLaunchKernelGGL(k_trd_trail<ADMM>, dim3(na, ((n2 + 127) / 128) * ((n2 + 63) / 64)), dim3(kTT), 0, st,
                            a, p);
+        if (hook) hook->after(hook->ctx, 2);
       }
+      if (hook) hook->before(hook->ctx, 3);
+      hipLaunchKernelGGL(k_trd_tail<ADMM>, dim3(ntask), dim3(kTailT), 0, st, a);
+      if (hook) hook->after(hook->ctx, 3);
       break;
     }
     case 2: hipLaunchKernelGGL(k_large_eig<ADMM>, dim3(ntask), dim3(kLT), 0, st, a); break;
@@ -901,19 +1095,20 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, int 
   }
 }
 
-void launch_cone_large_step(const DevPlan& d, const int32_t* tasks, int32_t ntask, int32_t kmax, int step,
-                            hipStream_t st) {
+void launch_cone_large_step(const DevPlan& d, const int32_t* tasks, int32_t ntask, int32_t kmax,
+                            const int32_t* host_sizes, int step, hipStream_t st, const LaunchHook* hook) {
   LargeArgs a{};
   a.d = d;
   a.tasks = tasks;
   a.work = d.big_work;
   a.woff = d.big_off;
-  run_large_step<true>(a, ntask, kmax, step, st);
+  a.tsize = d.big_size;
+  run_large_step<true>(a, ntask, kmax, host_sizes, step, st, hook);
 }
 
 void launch_psd_project_large(const int32_t* sizes, const int64_t* offs, const int32_t* tasks,
-                              const int32_t* /*host_sizes*/, int32_t ntask, int32_t kmax, const double* in,
-                              double* out, double* work, const int64_t* work_off, hipStream_t st) {
+                              const int32_t* task_sizes, const int32_t* host_sizes, int32_t ntask, int32_t kmax,
+                              const double* in, double* out, double* work, const int64_t* work_off, hipStream_t st) {
   LargeArgs a{};
   a.tasks = tasks;
   a.psizes = sizes;
@@ -922,7 +1117,8 @@ void launch_psd_project_large(const int32_t* sizes, const int64_t* offs, const i
   a.pout = out;
   a.work = work;
   a.woff = work_off;
-  for (int step = 0; step < kLargeSteps; ++step) run_large_step<false>(a, ntask, kmax, step, st);
+  a.tsize = task_sizes;
+  for (int step = 0; step < kLargeSteps; ++step) run_large_step<false>(a, ntask, kmax, host_sizes, step, st);
 }
 
 }  // namespace cdcs
