@@ -550,50 +550,68 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
     A[c * n + rr] = W[(size_t)(j0 + c) * ld + j0 + rr];
   }
   __syncthreads();
+  const int lane = tid & 63;
   for (int c = 0; c < n - 2; ++c) {
     const int j = j0 + c;
-    double ss = 0.0;
-    if (h == 0 && r >= c + 2 && r < n) ss = A[c * n + r] * A[c * n + r];
-    ss = block_sum<kTailT>(ss, red);
-    const double alpha = A[c * n + c + 1];
-    double beta, tu, scale;
-    if (ss == 0.0) {
-      beta = alpha;
-      tu = 0.0;
-      scale = 0.0;
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-      tu = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    if (h == 0 && r < n) {
-      const double vr = (r == c + 1) ? 1.0 : ((r > c + 1) ? A[c * n + r] * scale : 0.0);
-      vb[r] = vr;
-      if (r >= c + 2) W[(size_t)j * ld + j0 + r] = vr;   // Householder vector below the subdiagonal
-    }
-    if (tid == 0) {
-      w.d[j] = A[c * n + c];
-      w.e[j] = beta;
-      w.tau[j] = tu;
+    // (1) wave 0: reflector of column c (rows lane and lane + 64)
+    if (tid < 64) {
+      const int r0 = lane, r1 = lane + 64;
+      const double x0 = (r0 < n) ? A[c * n + r0] : 0.0, x1 = (r1 < n) ? A[c * n + r1] : 0.0;
+      double ss = ((r0 >= c + 2 && r0 < n) ? x0 * x0 : 0.0) + ((r1 >= c + 2 && r1 < n) ? x1 * x1 : 0.0);
+      ss = wave_sum(ss);
+      const double alpha = A[c * n + c + 1];
+      double beta, tu, scale;
+      if (ss == 0.0) {
+        beta = alpha;
+        tu = 0.0;
+        scale = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+        tu = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      const double v0 = (r0 == c + 1) ? 1.0 : ((r0 > c + 1 && r0 < n) ? x0 * scale : 0.0);
+      const double v1 = (r1 == c + 1) ? 1.0 : ((r1 > c + 1 && r1 < n) ? x1 * scale : 0.0);
+      vb[r0] = v0;
+      vb[r1] = v1;
+      if (r0 >= c + 2 && r0 < n) W[(size_t)j * ld + j0 + r0] = v0;   // Householder vector
+      if (r1 >= c + 2 && r1 < n) W[(size_t)j * ld + j0 + r1] = v1;
+      if (lane == 0) {
+        red[0] = tu;
+        w.d[j] = A[c * n + c];
+        w.e[j] = beta;
+        w.tau[j] = tu;
+      }
     }
     __syncthreads();
-    // p = tau A22 v on rows and columns > c
+    const double tu = red[0];
+    // (2) p = tau A22 v on rows and columns > c, column groups in ph
     double acc = 0.0;
     if (r > c && r < n)
       for (int q = c + 1 + h; q < n; q += kTailG) acc += A[q * n + r] * vb[q];
     ph[h][r] = acc;
     __syncthreads();
-    double pr = 0.0, pv = 0.0;
-    if (h == 0 && r > c && r < n) {
-      double t = 0.0;
+    // (3) wave 0: w = p - tau/2 (p^T v) v
+    if (tid < 64) {
+      double pr[2], pv = 0.0;
 #pragma unroll
-      for (int g = 0; g < kTailG; ++g) t += ph[g][r];
-      pr = tu * t;
-      pv = pr * vb[r];
+      for (int u = 0; u < 2; ++u) {
+        const int rr = lane + 64 * u;
+        double t = 0.0;
+#pragma unroll
+        for (int g = 0; g < kTailG; ++g) t += ph[g][rr];
+        pr[u] = (rr > c && rr < n) ? tu * t : 0.0;
+        pv += pr[u] * vb[rr];
+      }
+      pv = wave_sum(pv);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int rr = lane + 64 * u;
+        wb[rr] = (rr > c && rr < n) ? pr[u] - 0.5 * tu * pv * vb[rr] : 0.0;
+      }
     }
-    pv = block_sum<kTailT>(pv, red);
-    if (h == 0 && r < n) wb[r] = (r > c) ? pr - 0.5 * tu * pv * vb[r] : 0.0;
     __syncthreads();
+    // (4) A22 -= v w^T + w v^T
     if (r > c && r < n) {
       const double vr = vb[r], wr = wb[r];
       for (int q = c + 1 + h; q < n; q += kTailG) A[q * n + r] -= vr * wb[q] + wr * vb[q];
