@@ -122,25 +122,55 @@ __device__ __forceinline__ double yvec_of(const LargeArgs& a, int64_t base, int 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// 1. gather (full symmetric, padded rows zeroed)
+// 1. gather (full symmetric, padded rows zeroed): one workgroup per 32 x 32
+//    tile of the lower triangle; the tile is read from the packed slots
+//    column by column and written to both triangles through LDS, so that
+//    every global access is coalesced
 // ---------------------------------------------------------------------------
 template <bool ADMM>
 __global__ __launch_bounds__(256) void k_large_gather(LargeArgs a) {
+  __shared__ double tile[kTile][kTile + 1];   // tile[col][row]
   int K;
   int64_t base;
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  const int T = (K + kTile - 1) / kTile;
+  const int q = blockIdx.y;
+  if (q >= T * (T + 1) / 2) return;
+  int tr = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+  while (tr * (tr + 1) / 2 > q) --tr;
+  while ((tr + 1) * (tr + 2) / 2 <= q) ++tr;
+  const int tc = q - tr * (tr + 1) / 2;
+  const int i0 = tr * kTile, b0 = tc * kTile;   // rows i0.., columns b0.., i0 >= b0
   double* W = a.work + a.woff[blockIdx.x];
   const int ld = lead_dim(K);
-  for (int b = 0; b < K; ++b) {
-    const int p0 = packed_index(b, b, K);
-    for (int i = b + threadIdx.x; i < ld; i += 256) {
-      double y = 0.0;
-      if (i < K) {
-        y = yvec_of<ADMM>(a, base, p0 + (i - b));
-        if (i != b) y *= kInvSqrt2;
-        W[(size_t)i * ld + b] = y;
-      }
-      W[(size_t)b * ld + i] = y;
+  const int tid = threadIdx.x, il = tid & 31, g = tid >> 5;   // 8 column groups of 4
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int bl = g * 4 + u;
+    const int i = i0 + il, b = b0 + bl;
+    double y = 0.0;
+    if (i < K && b < K && i >= b) {
+      y = yvec_of<ADMM>(a, base, packed_index(i, b, K));
+      if (i != b) y *= kInvSqrt2;
+    }
+    tile[bl][il] = y;
+  }
+  __syncthreads();
+  const bool diag = tr == tc;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    // lower part: W(i, b) for column b, rows i (the mirror inside a diagonal tile)
+    const int bl = g * 4 + u;
+    const int i = i0 + il, b = b0 + bl;
+    if (b < K && i < ld) W[(size_t)b * ld + i] = (diag && il < bl) ? tile[il][bl] : tile[bl][il];
+  }
+  if (!diag) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      // upper part: W(b, i) = W(i, b) for column i, rows b
+      const int rl = g * 4 + u;   // tile row -> column of the upper block
+      const int i = i0 + rl, b = b0 + il;
+      if (i < K) W[(size_t)i * ld + b] = tile[il][rl];
     }
   }
 }
@@ -1063,7 +1093,7 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
   const int rmax = kmax / 2 + 1;
   const int T = (kmax + kTile - 1) / kTile;
   switch (step) {
-    case 0: hipLaunchKernelGGL(k_large_gather<ADMM>, dim3(ntask), dim3(256), 0, st, a); break;
+    case 0: hipLaunchKernelGGL(k_large_gather<ADMM>, dim3(ntask, T * (T + 1) / 2), dim3(256), 0, st, a); break;
     case 1: {
       // the panel steps of all tasks in lockstep; tasks are sorted by order
       // (descending), so the tasks that still have panel p form a prefix;
