@@ -29,7 +29,6 @@ constexpr int kLT = 1024;        // threads of the per-task kernels
 constexpr int kTT = 512;         // threads of the tridiagonalisation kernel
 constexpr int kNB = 32;          // panel width of the tridiagonalisation
 constexpr int kTile = 32;        // reconstruction tile
-constexpr int kBtCols = 16;      // eigenvector columns per back-transform workgroup
 constexpr double kEps = 2.220446049250313e-16;
 constexpr double kSqrt2 = 1.4142135623730951;
 constexpr double kInvSqrt2 = 0.70710678118654752;
@@ -950,35 +949,138 @@ __global__ __launch_bounds__(kLT) void k_large_eig(LargeArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// 4. back-transformation V = Q Z = H_0 H_1 ... H_{K-3} Z
+// 4. back-transformation V = Q Z = H_0 H_1 ... H_{K-3} Z, blocked: the
+//    reflectors of panel p (columns j0 = 32 p ..) form
+//    B_p = H_j0 ... H_j0+31 = I - V_p T_p V_p^T with T_p upper triangular
+//    (the compact WY form, Schreiber & Van Loan; T(i,i) = tau_i,
+//    T(0:i, i) = -tau_i T(0:i, 0:i) V_p(:, 0:i)^T v_i), and
+//    Q Z = B_0 (B_1 (... B_{P-1} Z)).
 // ---------------------------------------------------------------------------
+constexpr int kBtNC = 8;     // eigenvectors per apply workgroup, resident in LDS
+constexpr int kBtCR = 128;   // rows of a staged V panel chunk
+
+// element (row, a) of V_p: v_{j0+a} has 1 on row j0+a+1 and the stored
+// Householder vector below it
+__device__ __forceinline__ double bt_v(const double* W, int ld, int K, int j0, int nbp, int a, int row) {
+  if (a >= nbp || row >= K || row <= j0 + a) return 0.0;
+  return (row == j0 + a + 1) ? 1.0 : W[(size_t)(j0 + a) * ld + row];
+}
+
+__device__ __forceinline__ double* bt_tbuf(const Ws& w) { return w.S; }   // 32 x 32 per panel
+
 template <bool ADMM>
-__global__ __launch_bounds__(kLT) void k_large_backtrans(LargeArgs a) {
-  __shared__ double zc[kBtCols][1024];
+__global__ __launch_bounds__(1024) void k_bt_tfactor(LargeArgs a) {
+  __shared__ double Vc[32][33];
+  __shared__ double G[32][33];
+  __shared__ double Ts[32][33];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  const int P = (K - 2 + kNB - 1) / kNB;
+  const int p = blockIdx.y;
+  if (p >= P) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  if ((int)w.meta[0] == 0) return;
+  const int ld = lead_dim(K);
+  const int j0 = p * kNB, nbp = min(kNB, K - 2 - j0);
+  const int tid = threadIdx.x, ta = tid >> 5, tb = tid & 31;
+  // Gram matrix V_p^T V_p over 32-row chunks staged in LDS
+  double g = 0.0;
+  for (int row0 = j0 + 1; row0 < K; row0 += 32) {
+    Vc[tb][ta] = bt_v(w.W, ld, K, j0, nbp, ta, row0 + tb);   // Vc[row][col]
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < 32; ++rr) g += Vc[rr][ta] * Vc[rr][tb];
+    __syncthreads();
+  }
+  G[ta][tb] = g;
+  __syncthreads();
+  if (tid < 64) {
+    const int k = tid;
+    for (int i = 0; i < kNB; ++i) {
+      const double tu = (i < nbp) ? w.tau[j0 + i] : 0.0;
+      double t = 0.0;
+      if (k < i)
+        for (int m = k; m < i; ++m) t += Ts[k][m] * G[m][i];
+      if (k < 32) Ts[k][i] = (k < i) ? -tu * t : ((k == i) ? tu : 0.0);
+    }
+  }
+  __syncthreads();
+  bt_tbuf(w)[(size_t)p * kNB * kNB + ta * kNB + tb] = Ts[ta][tb];
+}
+
+template <bool ADMM>
+__global__ __launch_bounds__(1024) void k_bt_apply(LargeArgs a) {
+  __shared__ double Zs[kBtNC][1024];
+  __shared__ double Vc[kBtCR][33];
+  __shared__ double Sp[4][32][kBtNC];
+  __shared__ double Sq[32][kBtNC];
+  __shared__ double Ts[32][33];
   int K;
   int64_t base;
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const int r = (int)w.meta[0];
-  const int c0 = blockIdx.y * kBtCols;
+  const int c0 = blockIdx.y * kBtNC;
   if (c0 >= r) return;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;   // one wave per column
-  const int col = c0 + wid;
-  if (col >= r) return;       // whole waves exit; no block barriers below
-  double* z = zc[wid];
-  const double* zg = w.Z + (size_t)col * K;
-  for (int i = lane; i < K; i += 64) z[i] = zg[i];
-  for (int j = K - 3; j >= 0; --j) {
-    const double tu = w.tau[j];
-    if (tu == 0.0) continue;
-    const double* vcol = w.W + (size_t)j * lead_dim(K);   // v_{j+1} = 1, v_i = W[i, j] for i >= j+2
-    double acc = 0.0;
-    for (int i = j + 1 + lane; i < K; i += 64) acc += ((i == j + 1) ? 1.0 : vcol[i]) * z[i];
-    acc = wave_sum(acc) * tu;
-    for (int i = j + 1 + lane; i < K; i += 64) z[i] -= acc * ((i == j + 1) ? 1.0 : vcol[i]);
+  const int nc = min(kBtNC, r - c0);
+  const int ld = lead_dim(K);
+  const int P = (K - 2 + kNB - 1) / kNB;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kBtNC * K; idx += 1024) {
+    const int cl = idx / K, row = idx - cl * K;
+    Zs[cl][row] = (cl < nc) ? w.Z[(size_t)(c0 + cl) * K + row] : 0.0;
   }
-  double* zo = w.Z + (size_t)col * K;
-  for (int i = lane; i < K; i += 64) zo[i] = z[i];
+  const int a1 = tid & 31, cl1 = (tid >> 5) & 7, h1 = tid >> 8;   // pass 1: S(a, cl), row phase h
+  const int rl3 = tid & 127, cl3 = tid >> 7;                        // pass 2: Z(row, cl)
+  for (int p = P - 1; p >= 0; --p) {
+    const int j0 = p * kNB, nbp = min(kNB, K - 2 - j0);
+    Ts[tid >> 5][tid & 31] = bt_tbuf(w)[(size_t)p * kNB * kNB + tid];
+    // pass 1: S = V_p^T Z
+    double sp = 0.0;
+    for (int row0 = j0 + 1; row0 < K; row0 += kBtCR) {
+#pragma unroll
+      for (int q = 0; q < kBtCR * 32 / 1024; ++q) {
+        const int idx = tid + 1024 * q, as = idx / kBtCR, rl = idx - as * kBtCR;
+        Vc[rl][as] = bt_v(w.W, ld, K, j0, nbp, as, row0 + rl);
+      }
+      __syncthreads();
+      const int nr = min(kBtCR, K - row0);
+      for (int rr = h1; rr < nr; rr += 4) sp += Vc[rr][a1] * Zs[cl1][row0 + rr];
+      __syncthreads();
+    }
+    Sp[h1][a1][cl1] = sp;
+    __syncthreads();
+    // S <- T S
+    if (tid < 32 * kBtNC) {
+      const int k = tid & 31, cl = tid >> 5;
+      double t = 0.0;
+      for (int m = k; m < 32; ++m) t += Ts[k][m] * ((Sp[0][m][cl] + Sp[1][m][cl]) + (Sp[2][m][cl] + Sp[3][m][cl]));
+      Sq[k][cl] = t;
+    }
+    __syncthreads();
+    // pass 2: Z -= V_p S
+    for (int row0 = j0 + 1; row0 < K; row0 += kBtCR) {
+#pragma unroll
+      for (int q = 0; q < kBtCR * 32 / 1024; ++q) {
+        const int idx = tid + 1024 * q, as = idx / kBtCR, rl = idx - as * kBtCR;
+        Vc[rl][as] = bt_v(w.W, ld, K, j0, nbp, as, row0 + rl);
+      }
+      __syncthreads();
+      const int row = row0 + rl3;
+      if (row < K) {
+        double t = 0.0;
+#pragma unroll 8
+        for (int aa = 0; aa < 32; ++aa) t += Vc[rl3][aa] * Sq[aa][cl3];
+        Zs[cl3][row] -= t;
+      }
+      __syncthreads();
+    }
+  }
+  for (int idx = tid; idx < nc * K; idx += 1024) {
+    const int cl = idx / K, row = idx - cl * K;
+    w.Z[(size_t)(c0 + cl) * K + row] = Zs[cl][row];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1133,7 +1235,8 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
     }
     case 2: hipLaunchKernelGGL(k_large_eig<ADMM>, dim3(ntask), dim3(kLT), 0, st, a); break;
     case 3:
-      hipLaunchKernelGGL(k_large_backtrans<ADMM>, dim3(ntask, (rmax + kBtCols - 1) / kBtCols), dim3(kLT), 0, st, a);
+      hipLaunchKernelGGL(k_bt_tfactor<ADMM>, dim3(ntask, (kmax - 2 + kNB - 1) / kNB), dim3(1024), 0, st, a);
+      hipLaunchKernelGGL(k_bt_apply<ADMM>, dim3(ntask, (rmax + kBtNC - 1) / kBtNC), dim3(1024), 0, st, a);
       break;
     case 4: hipLaunchKernelGGL(k_large_recon<ADMM>, dim3(ntask, T * (T + 1) / 2), dim3(256), 0, st, a); break;
     case 5:
