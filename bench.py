@@ -33,42 +33,46 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 PEAK_HBM_GBS = 8000.0
 
 
+def trd_tail_start(K, tail=128, nb=32):
+    """First column of a clique's tridiagonalisation done in LDS by the tail kernel."""
+    return ((K - tail + nb - 1) // nb) * nb if K > tail else 0
+
+
 def phase_work(inst_sizes, prob_dims):
     """Algorithmic work of one average launch of each kernel phase.
 
     Returns {phase: (bound, amount, unit)}; amount is bytes for memory-bound
     phases and flops for arithmetic ones.  The tridiagonalisation runs one
-    symv and one update launch per column step of the largest clique (all
-    large cliques in lockstep) and one trailing update per panel of 32."""
-    large = [k for k in inst_sizes if k > 96]
+    symv and one update launch per column step of the panels (all large
+    cliques in lockstep, each until its last 128 columns), one trailing
+    update per panel of 32 and one LDS tail launch."""
+    large = sorted((k for k in inst_sizes if k > 96), reverse=True)
     small = [k for k in inst_sizes if k <= 96]
     nE, ns, m, p = prob_dims
     out = {}
     if large:
-        kmax, nbp = max(large), 32
-        npan = (kmax - 2 + nbp - 1) // nbp
+        nbp = 32
+        npan = trd_tail_start(large[0]) // nbp
         symv_b = upd_b = trail_f = 0.0
-        n_cols = 0
         for pp in range(npan):
-            nbm = min(nbp, kmax - 2 - pp * nbp)
-            n_cols += nbm
             for K in large:
-                j0 = pp * nbp
-                if j0 >= K - 2:
-                    continue
-                nb = min(nbp, K - 2 - j0)
-                n2 = K - j0 - nb
+                if trd_tail_start(K) <= pp * nbp:
+                    break
+                n2 = K - pp * nbp - nbp
                 # trailing update A22 -= V Wp^T + Wp V^T, both triangles: 4 nb flops per entry
-                trail_f += 4.0 * nb * n2 * n2
-                for i in range(nb):
-                    n1 = K - (j0 + i) - 1
+                trail_f += 4.0 * nbp * n2 * n2
+                for i in range(nbp):
+                    n1 = K - (pp * nbp + i) - 1
                     # y = A22 v plus the 2i panel dots: each operand read once
                     symv_b += 8.0 * (n1 * n1 + 2 * i * n1)
                     # w and the column update: y, 2i panel entries, v, column j+1 per row; Wp, W writes
                     upd_b += 8.0 * n1 * (2 * i + 6)
-        out["trd_symv"] = ("hbm", symv_b / n_cols, "GB/s")
-        out["trd_update"] = ("hbm", upd_b / n_cols, "GB/s")
-        out["trd_trail"] = ("alu", trail_f / npan, "TFLOP/s")
+        if npan:
+            out["trd_symv"] = ("hbm", symv_b / (npan * nbp), "GB/s")
+            out["trd_update"] = ("hbm", upd_b / (npan * nbp), "GB/s")
+            out["trd_trail"] = ("alu", trail_f / npan, "TFLOP/s")
+        # the last n <= 128 columns of every clique, (4/3) n^3 flops each
+        out["trd_tail"] = ("alu", sum(4.0 / 3.0 * (K - trd_tail_start(K)) ** 3 for K in large), "TFLOP/s")
     # Jacobi blocks: counted with the 10 K^3 eigen-decomposition convention
     for kmax, name in ((16, "cone_jacobi16"), (32, "cone_jacobi32"), (64, "cone_jacobi64"), (96, "cone_jacobi96")):
         lo = {16: 0, 32: 16, 64: 32, 96: 64}[kmax]
@@ -76,6 +80,27 @@ def phase_work(inst_sizes, prob_dims):
     # scatter H^T(s+z+v): read s,z,v (3 ns doubles) + slot ids + x, c, pinv; write hsum, q
     out["r0_scatter"] = ("hbm", 8.0 * 3 * ns + 4.0 * ns + 4.0 * (nE + 1) + 8.0 * 3 * nE + 8.0 * 2 * nE, "GB/s")
     return out
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the summary is missing or the kernel source changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel}_config1_traffic.md")
+    src = os.path.join(ROOT, "paper_1611_01828_amd", "csrc", "kernels_large.hip")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"<!-- traffic: (\{.*\}) -->", text)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha256") != digest:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def main():
@@ -156,7 +181,7 @@ def main():
             ach = amount / sec / 1e9
             peak = PEAK_HBM_GBS
         roof = {"kernel": dom, "bound": bound, "achieved": round(ach, 4), "peak": peak, "unit": unit,
-                "frac": round(ach / peak, 6), "traffic": None,
+                "frac": round(ach / peak, 6), "traffic": measured_traffic(dom),
                 "work_per_launch": amount, "avg_launch_ms": round(per_launch[dom], 5),
                 "launches_per_step": phases[dom][1] / args.steps,
                 "ms_per_step_in_kernel": round(phases[dom][0] / args.steps, 4)}

@@ -162,8 +162,8 @@ int bucket_of(int K) {
 }
 
 // record a phase launch between two events when timing is on
-// event pair from the pool, start recorded on s
-size_t timer_begin(cdcs_handle* h, hipStream_t s) {
+// event pair from the pool (not yet recorded)
+size_t timer_alloc(cdcs_handle* h) {
   const size_t slot = h->ev_used.size() + h->ev_open;
   while (slot >= h->ev_pool.size()) {
     hipEvent_t a, b;
@@ -172,14 +172,25 @@ size_t timer_begin(cdcs_handle* h, hipStream_t s) {
     h->ev_pool.push_back({a, b});
   }
   ++h->ev_open;
+  return slot;
+}
+
+// the pair holds a measurement of phase ph once the stream reaches it
+void timer_commit(cdcs_handle* h, size_t slot, int ph) {
+  --h->ev_open;
+  h->ev_used.push_back({ph, slot});
+}
+
+// event pair from the pool, start recorded on s
+size_t timer_begin(cdcs_handle* h, hipStream_t s) {
+  const size_t slot = timer_alloc(h);
   (void)hipEventRecord(h->ev_pool[slot].first, s);
   return slot;
 }
 
 void timer_end(cdcs_handle* h, size_t slot, int ph, hipStream_t s) {
   (void)hipEventRecord(h->ev_pool[slot].second, s);
-  --h->ev_open;
-  h->ev_used.push_back({ph, slot});
+  timer_commit(h, slot, ph);
 }
 
 struct PhaseTimer {
@@ -197,18 +208,20 @@ struct PhaseTimer {
   }
 };
 
-// times every launch of the tridiagonalisation step in its own phase
+// times every launch of the tridiagonalisation step in its own phase with
+// the kernel's own start and end (events passed to the launch)
 struct TrdTimer {
   cdcs_handle* h;
-  hipStream_t s;
   size_t slot;
-  static void before(void* c, int) {
+  static void begin(void* c, int, hipEvent_t* e0, hipEvent_t* e1) {
     auto* t = static_cast<TrdTimer*>(c);
-    t->slot = timer_begin(t->h, t->s);
+    t->slot = timer_alloc(t->h);
+    *e0 = t->h->ev_pool[t->slot].first;
+    *e1 = t->h->ev_pool[t->slot].second;
   }
-  static void after(void* c, int kind) {
+  static void end(void* c, int kind) {
     auto* t = static_cast<TrdTimer*>(c);
-    timer_end(t->h, t->slot, PH_LG_TRD_SYMV + kind, t->s);
+    timer_commit(t->h, t->slot, PH_LG_TRD_SYMV + kind);
   }
 };
 
@@ -243,8 +256,8 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
     HIPCHK(hipStreamWaitEvent(lst, h->ev_fork, 0));
   }
   if (h->ntasks[4]) {
-    TrdTimer tt{h, lst, 0};
-    const LaunchHook hook{&TrdTimer::before, &TrdTimer::after, &tt};
+    TrdTimer tt{h, 0};
+    const LaunchHook hook{&TrdTimer::begin, &TrdTimer::end, &tt};
     for (int step = 0; step < kLargeSteps; ++step) {
       PhaseTimer t(h, kLargeStepPhase[step], lst);
       launch_cone_large_step(d, h->tasks[4], h->ntasks[4], h->kmax_large, h->large_sizes.data(), step, lst,

@@ -152,11 +152,12 @@ void launch_scalar2(const DevPlan& d, double eps_tol, int32_t max_iter, int32_t 
 void launch_cone_jacobi(const DevPlan& d, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st);
 // large cliques: gather, tridiag, eig, backtrans, recon, partials
 constexpr int kLargeSteps = 6;
-// called around every launch of the tridiagonalisation step (kind 0 symv,
-// 1 update, 2 trailing update, 3 tail in LDS), e.g. to time them
+// timing of the tridiagonalisation launches (kind 0 symv, 1 update,
+// 2 trailing update, 3 tail in LDS): begin() hands out an event pair that
+// the launch itself records (the kernel's own start and end), end() files it
 struct LaunchHook {
-  void (*before)(void* ctx, int kind);
-  void (*after)(void* ctx, int kind);
+  void (*begin)(void* ctx, int kind, hipEvent_t* start, hipEvent_t* stop);
+  void (*end)(void* ctx, int kind);
   void* ctx;
 };
 // host_sizes: the tasks' clique orders on the host, sorted descending

@@ -17,6 +17,8 @@
 //                  s+, z+ = s+ - Y, v+ and the residual partial sums (ADMM
 //                  mode) or written to the output blocks (projection mode)
 //   6. partials    per-clique sum of the tile partials (fixed order)
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "device.h"
@@ -1205,6 +1207,16 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
         while (n < ntask && trd_tail_start(host_sizes[n]) > j0) ++n;
         return n;
       };
+      auto launch = [&](int kind, auto kernel, dim3 grid, dim3 block, auto... args) {
+        if (hook) {
+          hipEvent_t e0, e1;
+          hook->begin(hook->ctx, kind, &e0, &e1);
+          hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
+          hook->end(hook->ctx, kind);
+        } else {
+          hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+        }
+      };
       const int np = trd_tail_start(kmax) / kNB;
       const int ldm = (kmax + 7) & ~7;
       for (int p = 0; p < np; ++p) {
@@ -1214,23 +1226,13 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
           const int nallm = kmax - j - 1 + 2 * i;
           const int ncy = (nallm + kSymvCols - 1) / kSymvCols;
           const int nrbm = (ldm - ((j + 1) & ~1) + kSymvRows - 1) / kSymvRows;
-          if (hook) hook->before(hook->ctx, 0);
-          hipLaunchKernelGGL(k_trd_symv<ADMM>, dim3(na, ncy * nrbm), dim3(256), 0, st, a, p, i, ncy);
-          if (hook) hook->after(hook->ctx, 0);
-          if (hook) hook->before(hook->ctx, 1);
-          hipLaunchKernelGGL(k_trd_update<ADMM>, dim3(na, (ldm + kUpdRows - 1) / kUpdRows), dim3(256), 0, st, a,
-                             p, i);
-          if (hook) hook->after(hook->ctx, 1);
+          launch(0, k_trd_symv<ADMM>, dim3(na, ncy * nrbm), dim3(256), a, p, i, ncy);
+          launch(1, k_trd_update<ADMM>, dim3(na, (ldm + kUpdRows - 1) / kUpdRows), dim3(256), a, p, i);
         }
         const int n2 = kmax - p * kNB - kNB;
-        if (hook) hook->before(hook->ctx, 2);
-        hipLaunchKernelGGL(k_trd_trail<ADMM>, dim3(na, ((n2 + 127) / 128) * ((n2 + 63) / 64)), dim3(kTT), 0, st,
-                           a, p);
-        if (hook) hook->after(hook->ctx, 2);
+        launch(2, k_trd_trail<ADMM>, dim3(na, ((n2 + 127) / 128) * ((n2 + 63) / 64)), dim3(kTT), a, p);
       }
-      if (hook) hook->before(hook->ctx, 3);
-      hipLaunchKernelGGL(k_trd_tail<ADMM>, dim3(ntask), dim3(kTailT), 0, st, a);
-      if (hook) hook->after(hook->ctx, 3);
+      launch(3, k_trd_tail<ADMM>, dim3(ntask), dim3(kTailT), a);
       break;
     }
     case 2: hipLaunchKernelGGL(k_large_eig<ADMM>, dim3(ntask), dim3(kLT), 0, st, a); break;
