@@ -33,7 +33,7 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 PEAK_HBM_GBS = 8000.0
 
 
-def trd_tail_start(K, tail=128, nb=32):
+def trd_tail_start(K, tail=136, nb=32):
     """First column of a clique's tridiagonalisation done in LDS by the tail kernel."""
     return ((K - tail + nb - 1) // nb) * nb if K > tail else 0
 
@@ -44,7 +44,7 @@ def phase_work(inst_sizes, prob_dims):
     Returns {phase: (bound, amount, unit)}; amount is bytes for memory-bound
     phases and flops for arithmetic ones.  The tridiagonalisation runs one
     symv and one update launch per column step of the panels (all large
-    cliques in lockstep, each until its last 128 columns), one trailing
+    cliques in lockstep, each until its last <= 136 columns), one trailing
     update per panel of 32 and one LDS tail launch."""
     large = sorted((k for k in inst_sizes if k > 96), reverse=True)
     small = [k for k in inst_sizes if k <= 96]
@@ -71,7 +71,7 @@ def phase_work(inst_sizes, prob_dims):
             out["trd_symv"] = ("hbm", symv_b / (npan * nbp), "GB/s")
             out["trd_update"] = ("hbm", upd_b / (npan * nbp), "GB/s")
             out["trd_trail"] = ("alu", trail_f / npan, "TFLOP/s")
-        # the last n <= 128 columns of every clique, (4/3) n^3 flops each
+        # the last n <= 136 columns of every clique, (4/3) n^3 flops each
         out["trd_tail"] = ("alu", sum(4.0 / 3.0 * (K - trd_tail_start(K)) ** 3 for K in large), "TFLOP/s")
     # Jacobi blocks: counted with the 10 K^3 eigen-decomposition convention
     for kmax, name in ((16, "cone_jacobi16"), (32, "cone_jacobi32"), (64, "cone_jacobi64"), (96, "cone_jacobi96")):

@@ -228,7 +228,7 @@ __device__ __forceinline__ TrdBufs trd_bufs(const Ws& w, int ld) {
 // Once the trailing matrix has at most kTail columns it fits in LDS, and one
 // workgroup per task finishes the reduction there (k_trd_tail).  The panel
 // launches cover columns [0, trd_tail_start(K)), whole panels only.
-constexpr int kTail = 128;
+constexpr int kTail = 136;   // full n x n storage of 136 columns: 148 KB of LDS
 __host__ __device__ __forceinline__ int trd_tail_start(int K) {
   return (K > kTail) ? ((K - kTail + kNB - 1) / kNB) * kNB : 0;
 }
@@ -561,21 +561,24 @@ __global__ __launch_bounds__(kTT) void k_trd_trail(LargeArgs a, int p) {
 // reduced column by column: x = A(c+1:n, c) gives the reflector, then
 // p = tau A22 v, w = p - tau/2 (p^T v) v and A22 -= v w^T + w v^T
 // (Golub & Van Loan Algorithm 8.3.1).  Thread (r, h) owns row r and the
-// columns q = h mod kTailG.
+// columns q = h mod kTailG (kTailG groups of kTailR row slots; the last
+// threads of the block idle).
 constexpr int kTailT = 1024;
-constexpr int kTailG = kTailT / kTail;
+constexpr int kTailR = 144;
+constexpr int kTailG = kTailT / kTailR;
+static_assert(kTailR >= kTail && kTail <= 192, "tail layout");
 template <bool ADMM>
 __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
   __shared__ double A[kTail * kTail];
   __shared__ double vb[kTail], wb[kTail], ph[kTailG][kTail];
-  __shared__ double red[kTailT / 64 + 1];
+  __shared__ double red[4];
   const int K = a.tsize[blockIdx.x];
   const int j0 = trd_tail_start(K), n = K - j0;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const int ld = lead_dim(K);
   double* W = w.W;
   const int tid = threadIdx.x;
-  const int r = tid & (kTail - 1), h = tid / kTail;
+  const int r = tid % kTailR, h = tid / kTailR;   // h == kTailG: idle
   for (int idx = tid; idx < n * n; idx += kTailT) {
     const int c = idx / n, rr = idx - c * n;
     A[c * n + rr] = W[(size_t)(j0 + c) * ld + j0 + rr];
@@ -584,11 +587,15 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
   const int lane = tid & 63;
   for (int c = 0; c < n - 2; ++c) {
     const int j = j0 + c;
-    // (1) wave 0: reflector of column c (rows lane and lane + 64)
+    // (1) wave 0: reflector of column c (rows lane + 64 u)
     if (tid < 64) {
-      const int r0 = lane, r1 = lane + 64;
-      const double x0 = (r0 < n) ? A[c * n + r0] : 0.0, x1 = (r1 < n) ? A[c * n + r1] : 0.0;
-      double ss = ((r0 >= c + 2 && r0 < n) ? x0 * x0 : 0.0) + ((r1 >= c + 2 && r1 < n) ? x1 * x1 : 0.0);
+      double xs[3], ss = 0.0;
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int rr = lane + 64 * u;
+        xs[u] = (rr < n) ? A[c * n + rr] : 0.0;
+        if (rr >= c + 2 && rr < n) ss += xs[u] * xs[u];
+      }
       ss = wave_sum(ss);
       const double alpha = A[c * n + c + 1];
       double beta, tu, scale;
@@ -601,12 +608,13 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
         tu = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
       }
-      const double v0 = (r0 == c + 1) ? 1.0 : ((r0 > c + 1 && r0 < n) ? x0 * scale : 0.0);
-      const double v1 = (r1 == c + 1) ? 1.0 : ((r1 > c + 1 && r1 < n) ? x1 * scale : 0.0);
-      vb[r0] = v0;
-      vb[r1] = v1;
-      if (r0 >= c + 2 && r0 < n) W[(size_t)j * ld + j0 + r0] = v0;   // Householder vector
-      if (r1 >= c + 2 && r1 < n) W[(size_t)j * ld + j0 + r1] = v1;
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int rr = lane + 64 * u;
+        const double vr = (rr == c + 1) ? 1.0 : ((rr > c + 1 && rr < n) ? xs[u] * scale : 0.0);
+        if (rr < kTail) vb[rr] = vr;
+        if (rr >= c + 2 && rr < n) W[(size_t)j * ld + j0 + rr] = vr;   // Householder vector
+      }
       if (lane == 0) {
         red[0] = tu;
         w.d[j] = A[c * n + c];
@@ -617,33 +625,37 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
     __syncthreads();
     const double tu = red[0];
     // (2) p = tau A22 v on rows and columns > c, column groups in ph
+    const bool live = h < kTailG && r > c && r < n;
     double acc = 0.0;
-    if (r > c && r < n)
+    if (live)
       for (int q = c + 1 + h; q < n; q += kTailG) acc += A[q * n + r] * vb[q];
-    ph[h][r] = acc;
+    if (h < kTailG && r < kTail) ph[h][r] = acc;
     __syncthreads();
     // (3) wave 0: w = p - tau/2 (p^T v) v
     if (tid < 64) {
-      double pr[2], pv = 0.0;
+      double pr[3], pv = 0.0;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < 3; ++u) {
         const int rr = lane + 64 * u;
         double t = 0.0;
+        if (rr > c && rr < n) {
 #pragma unroll
-        for (int g = 0; g < kTailG; ++g) t += ph[g][rr];
-        pr[u] = (rr > c && rr < n) ? tu * t : 0.0;
-        pv += pr[u] * vb[rr];
+          for (int g = 0; g < kTailG; ++g) t += ph[g][rr];
+          t *= tu;
+          pv += t * vb[rr];
+        }
+        pr[u] = t;
       }
       pv = wave_sum(pv);
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < 3; ++u) {
         const int rr = lane + 64 * u;
-        wb[rr] = (rr > c && rr < n) ? pr[u] - 0.5 * tu * pv * vb[rr] : 0.0;
+        if (rr < kTail) wb[rr] = (rr > c && rr < n) ? pr[u] - 0.5 * tu * pv * vb[rr] : 0.0;
       }
     }
     __syncthreads();
     // (4) A22 -= v w^T + w v^T
-    if (r > c && r < n) {
+    if (live) {
       const double vr = vb[r], wr = wb[r];
       for (int q = c + 1 + h; q < n; q += kTailG) A[q * n + r] -= vr * wb[q] + wr * vb[q];
     }
