@@ -794,12 +794,13 @@ __device__ __forceinline__ double tri_solve(const double* __restrict__ f, int st
   return 1.0 / sqrt(nn);
 }
 
+// (a) prep, one workgroup per task: negligible off-diagonals are set to zero
+//     (they split T), the Gershgorin bound, the Sturm count at 0 and the
+//     side; meta = [r, pos, first, pivmin, ||T||]
 template <bool ADMM>
-__global__ __launch_bounds__(kLT) void k_large_eig(LargeArgs a) {
-  __shared__ double sd[1024], se[1024], se2[1024];
-  __shared__ double slam[512];
-  __shared__ int cls[513];
-  __shared__ int info[4];
+__global__ __launch_bounds__(kLT) void k_eig_prep(LargeArgs a) {
+  __shared__ double sd[1024], se[1024];
+  __shared__ double se2[1024];
   __shared__ double red[kLT / 64 + 1];
   int K;
   int64_t base;
@@ -811,35 +812,30 @@ __global__ __launch_bounds__(kLT) void k_large_eig(LargeArgs a) {
     se[i] = (i < K - 1) ? w.e[i] : 0.0;
   }
   __syncthreads();
-  // negligible off-diagonals split T; they are set to zero
   double tn = 0.0;
   for (int i = tid; i < K; i += kLT) {
     const double em = (i > 0) ? fabs(se[i - 1]) : 0.0;
     tn = fmax(tn, fabs(sd[i]) + em + fabs(se[i]));
   }
-  {
-    // block max through the sum helper on per-wave maxima
-    for (int off = 32; off > 0; off >>= 1) tn = fmax(tn, __shfl_xor(tn, off, 64));
-    if ((tid & 63) == 0) red[tid >> 6] = tn;
-    __syncthreads();
-    if (tid == 0) {
-      double m = 0.0;
-      for (int q = 0; q < kLT / 64; ++q) m = fmax(m, red[q]);
-      red[kLT / 64] = m;
-    }
-    __syncthreads();
-    tn = red[kLT / 64];
-    __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) tn = fmax(tn, __shfl_xor(tn, off, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = tn;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int q = 0; q < kLT / 64; ++q) m = fmax(m, red[q]);
+    red[kLT / 64] = m;
   }
+  __syncthreads();
+  tn = red[kLT / 64];
+  __syncthreads();
   double emax2 = 0.0;
   for (int i = tid; i < K - 1; i += kLT) {
     double ei = se[i];
     if (fabs(ei) <= kEps * (fabs(sd[i]) + fabs(sd[i + 1]))) ei = 0.0;
-    se[i] = ei;
+    w.e[i] = ei;
     se2[i] = ei * ei;
     emax2 = fmax(emax2, ei * ei);
   }
-  if (tid == 0) se2[K - 1] = 0.0;
   for (int off = 32; off > 0; off >>= 1) emax2 = fmax(emax2, __shfl_xor(emax2, off, 64));
   if ((tid & 63) == 0) red[tid >> 6] = emax2;
   __syncthreads();
@@ -849,50 +845,80 @@ __global__ __launch_bounds__(kLT) void k_large_eig(LargeArgs a) {
     const double pivmin = 2.2250738585072014e-308 * fmax(1.0, m) / kEps;
     const int nneg = sturm_count(sd, se2, K, 0.0, pivmin);
     const int pos = (nneg <= K - nneg) ? 0 : 1;
-    info[0] = pos ? K - nneg : nneg;     // r
-    info[1] = pos;
-    info[2] = pos ? nneg : 0;            // index of the first chosen eigenvalue
-    red[0] = pivmin;
+    w.meta[0] = (double)(pos ? K - nneg : nneg);   // r
+    w.meta[1] = (double)pos;
+    w.meta[2] = (double)(pos ? nneg : 0);           // index of the first chosen eigenvalue
+    w.meta[3] = pivmin;
+    w.meta[4] = fmax(tn, 2.2250738585072014e-308);
+  }
+}
+
+// (b) bisection, kBisEig eigenvalues per workgroup, one wave each: the 64
+//     lanes evaluate the Sturm count at 64 interior points (multisection) and
+//     the interval shrinks by 65 per round.  The chosen side lies in
+//     [Gershgorin low, 0] or [0, Gershgorin high]; the count at 0 is the
+//     nneg of the prep, so count(lo) <= k < count(hi) holds from the start.
+//     Intervals are refined to an absolute width of about eps ||T||, the
+//     accuracy inverse iteration and the low-rank update can use.
+constexpr int kBisEig = 4;
+template <bool ADMM>
+__global__ __launch_bounds__(64 * kBisEig) void k_eig_bisect(LargeArgs a) {
+  __shared__ double sd[1024], se2[1024];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int r = (int)w.meta[0];
+  const int t0 = blockIdx.y * kBisEig;
+  if (t0 >= r) return;
+  const int pos = (int)w.meta[1], first = (int)w.meta[2];
+  const double pivmin = w.meta[3], tnorm = w.meta[4];
+  const int tid = threadIdx.x, lane = tid & 63, t = t0 + (tid >> 6);
+  for (int i = tid; i < K; i += 64 * kBisEig) {
+    sd[i] = w.d[i];
+    const double ei = (i < K - 1) ? w.e[i] : 0.0;
+    se2[i] = ei * ei;
   }
   __syncthreads();
-  const double pivmin = red[0];
-  const int r = info[0], pos = info[1], first = info[2];
-  const double tnorm = fmax(tn, 2.2250738585072014e-308);
-  // Bisection by groups of g lanes per eigenvalue (multisection: the g lanes
-  // evaluate the Sturm count at g interior points and the interval shrinks
-  // by g + 1 per round).  The chosen side lies in [Gershgorin low, 0] or
-  // [0, Gershgorin high]; the count at 0 is the nneg found above, so the
-  // invariant count(lo) <= k < count(hi) holds from the start.  Intervals are
-  // refined to an absolute width of about eps * ||T||, which is the accuracy
-  // inverse iteration and the low-rank update below can use.
-  {
-    int g = 64;
-    while (g > 1 && r * g > kLT) g >>= 1;
-    const int ngroups = kLT / g;
-    const int grp = tid / g, gl = tid % g;
-    const int lane = tid & 63, gbase = lane - gl;
-    const uint64_t gmask = (g == 64) ? ~0ull : ((1ull << g) - 1ull);
-    const double glo = -tnorm * (1.0 + 4.0 * kEps) - pivmin, ghi = tnorm * (1.0 + 4.0 * kEps) + pivmin;
-    const double wtol = 2.0 * kEps * tnorm + 4.0 * pivmin;
-    for (int t = grp; t < r; t += ngroups) {
-      const int k = first + t;
-      double lo = pos ? 0.0 : glo, hi = pos ? ghi : 0.0;
-      for (int round = 0; round < 200; ++round) {
-        const double width = hi - lo;
-        if (width <= fmax(wtol, 2.0 * kEps * fmax(fabs(lo), fabs(hi)))) break;
-        const double step = width / (double)(g + 1);
-        const double x = lo + step * (double)(gl + 1);
-        const bool above = sturm_count(sd, se2, K, x, pivmin) > k;
-        const uint64_t m = (__ballot(above) >> gbase) & gmask;
-        const int j0 = m ? __builtin_ctzll(m) : g;   // first point with count > k
-        const double nlo = (j0 == 0) ? lo : lo + step * (double)j0;
-        const double nhi = (j0 == g) ? hi : lo + step * (double)(j0 + 1);
-        lo = nlo;
-        hi = fmax(nhi, nlo);
-      }
-      if (gl == 0) slam[t] = 0.5 * (lo + hi);
-    }
+  if (t >= r) return;   // whole waves; no barriers below
+  const double glo = -tnorm * (1.0 + 4.0 * kEps) - pivmin, ghi = tnorm * (1.0 + 4.0 * kEps) + pivmin;
+  const double wtol = 2.0 * kEps * tnorm + 4.0 * pivmin;
+  const int k = first + t;
+  double lo = pos ? 0.0 : glo, hi = pos ? ghi : 0.0;
+  for (int round = 0; round < 200; ++round) {
+    const double width = hi - lo;
+    if (width <= fmax(wtol, 2.0 * kEps * fmax(fabs(lo), fabs(hi)))) break;
+    const double step = width / 65.0;
+    const double x = lo + step * (double)(lane + 1);
+    const uint64_t m = __ballot(sturm_count(sd, se2, K, x, pivmin) > k);
+    const int j0 = m ? __builtin_ctzll(m) : 64;   // first point with count > k
+    const double nlo = (j0 == 0) ? lo : lo + step * (double)j0;
+    const double nhi = (j0 == 64) ? hi : lo + step * (double)(j0 + 1);
+    lo = nlo;
+    hi = fmax(nhi, nlo);
   }
+  if (lane == 0) w.lam[t] = 0.5 * (lo + hi);
+}
+
+// (c) eigenvectors of T for the chosen eigenvalues
+template <bool ADMM>
+__global__ __launch_bounds__(kLT) void k_eig_vec(LargeArgs a) {
+  __shared__ double sd[1024], se[1024];
+  __shared__ double slam[512];
+  __shared__ int cls[513];
+  __shared__ int info[4];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int tid = threadIdx.x;
+  const int r = (int)w.meta[0];
+  const double tnorm = w.meta[4];
+  for (int i = tid; i < K; i += kLT) {
+    sd[i] = w.d[i];
+    se[i] = (i < K - 1) ? w.e[i] : 0.0;
+  }
+  for (int t = tid; t < r; t += kLT) slam[t] = w.lam[t];
   __syncthreads();
   // clusters of close eigenvalues (consecutive gaps below the threshold)
   const double ortol = 1e-5 * tnorm;
@@ -913,7 +939,7 @@ __global__ __launch_bounds__(kLT) void k_large_eig(LargeArgs a) {
   // since r <= K / 2.
   double* X = w.S;
   const size_t KR = (size_t)K * r;
-  // (a) isolated eigenvalues: one lane each, three solves, the vector kept in
+  // (a) isolated eigenvalues: one lane each, two solves, the vector kept in
   //     the scratch area and normalised lazily
   for (int t = tid; t < r; t += kLT) {
     int c = 0;
@@ -930,8 +956,11 @@ __global__ __launch_bounds__(kLT) void k_large_eig(LargeArgs a) {
     double* zt = X + 5 * KR + t;
     tri_factor(sd, se, K, slam[t], tiny, X + t, r, KR);
     for (int i = 0; i < K; ++i) zt[(size_t)i * r] = hash_unit((uint32_t)t, (uint32_t)i);
+    // two solves: lambda is accurate to ~eps ||T|| and its gap to the other
+    // eigenvalues is above 1e-5 ||T||, so each solve shrinks the other
+    // components of a random start by ~1e-10 or more
     double sc = 1.0;
-    for (int it = 0; it < 3; ++it) sc = tri_solve(X + t, r, KR, K, zt, r, sc);
+    for (int it = 0; it < 2; ++it) sc = tri_solve(X + t, r, KR, K, zt, r, sc);
     double* zo = w.Z + (size_t)t * K;
     for (int i = 0; i < K; ++i) zo[i] = zt[(size_t)i * r] * sc;
   }
@@ -965,11 +994,6 @@ __global__ __launch_bounds__(kLT) void k_large_eig(LargeArgs a) {
         }
       }
     }
-  }
-  for (int t = tid; t < r; t += kLT) w.lam[t] = slam[t];
-  if (tid == 0) {
-    w.meta[0] = (double)r;
-    w.meta[1] = (double)pos;
   }
 }
 
@@ -1258,7 +1282,12 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
       launch(3, k_trd_tail<ADMM>, dim3(ntask), dim3(kTailT), a);
       break;
     }
-    case 2: hipLaunchKernelGGL(k_large_eig<ADMM>, dim3(ntask), dim3(kLT), 0, st, a); break;
+    case 2:
+      hipLaunchKernelGGL(k_eig_prep<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
+      hipLaunchKernelGGL(k_eig_bisect<ADMM>, dim3(ntask, (rmax + kBisEig - 1) / kBisEig), dim3(64 * kBisEig), 0, st,
+                         a);
+      hipLaunchKernelGGL(k_eig_vec<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
+      break;
     case 3:
       hipLaunchKernelGGL(k_bt_tfactor<ADMM>, dim3(ntask, (kmax - 2 + kNB - 1) / kNB), dim3(1024), 0, st, a);
       hipLaunchKernelGGL(k_bt_apply<ADMM>, dim3(ntask, (rmax + kBtNC - 1) / kBtNC), dim3(1024), 0, st, a);

@@ -57,6 +57,7 @@ def _rel(a, b):
     [33, 40, 63, 64],
     [65, 77, 95, 96],
     [97, 128, 129, 200],
+    [136, 137, 168, 169],        # tail only, one panel + tail, two panels + tail
     [333, 512, 673],
     [1024],
 ])
@@ -85,7 +86,7 @@ def test_psd_project_matches_oracle(lib, torch_cuda, sizes):
         assert err <= (1e-13 if K <= 96 else 1e-12), K
 
 
-@pytest.mark.parametrize("K", [12, 150])
+@pytest.mark.parametrize("K", [12, 150, 300])
 def test_psd_project_special_blocks(lib, torch_cuda, K):
     """Zero, PSD, NSD, rank-one and repeated-eigenvalue blocks."""
     torch = torch_cuda
