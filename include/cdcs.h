@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define CDCS_ABI_VERSION 1
+#define CDCS_ABI_VERSION 2
 
 /* outcomes (cdcs_info.status) */
 enum {
@@ -103,6 +103,15 @@ typedef struct {
   int32_t check_every; /* cdcs_solve reads the status words back every this many iterations */
   int32_t timing;      /* 1 = time each kernel phase with HIP events (cdcs_get_phase_times) */
   int32_t use_graph;   /* 1 = replay the iteration from a captured HIP graph */
+  int32_t eig_fp32;    /* 1 = eigen-decompose cliques of up to 96 vertices in FP32 (Jacobi in
+                          FP32; gather, Y and the update of s, z, v stay FP64); larger cliques
+                          always FP64.  The iterates then differ from the FP64 method by ~1e-7
+                          relative per conic step. */
+  int32_t autotune;    /* Jacobi tile shape (threads per clique) of every clique-size bucket:
+                          0 = the default shape; 1 = at setup, time both candidate shapes on
+                          synthetic blocks of the instance's clique orders and keep the
+                          faster; 2 = the other candidate without timing (for comparisons).
+                          cdcs_get_tuning reports the choice. */
 } cdcs_settings;
 
 typedef struct {
@@ -115,7 +124,7 @@ typedef struct {
 } cdcs_info;
 
 /* Fill s with eps_tol = 1e-4, max_iter = 2000, check_every = 1, timing = 0,
- * use_graph = 0. */
+ * use_graph = 0, eig_fp32 = 0, autotune = 0. */
 void cdcs_default_settings(cdcs_settings* s);
 
 /* Build the cached data of step 1 (the m x m factor of the matrix of eq.
@@ -201,6 +210,12 @@ int cdcs_reset_phase_times(cdcs_handle* h);
  * device pointers (may alias).  Runs on `stream` and synchronises it. */
 int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets,
                      const double* in, double* out, void* stream);
+
+/* The Jacobi tile shape used per clique-size bucket (the autotuner's choice,
+ * or the default): out[4 b + 0..3] = bucket's largest clique order (16, 32,
+ * 64, 96), threads per clique, number of cliques in the bucket, 1 if the
+ * autotuner measured it.  Returns the number of buckets (4) or an error. */
+int cdcs_get_tuning(const cdcs_handle* h, int32_t* out, int32_t cap);
 
 const char* cdcs_last_error(void);
 int cdcs_abi_version(void);

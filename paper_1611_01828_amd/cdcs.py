@@ -36,7 +36,8 @@ class Problem(C.Structure):
 
 class Settings(C.Structure):
     _fields_ = [("eps_tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
-                ("timing", C.c_int32), ("use_graph", C.c_int32)]
+                ("timing", C.c_int32), ("use_graph", C.c_int32), ("eig_fp32", C.c_int32),
+                ("autotune", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -53,7 +54,8 @@ EXPORTS = [
     "cdcs_default_settings", "cdcs_setup", "cdcs_setup_batch", "cdcs_iterate", "cdcs_solve",
     "cdcs_get_dims", "cdcs_get_entries", "cdcs_get_solution", "cdcs_get_certificate",
     "cdcs_get_state", "cdcs_set_state", "cdcs_get_phase_times", "cdcs_reset_phase_times",
-    "cdcs_psd_project", "cdcs_adjoint", "cdcs_last_error", "cdcs_abi_version", "cdcs_destroy",
+    "cdcs_psd_project", "cdcs_adjoint", "cdcs_get_tuning", "cdcs_last_error", "cdcs_abi_version",
+    "cdcs_destroy",
 ]
 
 
@@ -108,6 +110,7 @@ def load(path: str = LIB_PATH):
     lib.cdcs_get_state.argtypes = [vp, C.c_int32, _dp, _dp]
     lib.cdcs_set_state.argtypes = [vp, C.c_int32, _dp, _dp]
     lib.cdcs_get_phase_times.argtypes = [vp, C.POINTER(C.c_char_p), _dp, _i64p, C.c_int32]
+    lib.cdcs_get_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32]
     lib.cdcs_reset_phase_times.argtypes = [vp]
     lib.cdcs_psd_project.argtypes = [C.c_int32, _i32p, _i64p, vp, vp, vp]
     lib.cdcs_adjoint.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_int32)]
@@ -291,6 +294,14 @@ class Solver:
 
     def reset_phase_times(self):
         _check(load().cdcs_reset_phase_times(self.h))
+
+    def tuning(self):
+        """Jacobi tile shape per clique-size bucket: list of dicts
+        (kmax, threads, cliques, tuned)."""
+        out = (C.c_int32 * 16)()
+        n = _check(load().cdcs_get_tuning(self.h, out, 16))
+        return [dict(kmax=out[4 * b], threads=out[4 * b + 1], cliques=out[4 * b + 2], tuned=bool(out[4 * b + 3]))
+                for b in range(n)]
 
 
 def psd_project(sizes, offsets, inp, out, stream=None):

@@ -96,6 +96,10 @@ struct cdcs_handle {
   // cone work lists by kernel variant
   int32_t* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int32_t ntasks[5] = {0, 0, 0, 0, 0};
+  // Jacobi buckets: clique orders (host), tile variant, whether autotuned
+  std::vector<int32_t> bucket_sizes[4];
+  int32_t jvar[4] = {0, 0, 0, 0};
+  int32_t jtuned[4] = {0, 0, 0, 0};
   int32_t kmax_large = 0;
   std::vector<int32_t> large_sizes;      // host copy of large task sizes (launch shapes)
   // timing
@@ -267,7 +271,7 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
   for (int bk = 0; bk < 4; ++bk)
     if (h->ntasks[bk]) {
       PhaseTimer t(h, PH_CONE16 + bk);
-      launch_cone_jacobi(d, h->tasks[bk], h->ntasks[bk], kmaxs[bk], st);
+      launch_cone_jacobi(d, h->tasks[bk], h->ntasks[bk], kmaxs[bk], h->jvar[bk], h->set.eig_fp32, st);
     }
   if (fork) {
     HIPCHK(hipEventRecord(h->ev_join, lst));
@@ -276,6 +280,89 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
   { PhaseTimer t(h, PH_SCALAR2); launch_scalar2(d, h->set.eps_tol, h->set.max_iter, stop, st); }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return 0;
+}
+
+// Autotuner: for every Jacobi bucket, time its two tile shapes (threads per
+// clique) on synthetic symmetric blocks with the bucket's clique orders (at
+// most kTuneBlocks of them, entries from a fixed integer hash in [-1, 1)) and
+// keep the faster.  The stand-alone projection kernel is the proxy: it runs
+// the same Jacobi as the fused cone kernel.
+constexpr int kTuneBlocks = 1024;
+constexpr int kTuneReps = 3;
+
+int autotune(cdcs_handle* h) {
+  hipStream_t st = h->stream;
+  const int kmaxs[4] = {16, 32, 64, kJacobiMax};
+  for (int bk = 0; bk < 4; ++bk) {
+    const auto& all = h->bucket_sizes[bk];
+    if (all.empty()) continue;
+    const int nb = (int)std::min<size_t>(all.size(), kTuneBlocks);
+    std::vector<int32_t> sz(all.begin(), all.begin() + nb), tk(nb);
+    std::vector<int64_t> off(nb);
+    int64_t tot = 0;
+    for (int i = 0; i < nb; ++i) {
+      tk[i] = i;
+      off[i] = tot;
+      tot += (int64_t)sz[i] * (sz[i] + 1) / 2;
+    }
+    std::vector<double> vals((size_t)tot);
+    uint64_t x = 0x9E3779B97F4A7C15ull ^ (uint64_t)(bk + 1);
+    for (auto& v : vals) {
+      x ^= x << 13;
+      x ^= x >> 7;
+      x ^= x << 17;
+      v = (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+    int32_t *dsz = nullptr, *dtk = nullptr;
+    int64_t* doff = nullptr;
+    double *din = nullptr, *dout = nullptr;
+    auto release = [&]() {
+      (void)hipFree(dsz);
+      (void)hipFree(dtk);
+      (void)hipFree(doff);
+      (void)hipFree(din);
+      (void)hipFree(dout);
+    };
+    if (hipMalloc(&dsz, nb * 4) != hipSuccess || hipMalloc(&dtk, nb * 4) != hipSuccess ||
+        hipMalloc(&doff, nb * 8) != hipSuccess || hipMalloc(&din, tot * 8) != hipSuccess ||
+        hipMalloc(&dout, tot * 8) != hipSuccess) {
+      release();
+      return set_error(CDCS_E_NOMEM, "autotune: hipMalloc failed");
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      release();
+      return set_error(CDCS_E_DEVICE, "autotune: hipEventCreate failed");
+    }
+    float best = 0.f;
+    int bestv = 0;
+    hipError_t e = hipMemcpyAsync(dsz, sz.data(), nb * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dtk, tk.data(), nb * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(doff, off.data(), nb * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(din, vals.data(), tot * 8, hipMemcpyHostToDevice, st);
+    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+      launch_psd_project(dsz, doff, dtk, nb, kmaxs[bk], din, dout, st, v, h->set.eig_fp32);   // warm-up
+      (void)hipEventRecord(e0, st);
+      for (int rep = 0; rep < kTuneReps; ++rep)
+        launch_psd_project(dsz, doff, dtk, nb, kmaxs[bk], din, dout, st, v, h->set.eig_fp32);
+      (void)hipEventRecord(e1, st);
+      e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && (v == 0 || ms < best)) {
+        best = ms;
+        bestv = v;
+      }
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    release();
+    if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    h->jvar[bk] = bestv;
+    h->jtuned[bk] = 1;
+  }
   return 0;
 }
 
@@ -523,6 +610,10 @@ int pack_and_upload(cdcs_handle* h) {
   for (int bkt = 0; bkt < 5; ++bkt) {
     h->ntasks[bkt] = (int32_t)bk[bkt].size();
     if ((rc = dev_upload(h, &h->tasks[bkt], bk[bkt]))) return rc;
+    if (bkt < 4) {
+      h->bucket_sizes[bkt].clear();
+      for (int32_t g : bk[bkt]) h->bucket_sizes[bkt].push_back(csize[g]);
+    }
   }
   // large-clique workspace: one K x K (column-major) matrix + eigen data per task
   h->large_sizes.clear();
@@ -568,6 +659,8 @@ void cdcs_default_settings(cdcs_settings* s) {
   s->check_every = 1;
   s->timing = 0;
   s->use_graph = 0;
+  s->eig_fp32 = 0;
+  s->autotune = 0;
 }
 
 int cdcs_abi_version(void) { return CDCS_ABI_VERSION; }
@@ -603,6 +696,8 @@ int cdcs_setup_batch(int32_t count, const cdcs_problem* prob, const cdcs_setting
   if (s) set = *s;
   if (!(set.eps_tol > 0.0) || set.max_iter < 1 || set.check_every < 1)
     return set_error(CDCS_E_ARG, "settings: need eps_tol > 0, max_iter >= 1, check_every >= 1");
+  if ((set.eig_fp32 != 0 && set.eig_fp32 != 1) || set.autotune < 0 || set.autotune > 2)
+    return set_error(CDCS_E_ARG, "settings: eig_fp32 must be 0 or 1 and autotune 0, 1 or 2");
   const auto t0 = std::chrono::steady_clock::now();
   cdcs_handle* h = new cdcs_handle();
   h->stream = (hipStream_t)stream;
@@ -640,6 +735,9 @@ int cdcs_setup_batch(int32_t count, const cdcs_problem* prob, const cdcs_setting
       return rc;
     }
   int rc = pack_and_upload(h);
+  if (!rc && h->set.autotune == 1) rc = autotune(h);
+  if (!rc && h->set.autotune == 2)
+    for (int b = 0; b < 4; ++b) h->jvar[b] = 1;
   if (rc) {
     cdcs_destroy(h);
     return rc;
@@ -1159,6 +1257,18 @@ int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32
   if (dC) HIPCHK(hipMemcpy(dC, a.dc, NE * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
   if (db) HIPCHK(hipMemcpy(db, a.db, M * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
   return 0;
+}
+
+int cdcs_get_tuning(const cdcs_handle* h, int32_t* out, int32_t cap) {
+  if (!h || !out || cap < 16) return set_error(CDCS_E_ARG, "cdcs_get_tuning: need a handle and 16 outputs");
+  const int kmaxs[4] = {16, 32, 64, kJacobiMax};
+  for (int b = 0; b < 4; ++b) {
+    out[4 * b + 0] = kmaxs[b];
+    out[4 * b + 1] = jacobi_threads(kmaxs[b], h->jvar[b]);
+    out[4 * b + 2] = h->ntasks[b];
+    out[4 * b + 3] = h->jtuned[b];
+  }
+  return 4;
 }
 
 int cdcs_get_phase_times(const cdcs_handle* h, const char** names, double* ms, int64_t* launches, int32_t cap) {

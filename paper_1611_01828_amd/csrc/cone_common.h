@@ -30,25 +30,28 @@ __device__ __forceinline__ void unpack_index(int t, int K, int& a, int& b) {
   a = bb + (t - packed_index(bb, bb, K));
 }
 
-// Symmetric Schur 2x2: (c, s, t) with t = tan(theta) annihilating A_pq.
-__device__ __forceinline__ void schur2(double app, double aqq, double apq, double& c, double& s,
-                                      double& t) {
-  if (apq == 0.0) {
-    c = 1.0;
-    s = 0.0;
-    t = 0.0;
+// Symmetric Schur 2x2: (c, s, t) with t = tan(theta) annihilating A_pq, in
+// the working precision T (above `big`, 1 + theta^2 would overflow and
+// t = 1 / (2 theta) to working accuracy).
+template <typename T>
+__device__ __forceinline__ void schur2(T app, T aqq, T apq, T& c, T& s, T& t) {
+  if (apq == T(0)) {
+    c = T(1);
+    s = T(0);
+    t = T(0);
     return;
   }
-  const double theta = (aqq - app) / (2.0 * apq);
-  const double at = fabs(theta);
-  double tt;
-  if (at > 1e150) {
-    tt = 0.5 / theta;
+  const T big = sizeof(T) == 8 ? T(1e150) : T(1e18);
+  const T theta = (aqq - app) / (T(2) * apq);
+  const T at = fabs(theta);
+  T tt;
+  if (at > big) {
+    tt = T(0.5) / theta;
   } else {
-    tt = 1.0 / (at + sqrt(1.0 + at * at));
-    if (theta < 0.0) tt = -tt;
+    tt = T(1) / (at + sqrt(T(1) + at * at));
+    if (theta < T(0)) tt = -tt;
   }
-  c = 1.0 / sqrt(1.0 + tt * tt);
+  c = T(1) / sqrt(T(1) + tt * tt);
   s = tt * c;
   t = tt;
 }
@@ -57,24 +60,28 @@ __device__ __forceinline__ void schur2(double app, double aqq, double apq, doubl
 
 using namespace jac;
 
-// Cyclic Jacobi on the KP x KP (KP even, zero padded) matrix in LDS.  On
-// return A holds the eigenvalues on its diagonal and V the eigenvectors.
-template <int KMAX, int NT>
-__device__ void jacobi_lds(double* A, double* V, int K, int KP, double* rc, double* rs, double* rt,
-                           int* rp, int* rq, double* red) {
+// Cyclic Jacobi on the KP x KP (KP even, zero padded) matrix in LDS, in the
+// working precision T (double, or float for the FP32 variant; the
+// convergence sums are kept in double).  On return A holds the eigenvalues
+// on its diagonal and V the eigenvectors.
+template <int KMAX, int NT, typename T = double>
+__device__ void jacobi_lds(T* A, T* V, int K, int KP, T* rc, T* rs, T* rt, int* rp, int* rq, double* red) {
   const int tid = threadIdx.x;
   const int half = KP / 2;
+  // off(A)^2 <= tol ||A||_F^2: (1e-16)^2 in FP64; in FP32 a little above
+  // (2^-23)^2 so that rounding cannot keep the sweeps going
+  const double tol = sizeof(T) == 8 ? 1e-32 : 1e-13;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int idx = tid; idx < K * K; idx += NT) {
       const int i = idx / K, j = idx - (idx / K) * K;
-      const double a = A[i * KMAX + j];
+      const double a = (double)A[i * KMAX + j];
       tot += a * a;
       if (i != j) off += a * a;
     }
     off = block_sum<NT>(off, red);
     tot = block_sum<NT>(tot, red);
-    if (!(off > 1e-32 * tot)) break;   // off(A) <= 1e-16 ||A||_F (also stops on 0 or NaN)
+    if (!(off > tol * tot)) break;   // also stops on 0 or NaN
     for (int r = 0; r < KP - 1; ++r) {
       if (tid < half) {
         int p, q;
@@ -90,8 +97,8 @@ __device__ void jacobi_lds(double* A, double* V, int K, int KP, double* rc, doub
           p = q;
           q = tmp;
         }
-        double c, s, t;
-        schur2(A[p * KMAX + p], A[q * KMAX + q], A[p * KMAX + q], c, s, t);
+        T c, s, t;
+        schur2<T>(A[p * KMAX + p], A[q * KMAX + q], A[p * KMAX + q], c, s, t);
         rp[tid] = p;
         rq[tid] = q;
         rc[tid] = c;
@@ -104,18 +111,18 @@ __device__ void jacobi_lds(double* A, double* V, int K, int KP, double* rc, doub
         const int a = idx / half, bq = idx - (idx / half) * half;
         const int pa = rp[a], qa = rq[a], pb = rp[bq], qb = rq[bq];
         if (a == bq) {
-          const double t = rt[a];
-          const double apq = A[pa * KMAX + qa];
+          const T t = rt[a];
+          const T apq = A[pa * KMAX + qa];
           A[pa * KMAX + pa] -= t * apq;
           A[qa * KMAX + qa] += t * apq;
-          A[pa * KMAX + qa] = 0.0;
-          A[qa * KMAX + pa] = 0.0;
+          A[pa * KMAX + qa] = T(0);
+          A[qa * KMAX + pa] = T(0);
         } else {
-          const double ca = rc[a], sa = rs[a], cb = rc[bq], sb = rs[bq];
-          const double x00 = A[pa * KMAX + pb], x01 = A[pa * KMAX + qb];
-          const double x10 = A[qa * KMAX + pb], x11 = A[qa * KMAX + qb];
-          const double y00 = ca * x00 - sa * x10, y01 = ca * x01 - sa * x11;
-          const double y10 = sa * x00 + ca * x10, y11 = sa * x01 + ca * x11;
+          const T ca = rc[a], sa = rs[a], cb = rc[bq], sb = rs[bq];
+          const T x00 = A[pa * KMAX + pb], x01 = A[pa * KMAX + qb];
+          const T x10 = A[qa * KMAX + pb], x11 = A[qa * KMAX + qb];
+          const T y00 = ca * x00 - sa * x10, y01 = ca * x01 - sa * x11;
+          const T y10 = sa * x00 + ca * x10, y11 = sa * x01 + ca * x11;
           A[pa * KMAX + pb] = y00 * cb - y01 * sb;
           A[pa * KMAX + qb] = y00 * sb + y01 * cb;
           A[qa * KMAX + pb] = y10 * cb - y11 * sb;
@@ -125,8 +132,8 @@ __device__ void jacobi_lds(double* A, double* V, int K, int KP, double* rc, doub
       for (int idx = tid; idx < KP * half; idx += NT) {
         const int i = idx / half, bq = idx - (idx / half) * half;
         const int pb = rp[bq], qb = rq[bq];
-        const double cb = rc[bq], sb = rs[bq];
-        const double vp = V[i * KMAX + pb], vq = V[i * KMAX + qb];
+        const T cb = rc[bq], sb = rs[bq];
+        const T vp = V[i * KMAX + pb], vq = V[i * KMAX + qb];
         V[i * KMAX + pb] = cb * vp - sb * vq;
         V[i * KMAX + qb] = sb * vp + cb * vq;
       }
@@ -138,16 +145,16 @@ __device__ void jacobi_lds(double* A, double* V, int K, int KP, double* rc, doub
 // Select the cheaper side of the spectrum: Pi_+(Y) = sum_{l>0} lam_l v v^T
 // = Y - sum_{l<0} lam_l v v^T.  Fills sel[0..nsel) and returns sign flag
 // (1 = positive side).  Runs on thread 0 only; result broadcast via LDS.
-template <int NT>
-__device__ void choose_side(const double* A, int K, int KMAX_, int* sel, int* meta) {
+template <int NT, typename T = double>
+__device__ void choose_side(const T* A, int K, int KMAX_, int* sel, int* meta) {
   if (threadIdx.x == 0) {
     int npos = 0;
-    for (int l = 0; l < K; ++l) npos += (A[l * KMAX_ + l] > 0.0);
+    for (int l = 0; l < K; ++l) npos += (A[l * KMAX_ + l] > T(0));
     const int pos = (npos <= K - npos) ? 1 : 0;
     int n = 0;
     for (int l = 0; l < K; ++l) {
-      const double lam = A[l * KMAX_ + l];
-      if (pos ? (lam > 0.0) : (lam < 0.0)) sel[n++] = l;
+      const T lam = A[l * KMAX_ + l];
+      if (pos ? (lam > T(0)) : (lam < T(0))) sel[n++] = l;
     }
     meta[0] = n;
     meta[1] = pos;

@@ -124,6 +124,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Block-wide sum in a fixed order (wave tree, then waves in order).
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* red) {
+  static_assert(NT >= 64 && NT % 64 == 0, "block_sum needs whole waves");
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
@@ -148,8 +149,13 @@ void launch_scalar1(const DevPlan& d, hipStream_t st);
 void launch_update_e(const DevPlan& d, hipStream_t st);
 void launch_update_r(const DevPlan& d, hipStream_t st);
 void launch_scalar2(const DevPlan& d, double eps_tol, int32_t max_iter, int32_t stop, hipStream_t st);
-// cone step: tasks are clique ids; kind selects the kernel variant
-void launch_cone_jacobi(const DevPlan& d, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st);
+// cone step: tasks are clique ids.  Jacobi tile shape per bucket: variant 0
+// = the default threads per clique, 1 = the other candidate (twice as many for
+// 16-vertex cliques, half as many otherwise); fp32 = 1 runs the
+// eigen-decomposition in FP32.
+int jacobi_threads(int kmax, int variant);
+void launch_cone_jacobi(const DevPlan& d, const int32_t* tasks, int32_t ntask, int kmax, int variant, int fp32,
+                        hipStream_t st);
 // large cliques: gather, tridiag, eig, backtrans, recon, partials
 constexpr int kLargeSteps = 6;
 // timing of the tridiagonalisation launches (kind 0 symv, 1 update,
@@ -165,7 +171,7 @@ void launch_cone_large_step(const DevPlan& d, const int32_t* tasks, int32_t ntas
                             const int32_t* host_sizes, int step, hipStream_t st, const LaunchHook* hook = nullptr);
 // stand-alone projection of packed blocks
 void launch_psd_project(const int32_t* sizes, const int64_t* offs, const int32_t* tasks, int32_t ntask,
-                        int kmax, const double* in, double* out, hipStream_t st);
+                        int kmax, const double* in, double* out, hipStream_t st, int variant = 0, int fp32 = 0);
 // tasks sorted by block order, descending; task_sizes (device) and
 // host_sizes (host) hold those orders
 void launch_psd_project_large(const int32_t* sizes, const int64_t* offs, const int32_t* tasks,

@@ -10,15 +10,21 @@
 //   s+  = Pi_+(Y) = V max(Lambda, 0) V^T
 //   z+  = z - u_s + s+ = s+ - Y
 // plus the partial sums ||H_k x+ - s+||^2 and ||v+ - z+||^2 for the residuals.
+//
+// T is the working precision of the eigen-decomposition (double, or float
+// for the FP32 variant): Y is gathered and s+, z+, v+ are formed in double,
+// and Pi_+(Y) = Y - sum_{lam<0} lam v v^T keeps Y exact when the negative
+// side is the smaller one.  NT (threads per clique) is the tile shape the
+// autotuner chooses per bucket.
 #include "cone_common.h"
 
 namespace cdcs {
 
-template <int KMAX, int NT>
+template <int KMAX, int NT, typename T>
 __global__ __launch_bounds__(NT) void k_cone_jacobi(DevPlan d, const int32_t* tasks) {
-  __shared__ double A[KMAX * KMAX];
-  __shared__ double V[KMAX * KMAX];
-  __shared__ double rc[KMAX / 2], rs[KMAX / 2], rt[KMAX / 2];
+  __shared__ T A[KMAX * KMAX];
+  __shared__ T V[KMAX * KMAX];
+  __shared__ T rc[KMAX / 2], rs[KMAX / 2], rt[KMAX / 2];
   __shared__ int rp[KMAX / 2], rq[KMAX / 2];
   __shared__ int sel[KMAX];
   __shared__ int meta[2];
@@ -41,12 +47,12 @@ __global__ __launch_bounds__(NT) void k_cone_jacobi(DevPlan d, const int32_t* ta
       yv = 0.5 * (d.s[sl] - d.z[sl] - d.v[sl] + xv);
       if (a != bq) yv *= kInvSqrt2;
     }
-    A[i * KMAX + j] = yv;
-    V[i * KMAX + j] = (i == j) ? 1.0 : 0.0;
+    A[i * KMAX + j] = (T)yv;
+    V[i * KMAX + j] = (i == j) ? T(1) : T(0);
   }
   __syncthreads();
-  jacobi_lds<KMAX, NT>(A, V, K, KP, rc, rs, rt, rp, rq, red);
-  choose_side<NT>(A, K, KMAX, sel, meta);
+  jacobi_lds<KMAX, NT, T>(A, V, K, KP, rc, rs, rt, rp, rq, red);
+  choose_side<NT, T>(A, K, KMAX, sel, meta);
   const int nsel = meta[0], pos = meta[1];
   // epilogue over packed slots
   const int nslot = K * (K + 1) / 2;
@@ -57,7 +63,7 @@ __global__ __launch_bounds__(NT) void k_cone_jacobi(DevPlan d, const int32_t* ta
     double acc = 0.0;
     for (int u = 0; u < nsel; ++u) {
       const int l = sel[u];
-      acc += V[a * KMAX + l] * A[l * KMAX + l] * V[bq * KMAX + l];
+      acc += (double)V[a * KMAX + l] * (double)A[l * KMAX + l] * (double)V[bq * KMAX + l];
     }
     const int64_t sl = s0 + t;
     const double sv = d.s[sl], zv = d.z[sl], vv = d.v[sl];
@@ -82,13 +88,13 @@ __global__ __launch_bounds__(NT) void k_cone_jacobi(DevPlan d, const int32_t* ta
 }
 
 // Stand-alone projection of packed blocks: out_k = svec(Pi_+(smat(in_k))).
-template <int KMAX, int NT>
+template <int KMAX, int NT, typename T>
 __global__ __launch_bounds__(NT) void k_psd_jacobi(const int32_t* sizes, const int64_t* offs,
                                                    const int32_t* tasks, const double* in,
                                                    double* out) {
-  __shared__ double A[KMAX * KMAX];
-  __shared__ double V[KMAX * KMAX];
-  __shared__ double rc[KMAX / 2], rs[KMAX / 2], rt[KMAX / 2];
+  __shared__ T A[KMAX * KMAX];
+  __shared__ T V[KMAX * KMAX];
+  __shared__ T rc[KMAX / 2], rs[KMAX / 2], rt[KMAX / 2];
   __shared__ int rp[KMAX / 2], rq[KMAX / 2];
   __shared__ int sel[KMAX];
   __shared__ int meta[2];
@@ -106,12 +112,12 @@ __global__ __launch_bounds__(NT) void k_psd_jacobi(const int32_t* sizes, const i
       yv = in[o + packed_index(a, bq, K)];
       if (a != bq) yv *= kInvSqrt2;
     }
-    A[i * KMAX + j] = yv;
-    V[i * KMAX + j] = (i == j) ? 1.0 : 0.0;
+    A[i * KMAX + j] = (T)yv;
+    V[i * KMAX + j] = (i == j) ? T(1) : T(0);
   }
   __syncthreads();
-  jacobi_lds<KMAX, NT>(A, V, K, KP, rc, rs, rt, rp, rq, red);
-  choose_side<NT>(A, K, KMAX, sel, meta);
+  jacobi_lds<KMAX, NT, T>(A, V, K, KP, rc, rs, rt, rp, rq, red);
+  choose_side<NT, T>(A, K, KMAX, sel, meta);
   const int nsel = meta[0], pos = meta[1];
   const int nslot = K * (K + 1) / 2;
   for (int t = tid; t < nslot; t += NT) {
@@ -120,7 +126,7 @@ __global__ __launch_bounds__(NT) void k_psd_jacobi(const int32_t* sizes, const i
     double acc = 0.0;
     for (int u = 0; u < nsel; ++u) {
       const int l = sel[u];
-      acc += V[a * KMAX + l] * A[l * KMAX + l] * V[bq * KMAX + l];
+      acc += (double)V[a * KMAX + l] * (double)A[l * KMAX + l] * (double)V[bq * KMAX + l];
     }
     const double sc = (a == bq) ? 1.0 : kSqrt2;
     const double yvec = in[o + t];
@@ -128,29 +134,67 @@ __global__ __launch_bounds__(NT) void k_psd_jacobi(const int32_t* sizes, const i
   }
 }
 
-void launch_cone_jacobi(const DevPlan& d, const int32_t* tasks, int32_t ntask, int kmax, hipStream_t st) {
-  if (ntask <= 0) return;
-  if (kmax <= 16)
-    hipLaunchKernelGGL((k_cone_jacobi<16, 64>), dim3(ntask), dim3(64), 0, st, d, tasks);
-  else if (kmax <= 32)
-    hipLaunchKernelGGL((k_cone_jacobi<32, 128>), dim3(ntask), dim3(128), 0, st, d, tasks);
-  else if (kmax <= 64)
-    hipLaunchKernelGGL((k_cone_jacobi<64, 256>), dim3(ntask), dim3(256), 0, st, d, tasks);
-  else
-    hipLaunchKernelGGL((k_cone_jacobi<96, 512>), dim3(ntask), dim3(512), 0, st, d, tasks);
+// tile shapes: (KMAX, threads per clique) candidates per bucket
+namespace {
+template <int KMAX, int NT, typename T>
+void cone_launch(const DevPlan& d, const int32_t* tasks, int32_t ntask, hipStream_t st) {
+  hipLaunchKernelGGL((k_cone_jacobi<KMAX, NT, T>), dim3(ntask), dim3(NT), 0, st, d, tasks);
+}
+template <int KMAX, int NT, typename T>
+void psd_launch(const int32_t* sizes, const int64_t* offs, const int32_t* tasks, int32_t ntask, const double* in,
+                double* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_psd_jacobi<KMAX, NT, T>), dim3(ntask), dim3(NT), 0, st, sizes, offs, tasks, in, out);
+}
+// the bucket of KMAX; every thread count is a whole number of waves (the
+// block reductions need it)
+int bucket_kmax(int kmax) { return kmax <= 16 ? 16 : kmax <= 32 ? 32 : kmax <= 64 ? 64 : 96; }
+}  // namespace
+
+int jacobi_threads(int kmax, int variant) {
+  switch (bucket_kmax(kmax)) {
+    case 16: return variant ? 128 : 64;
+    case 32: return variant ? 64 : 128;
+    case 64: return variant ? 128 : 256;
+    default: return variant ? 256 : 512;
+  }
 }
 
-void launch_psd_project(const int32_t* sizes, const int64_t* offs, const int32_t* tasks, int32_t ntask,
-                        int kmax, const double* in, double* out, hipStream_t st) {
+#define CDCS_CONE_DISPATCH(CALL, T)                       \
+  switch (bucket_kmax(kmax) * 2 + (variant ? 1 : 0)) {    \
+    case 32: CALL(16, 64, T); break;                      \
+    case 33: CALL(16, 128, T); break;                     \
+    case 64: CALL(32, 128, T); break;                     \
+    case 65: CALL(32, 64, T); break;                      \
+    case 128: CALL(64, 256, T); break;                    \
+    case 129: CALL(64, 128, T); break;                    \
+    case 192: CALL(96, 512, T); break;                    \
+    default: CALL(96, 256, T); break;                     \
+  }
+
+void launch_cone_jacobi(const DevPlan& d, const int32_t* tasks, int32_t ntask, int kmax, int variant, int fp32,
+                        hipStream_t st) {
   if (ntask <= 0) return;
-  if (kmax <= 16)
-    hipLaunchKernelGGL((k_psd_jacobi<16, 64>), dim3(ntask), dim3(64), 0, st, sizes, offs, tasks, in, out);
-  else if (kmax <= 32)
-    hipLaunchKernelGGL((k_psd_jacobi<32, 128>), dim3(ntask), dim3(128), 0, st, sizes, offs, tasks, in, out);
-  else if (kmax <= 64)
-    hipLaunchKernelGGL((k_psd_jacobi<64, 256>), dim3(ntask), dim3(256), 0, st, sizes, offs, tasks, in, out);
-  else
-    hipLaunchKernelGGL((k_psd_jacobi<96, 512>), dim3(ntask), dim3(512), 0, st, sizes, offs, tasks, in, out);
+#define CONE_CALL(KM, NTH, T) cone_launch<KM, NTH, T>(d, tasks, ntask, st)
+  if (fp32) {
+    CDCS_CONE_DISPATCH(CONE_CALL, float)
+  } else {
+    CDCS_CONE_DISPATCH(CONE_CALL, double)
+  }
+#undef CONE_CALL
 }
+
+void launch_psd_project(const int32_t* sizes, const int64_t* offs, const int32_t* tasks, int32_t ntask, int kmax,
+                        const double* in, double* out, hipStream_t st, int variant, int fp32) {
+  if (ntask <= 0) return;
+#define PSD_CALL(KM, NTH, T) psd_launch<KM, NTH, T>(sizes, offs, tasks, ntask, in, out, st)
+  if (fp32) {
+    CDCS_CONE_DISPATCH(PSD_CALL, float)
+  } else {
+    CDCS_CONE_DISPATCH(PSD_CALL, double)
+  }
+#undef PSD_CALL
+}
+
+#undef CDCS_CONE_DISPATCH
 
 }  // namespace cdcs

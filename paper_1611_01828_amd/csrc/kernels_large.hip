@@ -736,12 +736,12 @@ __device__ __forceinline__ void tri_factor(const double* d, const double* e, int
 
 // One inverse-iteration solve (T - lambda I) z_new = sc * z in place (z at
 // stride zs); returns 1 / ||z_new||.  Both sweeps are recurrences carried in
-// registers; the operands of 8 consecutive steps are loaded ahead (clamped
+// registers; the operands of C consecutive steps are loaded ahead (clamped
 // indices, no predicated loads) so that one lane's chain does not wait on
 // every load.
+template <int C>
 __device__ __forceinline__ double tri_solve(const double* __restrict__ f, int st, size_t KR, int K,
                                             double* __restrict__ z, int zs, double sc) {
-  constexpr int C = 8;
   // forward: P and the unit lower bidiagonal L
   double cur = z[0] * sc;
   for (int i0 = 0; i0 < K - 1; i0 += C) {
@@ -900,7 +900,51 @@ __global__ __launch_bounds__(64 * kBisEig) void k_eig_bisect(LargeArgs a) {
   if (lane == 0) w.lam[t] = 0.5 * (lo + hi);
 }
 
-// (c) eigenvectors of T for the chosen eigenvalues
+// Inverse iteration with a partially pivoted LU of T - lambda I.  The
+// factors of eigenvalue t live in the scratch area element-major (entry i of
+// array a at ((a * K + i) * r + t)), so lanes that work on consecutive
+// eigenvalues touch consecutive addresses; 6 K r <= 3 K^2 since r <= K / 2.
+// Eigenvalues closer than 1e-5 ||T|| to a neighbour form clusters.
+__device__ __forceinline__ double eig_ortol(double tnorm) { return 1e-5 * tnorm; }
+
+// (c) isolated eigenvalues: one lane each (64-lane workgroups, so the solves
+//     can keep 32 steps of operands in flight), two solves, the vector kept in
+//     the scratch area and normalised lazily.  Two solves suffice: lambda is
+//     accurate to ~eps ||T|| and its gap to the other eigenvalues is above
+//     1e-5 ||T||, so each solve shrinks the other components of a random start
+//     by ~1e-10 or more.
+template <bool ADMM>
+__global__ __launch_bounds__(64) void k_eig_single(LargeArgs a) {
+  __shared__ double sd[1024], se[1024];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int r = (int)w.meta[0];
+  const int t = blockIdx.y * 64 + threadIdx.x;
+  if (blockIdx.y * 64 >= r) return;
+  const double tnorm = w.meta[4];
+  for (int i = threadIdx.x; i < K; i += 64) {
+    sd[i] = w.d[i];
+    se[i] = (i < K - 1) ? w.e[i] : 0.0;
+  }
+  __syncthreads();
+  if (t >= r) return;
+  const double lam = w.lam[t], ortol = eig_ortol(tnorm);
+  const bool iso = (t == 0 || lam - w.lam[t - 1] > ortol) && (t == r - 1 || w.lam[t + 1] - lam > ortol);
+  if (!iso) return;
+  double* X = w.S;
+  const size_t KR = (size_t)K * r;
+  double* zt = X + 5 * KR + t;
+  tri_factor(sd, se, K, lam, kEps * tnorm, X + t, r, KR);
+  for (int i = 0; i < K; ++i) zt[(size_t)i * r] = hash_unit((uint32_t)t, (uint32_t)i);
+  double sc = 1.0;
+  for (int it = 0; it < 2; ++it) sc = tri_solve<32>(X + t, r, KR, K, zt, r, sc);
+  double* zo = w.Z + (size_t)t * K;
+  for (int i = 0; i < K; ++i) zo[i] = zt[(size_t)i * r] * sc;
+}
+
+// (d) eigenvectors of the clustered eigenvalues (the isolated ones are (c))
 template <bool ADMM>
 __global__ __launch_bounds__(kLT) void k_eig_vec(LargeArgs a) {
   __shared__ double sd[1024], se[1024];
@@ -921,7 +965,7 @@ __global__ __launch_bounds__(kLT) void k_eig_vec(LargeArgs a) {
   for (int t = tid; t < r; t += kLT) slam[t] = w.lam[t];
   __syncthreads();
   // clusters of close eigenvalues (consecutive gaps below the threshold)
-  const double ortol = 1e-5 * tnorm;
+  const double ortol = eig_ortol(tnorm);
   if (tid == 0) {
     int nc = 0;
     for (int t = 0; t < r; ++t)
@@ -932,39 +976,9 @@ __global__ __launch_bounds__(kLT) void k_eig_vec(LargeArgs a) {
   __syncthreads();
   const int ncl = info[3];
   const double tiny = kEps * tnorm;
-  // Inverse iteration with a partially pivoted LU of T - lambda I.  The
-  // factors of eigenvalue t live in the scratch area element-major
-  // (entry i of array a at ((a * K + i) * r + t)), so lanes that work on
-  // consecutive eigenvalues touch consecutive addresses; 6 K r <= 3 K^2
-  // since r <= K / 2.
   double* X = w.S;
   const size_t KR = (size_t)K * r;
-  // (a) isolated eigenvalues: one lane each, two solves, the vector kept in
-  //     the scratch area and normalised lazily
-  for (int t = tid; t < r; t += kLT) {
-    int c = 0;
-    {
-      int lo = 0, hi = ncl;   // cluster of t: largest c with cls[c] <= t
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (cls[mid] <= t) lo = mid;
-        else hi = mid;
-      }
-      c = lo;
-    }
-    if (cls[c + 1] - cls[c] != 1) continue;
-    double* zt = X + 5 * KR + t;
-    tri_factor(sd, se, K, slam[t], tiny, X + t, r, KR);
-    for (int i = 0; i < K; ++i) zt[(size_t)i * r] = hash_unit((uint32_t)t, (uint32_t)i);
-    // two solves: lambda is accurate to ~eps ||T|| and its gap to the other
-    // eigenvalues is above 1e-5 ||T||, so each solve shrinks the other
-    // components of a random start by ~1e-10 or more
-    double sc = 1.0;
-    for (int it = 0; it < 2; ++it) sc = tri_solve(X + t, r, KR, K, zt, r, sc);
-    double* zo = w.Z + (size_t)t * K;
-    for (int i = 0; i < K; ++i) zo[i] = zt[(size_t)i * r] * sc;
-  }
-  // (b) clusters: one wave each; lane 0 runs the sequential solves on the
+  // clusters: one wave each; lane 0 runs the sequential solves on the
   //     member's column of Z, the wave orthogonalises it against the
   //     cluster's earlier members (twice) and normalises it
   {
@@ -977,7 +991,7 @@ __global__ __launch_bounds__(kLT) void k_eig_vec(LargeArgs a) {
         for (int i = lane; i < K; i += 64) z[i] = hash_unit((uint32_t)t, (uint32_t)i);
         for (int it = 0; it < 3; ++it) {
           __threadfence_block();
-          if (lane == 0) (void)tri_solve(X + t, r, KR, K, z, 1, 1.0);
+          if (lane == 0) (void)tri_solve<8>(X + t, r, KR, K, z, 1, 1.0);
           __threadfence_block();
           for (int pass = 0; pass < 2; ++pass)
             for (int p = cls[c]; p < t; ++p) {
@@ -1286,6 +1300,7 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
       hipLaunchKernelGGL(k_eig_prep<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
       hipLaunchKernelGGL(k_eig_bisect<ADMM>, dim3(ntask, (rmax + kBisEig - 1) / kBisEig), dim3(64 * kBisEig), 0, st,
                          a);
+      hipLaunchKernelGGL(k_eig_single<ADMM>, dim3(ntask, (rmax + 63) / 64), dim3(64), 0, st, a);
       hipLaunchKernelGGL(k_eig_vec<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
       break;
     case 3:
