@@ -253,54 +253,85 @@ def main():
 
 
 def bench_batch(args, cdcs, configs):
-    """Config 3: one batched handle for all instances vs one handle per instance."""
+    """Config 3: one batched handle for all instances vs one handle per instance;
+    FP64 with the default and the autotuned Jacobi tiles, and the FP32-eigensolve
+    variant with its errors against FP64."""
     import numpy as np
     import torch
     t0 = time.perf_counter()
     insts = configs.config3()
     print(f"[bench] 256 block-arrow instances generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    s = cdcs.Solver(insts, timing=1)
-    setup_s = time.perf_counter() - t0
-    print(f"[bench] batched setup {setup_s:.1f}s", file=sys.stderr, flush=True)
-    s.iterate(args.warmup)
-    s.reset_phase_times()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.iterate(args.steps)
-    dt = time.perf_counter() - t0
-    phases = s.phase_times()
-    batched = len(insts) * args.steps / dt
-    print(f"[bench] batched: {batched:.0f} instance-iterations/s", file=sys.stderr, flush=True)
+
+    def run(label, **settings):
+        t0 = time.perf_counter()
+        s = cdcs.Solver(insts, use_graph=1, **settings)
+        setup = time.perf_counter() - t0
+        s.iterate(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(args.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tuning = s.tuning()
+        s.close()
+        f = cdcs.Solver(insts, check_every=10, use_graph=1, **settings)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = f.solve()
+        tsolve = time.perf_counter() - t0
+        f.close()
+        st = {}
+        for x in infos:
+            st[cdcs.STATUS_NAMES[x["status"]]] = st.get(cdcs.STATUS_NAMES[x["status"]], 0) + 1
+        rate = len(insts) * args.steps / dt
+        print(f"[bench] {label}: {rate:.0f} instance-iterations/s, solve {tsolve:.2f}s {st}", file=sys.stderr,
+              flush=True)
+        return {"value": round(rate, 1), "ms_per_step": round(1e3 * dt / args.steps, 4), "setup_s": round(setup, 2),
+                "time_to_1e-4": {"seconds": round(tsolve, 3), "max_iterations": max(x["iter"] for x in infos),
+                                 "status_counts": st},
+                "tuning": [{"kmax": b["kmax"], "threads": b["threads"], "cliques": b["cliques"]} for b in tuning]}, infos
+
+    fp64, inf64 = run("FP64, default tiles")
+    tuned, _ = run("FP64, autotuned tiles", autotune=1)
+    fp32, inf32 = run("FP32 eigensolves, autotuned tiles", eig_fp32=1, autotune=1)
+    # FP32 against FP64 on every instance that both solved
+    both = [i for i in range(len(insts)) if inf64[i]["status"] == cdcs.SOLVED and inf32[i]["status"] == cdcs.SOLVED]
+    rel = [abs(inf32[i]["obj_p"] - inf64[i]["obj_p"]) / max(1.0, abs(inf64[i]["obj_p"])) for i in both]
+    dit = [inf32[i]["iter"] - inf64[i]["iter"] for i in both]
+    fp32["vs_fp64"] = {"instances": len(both), "obj_rel_max": float(max(rel)), "obj_rel_median": float(np.median(rel)),
+                       "iter_delta_mean": float(np.mean(dit)), "iter_delta_max_abs": int(max(abs(d) for d in dit)),
+                       "eps_p_max": float(max(inf32[i]["eps_p"] for i in both)),
+                       "eps_d_max": float(max(inf32[i]["eps_d"] for i in both))}
+    # and against the FP64 oracle on the two smallest instances
+    from oracle import hsde
+    small = sorted(range(len(insts)), key=lambda i: insts[i].n)[:2]
+    orc = []
+    for i in small:
+        ref = hsde.solve(insts[i])
+        o = hsde.recover(ref)["obj_p"] if ref.status == hsde.SOLVED else float("nan")
+        orc.append({"instance": i, "n": insts[i].n, "oracle_iters": ref.iters, "fp32_iters": inf32[i]["iter"],
+                    "fp64_iters": inf64[i]["iter"], "obj_rel_fp32_vs_oracle": abs(inf32[i]["obj_p"] - o) / max(1.0, abs(o)),
+                    "obj_rel_fp64_vs_oracle": abs(inf64[i]["obj_p"] - o) / max(1.0, abs(o))})
+    fp32["vs_oracle"] = orc
+    print(f"[bench] FP32 vs FP64: {fp32['vs_fp64']}; vs oracle: {orc}", file=sys.stderr, flush=True)
     # plain path: a sample of instances, one handle each, same number of steps
     sample = insts[::16]
     plain_t = 0.0
     for inst in sample:
-        p = cdcs.Solver(inst)
+        p = cdcs.Solver(inst, use_graph=1)
         p.iterate(args.warmup)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         p.iterate(args.steps)
+        torch.cuda.synchronize()
         plain_t += time.perf_counter() - t1
         p.close()
     plain = len(sample) * args.steps / plain_t
     print(f"[bench] plain per instance: {plain:.0f} instance-iterations/s", file=sys.stderr, flush=True)
-    fresh = cdcs.Solver(insts, check_every=10)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = fresh.solve()
-    tsolve = time.perf_counter() - t0
-    st = {}
-    for f in infos:
-        st[cdcs.STATUS_NAMES[f["status"]]] = st.get(cdcs.STATUS_NAMES[f["status"]], 0) + 1
-    per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()}
-    out = {"metric": "batched instance-iterations/s (256 block-arrow SDPs)", "value": round(batched, 1),
-           "unit": "instance-iter/s", "plain_value": round(plain, 1), "speedup_vs_plain": round(batched / plain, 2),
-           "steps": args.steps, "ms_per_step": round(1e3 * dt / args.steps, 4), "dtype": "f64",
-           "time_to_1e-4": {"seconds": round(tsolve, 3), "max_iterations": max(f["iter"] for f in infos),
-                            "status_counts": st},
-           "setup_s": round(setup_s, 2),
-           "phases_ms_per_launch": {k: round(v, 4) for k, v in per_launch.items() if phases[k][1]}}
+    out = {"metric": "batched instance-iterations/s (256 block-arrow SDPs)", "value": fp64["value"],
+           "unit": "instance-iter/s", "plain_value": round(plain, 1),
+           "speedup_vs_plain": round(fp64["value"] / plain, 2), "steps": args.steps, "dtype": "f64",
+           "fp64": fp64, "fp64_autotuned": tuned, "fp32_eig_autotuned": fp32}
     print(json.dumps(out))
 
 
@@ -323,20 +354,37 @@ def bench_grad(args, cdcs, configs):
         dX.append(v)
     dX = np.concatenate(dX)
     s.close()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    f = cdcs.Solver(insts, check_every=10)
-    infos = f.solve()
-    tf = time.perf_counter() - t0
+
+    def run(**settings):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = cdcs.Solver(insts, check_every=10, use_graph=1, **settings)
+        infos = f.solve()
+        tf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        dc, db, it = f.adjoint(dX, max_iter=20000, tol=1e-10)
+        tb = time.perf_counter() - t0
+        f.close()
+        return infos, tf, tb, dc, db, it
+
+    infos, tf, tb, dc, db, it = run()
     nsolved = sum(1 for x in infos if x["status"] == cdcs.SOLVED)
-    t0 = time.perf_counter()
-    dc, db, it = f.adjoint(dX, max_iter=20000, tol=1e-10)
-    tb = time.perf_counter() - t0
+    print(f"[bench] FP64: forward {tf:.3f}s backward {tb:.3f}s ({it} GMRES applications)", file=sys.stderr,
+          flush=True)
+    # FP32-eigensolve forward (the adjoint's eigen-cache stays FP64)
+    inf32, tf32, tb32, dc32, db32, it32 = run(eig_fp32=1)
+    fp32 = {"forward_s": round(tf32, 3), "backward_s": round(tb32, 3), "adjoint_iterations": it32,
+            "solved": sum(1 for x in inf32 if x["status"] == cdcs.SOLVED),
+            "grad_c_rel_vs_fp64": float(np.linalg.norm(dc32 - dc) / np.linalg.norm(dc)),
+            "grad_b_rel_vs_fp64": float(np.linalg.norm(db32 - db) / np.linalg.norm(db)),
+            "value": round(1.0 / (tf32 + tb32), 4)}
+    print(f"[bench] FP32 eig forward: {fp32}", file=sys.stderr, flush=True)
     out = {"metric": "differentiated batch (64 SDPs): forward+backward per second vs forward only",
            "value": round(1.0 / (tf + tb), 4), "unit": "batches/s", "forward_only": round(1.0 / tf, 4),
            "forward_s": round(tf, 3), "backward_s": round(tb, 3), "adjoint_iterations": it,
            "forward_iterations_max": max(x["iter"] for x in infos), "solved": nsolved, "dtype": "f64",
-           "grad_norm_c": float(np.linalg.norm(dc)), "grad_norm_b": float(np.linalg.norm(db))}
+           "grad_norm_c": float(np.linalg.norm(dc)), "grad_norm_b": float(np.linalg.norm(db)),
+           "fp32_eig_forward": fp32}
     print(json.dumps(out))
 
 
