@@ -112,7 +112,7 @@ struct DevPlan {
 inline int64_t large_work_size(int K) {
   const int64_t T = (K + 31) / 32;
   const int64_t ld = (K + 7) & ~7;
-  return 5LL * ld * ld + 4LL * ld + 16 + T * (T + 1) + 64;
+  return 5LL * ld * ld + 5LL * ld + 16 + T * (T + 1) + 64;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

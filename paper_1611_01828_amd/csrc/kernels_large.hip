@@ -49,7 +49,8 @@ struct Ws {
   double* e;     // ld    off-diagonal of T
   double* tau;   // ld    reflector scalars
   double* lam;   // ld    chosen eigenvalues
-  double* meta;  // 16    [0] r, [1] 1 = positive side
+  double* zs;    // ld    scale of each eigenvector column of Z (1 / its norm)
+  double* meta;  // 16    [0] r, [1] 1 = positive side, [2] first, [3] pivmin, [4] ||T||
   double* tiles; // 2 * ntiles partial sums
 };
 
@@ -66,7 +67,8 @@ __device__ __forceinline__ Ws ws_of(double* base, int K) {
   w.e = w.d + ld;
   w.tau = w.e + ld;
   w.lam = w.tau + ld;
-  w.meta = w.lam + ld;
+  w.zs = w.lam + ld;
+  w.meta = w.zs + ld;
   w.tiles = w.meta + 16;
   return w;
 }
@@ -740,8 +742,12 @@ __device__ __forceinline__ void tri_factor(const double* d, const double* e, int
 // indices, no predicated loads) so that one lane's chain does not wait on
 // every load.
 template <int C>
-__device__ __forceinline__ double tri_solve(const double* __restrict__ f, int st, size_t KR, int K,
-                                            double* __restrict__ z, int zs, double sc) {
+__device__ __forceinline__ double tri_solve(const double* __restrict__ f, int st, size_t KR, int K, double* z,
+                                            int zs, double sc, double* zo = nullptr, int zos = 0) {
+  if (!zo) {
+    zo = z;
+    zos = zs;
+  }
   // forward: P and the unit lower bidiagonal L
   double cur = z[0] * sc;
   for (int i0 = 0; i0 < K - 1; i0 += C) {
@@ -784,7 +790,7 @@ __device__ __forceinline__ double tri_solve(const double* __restrict__ f, int st
       const int i = i0 - j;
       if (i >= 0) {
         const double zi = (zv[j] - u1[j] * z1 - u2[j] * z2) * r0[j];
-        z[(size_t)i * zs] = zi;
+        zo[(size_t)i * zos] = zi;
         nn += zi * zi;
         z2 = z1;
         z1 = zi;
@@ -907,41 +913,43 @@ __global__ __launch_bounds__(64 * kBisEig) void k_eig_bisect(LargeArgs a) {
 // Eigenvalues closer than 1e-5 ||T|| to a neighbour form clusters.
 __device__ __forceinline__ double eig_ortol(double tnorm) { return 1e-5 * tnorm; }
 
-// (c) isolated eigenvalues: one lane each (64-lane workgroups, so the solves
-//     can keep 32 steps of operands in flight), two solves, the vector kept in
-//     the scratch area and normalised lazily.  Two solves suffice: lambda is
-//     accurate to ~eps ||T|| and its gap to the other eigenvalues is above
-//     1e-5 ||T||, so each solve shrinks the other components of a random start
-//     by ~1e-10 or more.
+// (c) isolated eigenvalues: kSingle per workgroup, one lane each, with the
+//     LU factors and the iterate of each in LDS (6 K doubles per eigenvalue),
+//     so the sequential sweeps never wait on global memory; two solves, the
+//     second writing the eigenvector straight into its column of Z (its
+//     normalisation is applied by the back-transformation).  Two solves
+//     suffice: lambda is accurate to ~eps ||T|| and its gap to the other
+//     eigenvalues is above 1e-5 ||T||, so each solve shrinks the other
+//     components of a random start by ~1e-10 or more.
+constexpr int kSingle = 2;
 template <bool ADMM>
 __global__ __launch_bounds__(64) void k_eig_single(LargeArgs a) {
   __shared__ double sd[1024], se[1024];
+  __shared__ double F[kSingle][6 * 1024];
   int K;
   int64_t base;
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const int r = (int)w.meta[0];
-  const int t = blockIdx.y * 64 + threadIdx.x;
-  if (blockIdx.y * 64 >= r) return;
+  if (blockIdx.y * kSingle >= r) return;
   const double tnorm = w.meta[4];
   for (int i = threadIdx.x; i < K; i += 64) {
     sd[i] = w.d[i];
     se[i] = (i < K - 1) ? w.e[i] : 0.0;
   }
   __syncthreads();
-  if (t >= r) return;
+  const int t = blockIdx.y * kSingle + threadIdx.x;
+  if (threadIdx.x >= kSingle || t >= r) return;
   const double lam = w.lam[t], ortol = eig_ortol(tnorm);
   const bool iso = (t == 0 || lam - w.lam[t - 1] > ortol) && (t == r - 1 || w.lam[t + 1] - lam > ortol);
   if (!iso) return;
-  double* X = w.S;
-  const size_t KR = (size_t)K * r;
-  double* zt = X + 5 * KR + t;
-  tri_factor(sd, se, K, lam, kEps * tnorm, X + t, r, KR);
-  for (int i = 0; i < K; ++i) zt[(size_t)i * r] = hash_unit((uint32_t)t, (uint32_t)i);
-  double sc = 1.0;
-  for (int it = 0; it < 2; ++it) sc = tri_solve<32>(X + t, r, KR, K, zt, r, sc);
-  double* zo = w.Z + (size_t)t * K;
-  for (int i = 0; i < K; ++i) zo[i] = zt[(size_t)i * r] * sc;
+  double* f = F[threadIdx.x];    // arrays a = 0..4 at f[a K + i], the iterate at f[5 K + i]
+  double* z = f + 5 * K;
+  tri_factor(sd, se, K, lam, kEps * tnorm, f, 1, (size_t)K);
+  for (int i = 0; i < K; ++i) z[i] = hash_unit((uint32_t)t, (uint32_t)i);
+  double sc = tri_solve<8>(f, 1, (size_t)K, K, z, 1, 1.0);
+  sc = tri_solve<8>(f, 1, (size_t)K, K, z, 1, sc, w.Z + (size_t)t * K, 1);
+  w.zs[t] = sc;
 }
 
 // (d) eigenvectors of the clustered eigenvalues (the isolated ones are (c))
@@ -1006,6 +1014,7 @@ __global__ __launch_bounds__(kLT) void k_eig_vec(LargeArgs a) {
           const double sc = 1.0 / sqrt(wave_sum(nn));
           for (int i = lane; i < K; i += 64) z[i] *= sc;
         }
+        if (lane == 0) w.zs[t] = 1.0;
       }
     }
   }
@@ -1020,7 +1029,7 @@ __global__ __launch_bounds__(kLT) void k_eig_vec(LargeArgs a) {
 //    Q Z = B_0 (B_1 (... B_{P-1} Z)).
 // ---------------------------------------------------------------------------
 constexpr int kBtNC = 8;     // eigenvectors per apply workgroup, resident in LDS
-constexpr int kBtCR = 128;   // rows of a staged V panel chunk
+constexpr int kBtCR = 256;   // rows of a staged V panel chunk
 
 // element (row, a) of V_p: v_{j0+a} has 1 on row j0+a+1 and the stored
 // Householder vector below it
@@ -1092,7 +1101,7 @@ __global__ __launch_bounds__(1024) void k_bt_apply(LargeArgs a) {
   const int tid = threadIdx.x;
   for (int idx = tid; idx < kBtNC * K; idx += 1024) {
     const int cl = idx / K, row = idx - cl * K;
-    Zs[cl][row] = (cl < nc) ? w.Z[(size_t)(c0 + cl) * K + row] : 0.0;
+    Zs[cl][row] = (cl < nc) ? w.Z[(size_t)(c0 + cl) * K + row] * w.zs[c0 + cl] : 0.0;
   }
   const int a1 = tid & 31, cl1 = (tid >> 5) & 7, h1 = tid >> 8;   // pass 1: S(a, cl), row phase h
   const int rl3 = tid & 127, cl3 = tid >> 7;                        // pass 2: Z(row, cl)
@@ -1130,12 +1139,15 @@ __global__ __launch_bounds__(1024) void k_bt_apply(LargeArgs a) {
         Vc[rl][as] = bt_v(w.W, ld, K, j0, nbp, as, row0 + rl);
       }
       __syncthreads();
-      const int row = row0 + rl3;
-      if (row < K) {
-        double t = 0.0;
+#pragma unroll
+      for (int hh = 0; hh < kBtCR / 128; ++hh) {
+        const int rr = hh * 128 + rl3, row = row0 + rr;
+        if (row < K) {
+          double t = 0.0;
 #pragma unroll 8
-        for (int aa = 0; aa < 32; ++aa) t += Vc[rl3][aa] * Sq[aa][cl3];
-        Zs[cl3][row] -= t;
+          for (int aa = 0; aa < 32; ++aa) t += Vc[rr][aa] * Sq[aa][cl3];
+          Zs[cl3][row] -= t;
+        }
       }
       __syncthreads();
     }
@@ -1300,7 +1312,7 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
       hipLaunchKernelGGL(k_eig_prep<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
       hipLaunchKernelGGL(k_eig_bisect<ADMM>, dim3(ntask, (rmax + kBisEig - 1) / kBisEig), dim3(64 * kBisEig), 0, st,
                          a);
-      hipLaunchKernelGGL(k_eig_single<ADMM>, dim3(ntask, (rmax + 63) / 64), dim3(64), 0, st, a);
+      hipLaunchKernelGGL(k_eig_single<ADMM>, dim3(ntask, (rmax + kSingle - 1) / kSingle), dim3(64), 0, st, a);
       hipLaunchKernelGGL(k_eig_vec<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
       break;
     case 3:
