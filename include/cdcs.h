@@ -15,9 +15,10 @@
  *    given as lower-triangular COO (row >= col); an off-diagonal entry (i,j)
  *    stands for both X_ij and X_ji.  Duplicate entries are summed.
  *  - Cliques: p vertex lists in CSR form (clique_ptr[p+1], clique_vtx), each
- *    list strictly increasing (the natural order of Section 2.1).  Every
- *    vertex must lie in some clique and every data entry inside some
- *    C_k x C_k (the chordal pattern E').  The optional clique_parent array
+ *    list strictly increasing (the natural order of Section 2.1) and of at
+ *    most 1024 vertices (CDCS_E_CLIQUES otherwise).  Every vertex must lie in
+ *    some clique and every data entry inside some C_k x C_k (the chordal
+ *    pattern E').  At most 8192 constraints per instance (CDCS_E_ARG).  The optional clique_parent array
  *    (p entries, -1 = root) is checked for the running-intersection
  *    property.  Chordal extension and clique-tree construction are done by
  *    the caller on the host.
