@@ -68,14 +68,16 @@ int set_error(int code, const std::string& msg) {
 enum Phase {
   PH_R0 = 0, PH_SPMV_A, PH_TRSV, PH_SPMV_AT, PH_SCALAR1, PH_UPDATE_E, PH_UPDATE_R,
   PH_CONE16, PH_CONE32, PH_CONE64, PH_CONE96, PH_LG_GATHER, PH_LG_TRD_SYMV, PH_LG_TRD_UPDATE, PH_LG_TRD_TRAIL,
-  PH_LG_TRD_TAIL, PH_LG_EIG, PH_LG_BACKTRANS, PH_LG_RECON, PH_LG_PARTIALS, PH_SCALAR2, kNumPhases
+  PH_LG_TRD_TAIL, PH_LG_EIG_PREP, PH_LG_EIG_BISECT, PH_LG_EIG_SINGLE, PH_LG_EIG_CLUSTER, PH_LG_BT_TFACTOR,
+  PH_LG_BT_APPLY, PH_LG_RECON, PH_LG_PARTIALS, PH_SCALAR2, kNumPhases
 };
 const char* kPhaseNames[kNumPhases] = {
     "r0_scatter", "spmv_A", "trsv", "spmv_At", "scalar1", "update_x", "update_y",
     "cone_jacobi16", "cone_jacobi32", "cone_jacobi64", "cone_jacobi96", "large_gather", "trd_symv",
-    "trd_update", "trd_trail", "trd_tail", "large_eig", "large_backtrans", "large_recon", "large_partials", "scalar2"};
+    "trd_update", "trd_trail", "trd_tail", "eig_prep", "eig_bisect", "eig_single", "eig_cluster", "bt_tfactor",
+    "bt_apply", "large_recon", "large_partials", "scalar2"};
 // phase of each large-clique step (the tridiagonalisation is timed per launch kind)
-const int kLargeStepPhase[kLargeSteps] = {PH_LG_GATHER, -1, PH_LG_EIG, PH_LG_BACKTRANS, PH_LG_RECON, PH_LG_PARTIALS};
+const int kLargeStepPhase[kLargeSteps] = {PH_LG_GATHER, -1, -1, -1, PH_LG_RECON, PH_LG_PARTIALS};
 
 }  // namespace
 

@@ -158,9 +158,11 @@ void launch_cone_jacobi(const DevPlan& d, const int32_t* tasks, int32_t ntask, i
                         hipStream_t st);
 // large cliques: gather, tridiag, eig, backtrans, recon, partials
 constexpr int kLargeSteps = 6;
-// timing of the tridiagonalisation launches (kind 0 symv, 1 update,
-// 2 trailing update, 3 tail in LDS): begin() hands out an event pair that
-// the launch itself records (the kernel's own start and end), end() files it
+// timing of the large-clique launches (kind 0 symv, 1 update, 2 trailing
+// update, 3 tail in LDS, 4 eigen prep, 5 bisection, 6 isolated vectors,
+// 7 clustered vectors, 8 WY factors, 9 back-transformation): begin() hands
+// out an event pair that the launch itself records (the kernel's own start
+// and end), end() files it
 struct LaunchHook {
   void (*begin)(void* ctx, int kind, hipEvent_t* start, hipEvent_t* stop);
   void (*end)(void* ctx, int kind);

@@ -714,7 +714,8 @@ __device__ __forceinline__ void tri_factor(const double* d, const double* e, int
     double a0 = al;
     if (!piv && fabs(a0) < tiny) a0 = (a0 < 0.0) ? -tiny : tiny;
     const double u0 = piv ? cc : a0;
-    const double r0 = 1.0 / u0;
+    const double au = fabs(u0);
+    const double r0 = (au > 1e-290 && au < 1e290) ? rcp_nr(u0) : 1.0 / u0;
     const double l = (piv ? al : cc) * r0;
     const size_t o = (size_t)i * st;
     f[o] = l;
@@ -921,7 +922,12 @@ __device__ __forceinline__ double eig_ortol(double tnorm) { return 1e-5 * tnorm;
 //     suffice: lambda is accurate to ~eps ||T|| and its gap to the other
 //     eigenvalues is above 1e-5 ||T||, so each solve shrinks the other
 //     components of a random start by ~1e-10 or more.
+//     The LDS-resident form (114 KB per workgroup) suits tasks with few chosen
+//     eigenvalues; tasks with more than kSingleLds of them use the wide form
+//     below (64 eigenvalues per workgroup, factors in the element-major global
+//     scratch), which keeps many more workgroups per CU.
 constexpr int kSingle = 2;
+constexpr int kSingleLds = 32;
 template <bool ADMM>
 __global__ __launch_bounds__(64) void k_eig_single(LargeArgs a) {
   __shared__ double sd[1024], se[1024];
@@ -931,7 +937,7 @@ __global__ __launch_bounds__(64) void k_eig_single(LargeArgs a) {
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const int r = (int)w.meta[0];
-  if (blockIdx.y * kSingle >= r) return;
+  if (r > kSingleLds || blockIdx.y * kSingle >= r) return;
   const double tnorm = w.meta[4];
   for (int i = threadIdx.x; i < K; i += 64) {
     sd[i] = w.d[i];
@@ -952,71 +958,113 @@ __global__ __launch_bounds__(64) void k_eig_single(LargeArgs a) {
   w.zs[t] = sc;
 }
 
-// (d) eigenvectors of the clustered eigenvalues (the isolated ones are (c))
 template <bool ADMM>
-__global__ __launch_bounds__(kLT) void k_eig_vec(LargeArgs a) {
+__global__ __launch_bounds__(64) void k_eig_single_wide(LargeArgs a) {
   __shared__ double sd[1024], se[1024];
-  __shared__ double slam[512];
-  __shared__ int cls[513];
-  __shared__ int info[4];
   int K;
   int64_t base;
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
-  const int tid = threadIdx.x;
   const int r = (int)w.meta[0];
+  if (r <= kSingleLds || blockIdx.y * 64 >= r) return;
   const double tnorm = w.meta[4];
-  for (int i = tid; i < K; i += kLT) {
+  for (int i = threadIdx.x; i < K; i += 64) {
     sd[i] = w.d[i];
     se[i] = (i < K - 1) ? w.e[i] : 0.0;
   }
-  for (int t = tid; t < r; t += kLT) slam[t] = w.lam[t];
   __syncthreads();
-  // clusters of close eigenvalues (consecutive gaps below the threshold)
-  const double ortol = eig_ortol(tnorm);
-  if (tid == 0) {
-    int nc = 0;
-    for (int t = 0; t < r; ++t)
-      if (t == 0 || slam[t] - slam[t - 1] > ortol) cls[nc++] = t;
-    cls[nc] = r;
-    info[3] = nc;
-  }
-  __syncthreads();
-  const int ncl = info[3];
-  const double tiny = kEps * tnorm;
+  const int t = blockIdx.y * 64 + threadIdx.x;
+  if (t >= r) return;
+  const double lam = w.lam[t], ortol = eig_ortol(tnorm);
+  const bool iso = (t == 0 || lam - w.lam[t - 1] > ortol) && (t == r - 1 || w.lam[t + 1] - lam > ortol);
+  if (!iso) return;
+  // element-major scratch: entry i of array a of eigenvalue t at (a K + i) r + t
   double* X = w.S;
   const size_t KR = (size_t)K * r;
-  // clusters: one wave each; lane 0 runs the sequential solves on the
-  //     member's column of Z, the wave orthogonalises it against the
-  //     cluster's earlier members (twice) and normalises it
-  {
-    const int wid = tid >> 6, lane = tid & 63;
-    for (int c = wid; c < ncl; c += kLT / 64) {
-      if (cls[c + 1] - cls[c] < 2) continue;
-      for (int t = cls[c]; t < cls[c + 1]; ++t) {
-        double* z = w.Z + (size_t)t * K;
-        if (lane == 0) tri_factor(sd, se, K, slam[t], tiny, X + t, r, KR);
-        for (int i = lane; i < K; i += 64) z[i] = hash_unit((uint32_t)t, (uint32_t)i);
-        for (int it = 0; it < 3; ++it) {
-          __threadfence_block();
-          if (lane == 0) (void)tri_solve<8>(X + t, r, KR, K, z, 1, 1.0);
-          __threadfence_block();
-          for (int pass = 0; pass < 2; ++pass)
-            for (int p = cls[c]; p < t; ++p) {
-              const double* q = w.Z + (size_t)p * K;
-              double dot = 0.0;
-              for (int i = lane; i < K; i += 64) dot += q[i] * z[i];
-              dot = wave_sum(dot);
-              for (int i = lane; i < K; i += 64) z[i] -= dot * q[i];
-            }
-          double nn = 0.0;
-          for (int i = lane; i < K; i += 64) nn += z[i] * z[i];
-          const double sc = 1.0 / sqrt(wave_sum(nn));
-          for (int i = lane; i < K; i += 64) z[i] *= sc;
+  double* zt = X + 5 * KR + t;
+  tri_factor(sd, se, K, lam, kEps * tnorm, X + t, r, KR);
+  for (int i = 0; i < K; ++i) zt[(size_t)i * r] = hash_unit((uint32_t)t, (uint32_t)i);
+  double sc = tri_solve<32>(X + t, r, KR, K, zt, r, 1.0);
+  sc = tri_solve<32>(X + t, r, KR, K, zt, r, sc, w.Z + (size_t)t * K, 1);
+  w.zs[t] = sc;
+}
+
+// (d) eigenvectors of the clustered eigenvalues (the isolated ones are (c)):
+//     one 64-lane workgroup per cluster (the c-th run of eigenvalues whose
+//     consecutive gaps are at most 1e-5 ||T||, found by a scan of lam).
+//     Members are taken in order; for each, lane 0 factors T - lambda I and
+//     runs the sequential solves on LU factors and an iterate held in LDS, and
+//     after every solve the wave orthogonalises the iterate against the
+//     cluster's earlier members (twice) and normalises it.  The finished
+//     vector goes to its column of Z (scale 1).
+template <bool ADMM>
+__global__ __launch_bounds__(64) void k_eig_cluster(LargeArgs a) {
+  __shared__ double sd[1024], se[1024];
+  __shared__ double F[6 * 1024];
+  __shared__ double slam[512];
+  __shared__ int span[2];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int r = (int)w.meta[0];
+  if ((int)blockIdx.y * 2 >= r) return;   // a cluster has at least 2 members
+  const int lane = threadIdx.x;
+  const double tnorm = w.meta[4], ortol = eig_ortol(tnorm);
+  for (int t = lane; t < r; t += 64) slam[t] = w.lam[t];
+  __syncthreads();
+  if (lane == 0) {
+    // start and end of the blockIdx.y-th cluster of size >= 2
+    int c = -1, t0 = 0, found0 = -1, found1 = -1;
+    for (int t = 1; t <= r; ++t) {
+      if (t == r || slam[t] - slam[t - 1] > ortol) {
+        if (t - t0 >= 2 && ++c == (int)blockIdx.y) {
+          found0 = t0;
+          found1 = t;
+          break;
         }
-        if (lane == 0) w.zs[t] = 1.0;
+        t0 = t;
       }
     }
+    span[0] = found0;
+    span[1] = found1;
+  }
+  for (int i = lane; i < K; i += 64) {
+    sd[i] = w.d[i];
+    se[i] = (i < K - 1) ? w.e[i] : 0.0;
+  }
+  __syncthreads();
+  const int c0 = span[0], c1 = span[1];
+  if (c0 < 0) return;
+  const double tiny = kEps * tnorm;
+  double* f = F;              // LU arrays a = 0..4 at f[a K + i]
+  double* z = F + 5 * K;      // the member's iterate
+  for (int t = c0; t < c1; ++t) {
+    if (lane == 0) tri_factor(sd, se, K, slam[t], tiny, f, 1, (size_t)K);
+    for (int i = lane; i < K; i += 64) z[i] = hash_unit((uint32_t)t, (uint32_t)i);
+    __syncthreads();
+    for (int it = 0; it < 3; ++it) {
+      if (lane == 0) (void)tri_solve<8>(f, 1, (size_t)K, K, z, 1, 1.0);
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass)
+        for (int p = c0; p < t; ++p) {
+          const double* q = w.Z + (size_t)p * K;
+          double dot = 0.0;
+          for (int i = lane; i < K; i += 64) dot += q[i] * z[i];
+          dot = wave_sum(dot);
+          for (int i = lane; i < K; i += 64) z[i] -= dot * q[i];
+        }
+      double nn = 0.0;
+      for (int i = lane; i < K; i += 64) nn += z[i] * z[i];
+      const double sc = 1.0 / sqrt(wave_sum(nn));
+      for (int i = lane; i < K; i += 64) z[i] *= sc;
+      __syncthreads();
+    }
+    double* zo = w.Z + (size_t)t * K;
+    for (int i = lane; i < K; i += 64) zo[i] = z[i];
+    if (lane == 0) w.zs[t] = 1.0;
+    __threadfence_block();
+    __syncthreads();
   }
 }
 
@@ -1269,6 +1317,16 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
   if (ntask <= 0) return;
   const int rmax = kmax / 2 + 1;
   const int T = (kmax + kTile - 1) / kTile;
+  auto launch = [&](int kind, auto kernel, dim3 grid, dim3 block, auto... args) {
+    if (hook) {
+      hipEvent_t e0, e1;
+      hook->begin(hook->ctx, kind, &e0, &e1);
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
+      hook->end(hook->ctx, kind);
+    } else {
+      hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+    }
+  };
   switch (step) {
     case 0: hipLaunchKernelGGL(k_large_gather<ADMM>, dim3(ntask, T * (T + 1) / 2), dim3(256), 0, st, a); break;
     case 1: {
@@ -1279,16 +1337,6 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
         int n = 0;
         while (n < ntask && trd_tail_start(host_sizes[n]) > j0) ++n;
         return n;
-      };
-      auto launch = [&](int kind, auto kernel, dim3 grid, dim3 block, auto... args) {
-        if (hook) {
-          hipEvent_t e0, e1;
-          hook->begin(hook->ctx, kind, &e0, &e1);
-          hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
-          hook->end(hook->ctx, kind);
-        } else {
-          hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
-        }
       };
       const int np = trd_tail_start(kmax) / kNB;
       const int ldm = (kmax + 7) & ~7;
@@ -1309,15 +1357,15 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
       break;
     }
     case 2:
-      hipLaunchKernelGGL(k_eig_prep<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
-      hipLaunchKernelGGL(k_eig_bisect<ADMM>, dim3(ntask, (rmax + kBisEig - 1) / kBisEig), dim3(64 * kBisEig), 0, st,
-                         a);
-      hipLaunchKernelGGL(k_eig_single<ADMM>, dim3(ntask, (rmax + kSingle - 1) / kSingle), dim3(64), 0, st, a);
-      hipLaunchKernelGGL(k_eig_vec<ADMM>, dim3(ntask), dim3(kLT), 0, st, a);
+      launch(4, k_eig_prep<ADMM>, dim3(ntask), dim3(kLT), a);
+      launch(5, k_eig_bisect<ADMM>, dim3(ntask, (rmax + kBisEig - 1) / kBisEig), dim3(64 * kBisEig), a);
+      launch(6, k_eig_single<ADMM>, dim3(ntask, (std::min(rmax, kSingleLds) + kSingle - 1) / kSingle), dim3(64), a);
+      launch(6, k_eig_single_wide<ADMM>, dim3(ntask, (rmax + 63) / 64), dim3(64), a);
+      launch(7, k_eig_cluster<ADMM>, dim3(ntask, (rmax + 1) / 2), dim3(64), a);
       break;
     case 3:
-      hipLaunchKernelGGL(k_bt_tfactor<ADMM>, dim3(ntask, (kmax - 2 + kNB - 1) / kNB), dim3(1024), 0, st, a);
-      hipLaunchKernelGGL(k_bt_apply<ADMM>, dim3(ntask, (rmax + kBtNC - 1) / kBtNC), dim3(1024), 0, st, a);
+      launch(8, k_bt_tfactor<ADMM>, dim3(ntask, (kmax - 2 + kNB - 1) / kNB), dim3(1024), a);
+      launch(9, k_bt_apply<ADMM>, dim3(ntask, (rmax + kBtNC - 1) / kBtNC), dim3(1024), a);
       break;
     case 4: hipLaunchKernelGGL(k_large_recon<ADMM>, dim3(ntask, T * (T + 1) / 2), dim3(256), 0, st, a); break;
     case 5:
