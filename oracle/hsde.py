@@ -10,6 +10,8 @@ ADMM for homogeneous self-dual embedding of sparse SDPs":
                                           (DualVectorForm); H_k = E_k (x) E_k
   * homogeneous self-dual embedding Q     Section 3.2, eq. (HomogeneousEmbedding)
   * ADMM steps 1-3                        Section 4.1, eqs. (Step1)-(Step3)
+    + optional over-relaxation            the relaxed steps of O'Donoghue et al.
+                                          2016, whose algorithm Section 4.1 applies
   * step 1 by block elimination           Section 4.2, eqs. (LinearSystem),
     + Sherman-Morrison                    (MatrixInverse), (FirstBlockElimination),
                                           (MatrixInverseResult)
@@ -306,10 +308,17 @@ def initial_point(prob: Problem):
     return u, vt
 
 
-def iterate(prob: Problem, cache: AffineCache, u, vt, sizes):
-    """One ADMM iteration, eqs. (Step1)-(Step3)."""
+def iterate(prob: Problem, cache: AffineCache, u, vt, sizes, alpha=1.0):
+    """One ADMM iteration, eqs. (Step1)-(Step3).
+
+    alpha != 1 is the over-relaxed form of the same algorithm (O'Donoghue et
+    al. 2016, the method Section 4.1 applies): steps 2 and 3 take
+    alpha u_hat + (1 - alpha) u in place of u_hat.  alpha = 1 is the paper's
+    iteration exactly."""
     omega = [a + b for a, b in zip(u, vt)]
     uh = cache.solve(omega)                                   # (Step1)
+    if alpha != 1.0:
+        uh = [alpha * a + (1.0 - alpha) * b for a, b in zip(uh, u)]
     d = [a - b for a, b in zip(uh, vt)]                       # u_hat - v
     un = [d[0].copy(),                                        # free (x)
           proj_psd_packed(d[1], sizes, prob.slot_off[:-1]),    # S = S_1 x ... x S_p
@@ -368,8 +377,10 @@ class Result:
     prob: Problem
 
 
-def solve(inst_or_prob, eps_tol=1e-4, max_iter=2000, record=0, stop=True, cache=None, state=None):
-    """Run the ADMM until a status other than running (R5) or max_iter."""
+def solve(inst_or_prob, eps_tol=1e-4, max_iter=2000, record=0, stop=True, cache=None, state=None,
+          alpha=1.0):
+    """Run the ADMM until a status other than running (R5) or max_iter
+    (alpha: relaxation of steps 2-3, see iterate)."""
     prob = inst_or_prob if isinstance(inst_or_prob, Problem) else build_problem(inst_or_prob)
     cache = cache or AffineCache(prob)
     sizes = np.diff(prob.slot_off)
@@ -381,7 +392,7 @@ def solve(inst_or_prob, eps_tol=1e-4, max_iter=2000, record=0, stop=True, cache=
     r = {}
     k = 0
     for k in range(1, max_iter + 1):
-        u, vt = iterate(prob, cache, u, vt, sizes)
+        u, vt = iterate(prob, cache, u, vt, sizes, alpha)
         if k <= record:
             history.append(([a.copy() if isinstance(a, np.ndarray) else a for a in u],
                             [a.copy() if isinstance(a, np.ndarray) else a for a in vt]))
