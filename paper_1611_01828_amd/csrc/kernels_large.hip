@@ -299,8 +299,10 @@ __global__ __launch_bounds__(256) void k_trd_symv(LargeArgs a, int p, int i, int
   //     summed here at the first column of a panel)
   const double alpha = W[(size_t)j * ld + j + 1];
   const double djj = W[(size_t)j * ld + j];
-  const int rown = rbase + tid;
-  const double xrow = W[(size_t)j * ld + min(rown, K - 1)];
+  constexpr int NR = kSymvRows / 256;   // rows of v each thread stages
+  double xrow[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) xrow[q] = W[(size_t)j * ld + min(rbase + tid + 256 * q, K - 1)];
   double xcol[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) xcol[u] = W[(size_t)j * ld + min(j + 1 + cg + u, K - 1)];
@@ -333,7 +335,11 @@ __global__ __launch_bounds__(256) void k_trd_symv(LargeArgs a, int p, int i, int
     scale = 1.0 / (alpha - beta);
   }
   auto vof = [&](int r, double x) { return (r == j + 1) ? 1.0 : ((r > j + 1 && r < K) ? x * scale : 0.0); };
-  if (rown < ld) vbuf[rown] = vof(rown, xrow);
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int rown = rbase + tid + 256 * q;
+    if (rown < ld) vbuf[rown] = vof(rown, xrow[q]);
+  }
   if (lead && tid == 0) {   // V(:, i) itself is written by the update launch
     w.d[j] = djj;
     w.e[j] = beta;
