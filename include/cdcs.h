@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CDCS_ABI_VERSION 2
+#define CDCS_ABI_VERSION 3
 
 /* outcomes (cdcs_info.status) */
 enum {
@@ -113,6 +113,15 @@ typedef struct {
                           synthetic blocks of the instance's clique orders and keep the
                           faster; 2 = the other candidate without timing (for comparisons).
                           cdcs_get_tuning reports the choice. */
+  double alpha;        /* relaxation of steps 2-3, in (0, 2): they take
+                          alpha u_hat + (1 - alpha) u in place of u_hat, the
+                          over-relaxed form of the ADMM of O'Donoghue et al.
+                          2016 that Section 4.1 applies (same fixed points).
+                          1 = eqs. Step2-Step3 exactly (the default).  Other
+                          values add, per iteration, one pass of A over x, of
+                          A^T over y and of H^T over v of the previous iterate
+                          inside the existing kernels, and 4 vectors (3 nE,
+                          1 m) of device memory; otherwise CDCS_E_ARG. */
 } cdcs_settings;
 
 typedef struct {
@@ -125,7 +134,7 @@ typedef struct {
 } cdcs_info;
 
 /* Fill s with eps_tol = 1e-4, max_iter = 2000, check_every = 1, timing = 0,
- * use_graph = 0, eig_fp32 = 0, autotune = 0. */
+ * use_graph = 0, eig_fp32 = 0, autotune = 0, alpha = 1. */
 void cdcs_default_settings(cdcs_settings* s);
 
 /* Build the cached data of step 1 (the m x m factor of the matrix of eq.

@@ -37,7 +37,7 @@ class Problem(C.Structure):
 class Settings(C.Structure):
     _fields_ = [("eps_tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("timing", C.c_int32), ("use_graph", C.c_int32), ("eig_fp32", C.c_int32),
-                ("autotune", C.c_int32)]
+                ("autotune", C.c_int32), ("alpha", C.c_double)]
 
 
 class Info(C.Structure):
@@ -49,6 +49,8 @@ class Info(C.Structure):
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
+
+ABI_VERSION = 3   # the layout of the structures above
 
 EXPORTS = [
     "cdcs_default_settings", "cdcs_setup", "cdcs_setup_batch", "cdcs_iterate", "cdcs_solve",
@@ -122,6 +124,9 @@ def load(path: str = LIB_PATH):
     for name in EXPORTS:
         if name not in ("cdcs_default_settings", "cdcs_last_error", "cdcs_destroy", "cdcs_abi_version"):
             getattr(lib, name).restype = C.c_int
+    if lib.cdcs_abi_version() != ABI_VERSION:
+        raise ImportError(f"{path} has ABI version {lib.cdcs_abi_version()}, this binding needs "
+                          f"{ABI_VERSION}; rebuild with `python -m paper_1611_01828_amd.build`")
     _lib = lib
     return lib
 

@@ -518,6 +518,14 @@ int pack_and_upload(cdcs_handle* h) {
       (rc = dev_upload(h, (int32_t**)&d.at_row, atrow)) || (rc = dev_upload(h, (double**)&d.at_val, atval)) ||
       (rc = dev_zeros(h, &d.y, M)) || (rc = dev_zeros(h, &d.g, M)) || (rc = dev_zeros(h, &d.w, M)))
     return rc;
+  // relaxed steps 2-3: u_hat_x and the previous iterate's products
+  d.alpha = h->set.alpha;
+  d.relax = h->set.alpha != 1.0;
+  d.xh = d.x;
+  d.atyo = d.hvo = d.axo = nullptr;
+  if (d.relax && ((rc = dev_zeros(h, &d.xh, NE)) || (rc = dev_zeros(h, &d.atyo, NE)) ||
+                  (rc = dev_zeros(h, &d.hvo, NE)) || (rc = dev_zeros(h, &d.axo, M))))
+    return rc;
   // factors
   std::vector<int32_t> fmode(B), perm(M, 0), lptr, lcol, uptr, ucol, flev_off(B + 1, 0), flev_ptr,
       flev_rows, blev_off(B + 1, 0), blev_ptr, blev_rows;
@@ -663,6 +671,7 @@ void cdcs_default_settings(cdcs_settings* s) {
   s->use_graph = 0;
   s->eig_fp32 = 0;
   s->autotune = 0;
+  s->alpha = 1.0;
 }
 
 int cdcs_abi_version(void) { return CDCS_ABI_VERSION; }
@@ -700,6 +709,8 @@ int cdcs_setup_batch(int32_t count, const cdcs_problem* prob, const cdcs_setting
     return set_error(CDCS_E_ARG, "settings: need eps_tol > 0, max_iter >= 1, check_every >= 1");
   if ((set.eig_fp32 != 0 && set.eig_fp32 != 1) || set.autotune < 0 || set.autotune > 2)
     return set_error(CDCS_E_ARG, "settings: eig_fp32 must be 0 or 1 and autotune 0, 1 or 2");
+  if (!(set.alpha > 0.0 && set.alpha < 2.0))
+    return set_error(CDCS_E_ARG, "settings: alpha must lie in (0, 2)");
   const auto t0 = std::chrono::steady_clock::now();
   cdcs_handle* h = new cdcs_handle();
   h->stream = (hipStream_t)stream;

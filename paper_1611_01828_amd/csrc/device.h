@@ -53,6 +53,16 @@ struct DevPlan {
   const double* atzy;         // A^T (y part of M^{-1} zeta)
   const int32_t* ent_sptr;    // NE+1: slots covering each entry (H^T as CSR)
   const int32_t* ent_slots;
+  // over-relaxation of steps 2-3 (relax = alpha != 1); with relax the step-1
+  // point u_hat_x is kept apart from x+ in xh, and the products of the
+  // previous iterate A x, A^T y, H^T v are formed in the passes that already
+  // read those operands.  Without relax xh aliases x and the others are null.
+  double alpha;
+  int32_t relax;
+  double* xh;                 // u_hat_x
+  double* atyo;               // A^T y (previous iterate)
+  double* hvo;                // H^T v (previous iterate)
+  double* axo;                // A x   (previous iterate), row space
   // slot space
   double* s;
   double* z;
@@ -138,6 +148,22 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   }
   __syncthreads();
   return red[NT / 64];
+}
+
+// Steps 2-3 at one clique slot.  Step 1 in the eliminated form gives
+// u_hat_s = (s + z - v + xh)/2 and u_hat_v = (s + z + v - xh)/2, with xh the
+// slot's entry of H u_hat_x (h = r = w = 0).  Step 2 projects Y = ub_s - z and
+// sets v+ = ub_v, where ub = u_hat (eqs. Step2-Step3) or, relaxed,
+// ub = u + alpha (u_hat - u).  Without relaxation the paper's form is
+// evaluated as such (Y = (s - z - v + xh)/2).
+__device__ __forceinline__ double slot_arg(const DevPlan& d, double s, double z, double v, double xh) {
+  if (!d.relax) return 0.5 * (s - z - v + xh);
+  const double us = 0.5 * (s + z - v + xh);
+  return (s + d.alpha * (us - s)) - z;
+}
+__device__ __forceinline__ double slot_vnew(const DevPlan& d, double s, double z, double v, double xh) {
+  const double uv = 0.5 * (s + z + v - xh);
+  return d.relax ? v + d.alpha * (uv - v) : uv;
 }
 
 // launchers (defined in the .hip files)

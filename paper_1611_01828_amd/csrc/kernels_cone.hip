@@ -10,6 +10,8 @@
 //   s+  = Pi_+(Y) = V max(Lambda, 0) V^T
 //   z+  = z - u_s + s+ = s+ - Y
 // plus the partial sums ||H_k x+ - s+||^2 and ||v+ - z+||^2 for the residuals.
+// With relaxed steps 2-3 u_s and v+ are the blends of slot_arg / slot_vnew,
+// H_k reads u_hat_x (xh) for them and x+ for the residual.
 //
 // T is the working precision of the eigen-decomposition (double, or float
 // for the FP32 variant): Y is gathered and s+, z+, v+ are formed in double,
@@ -43,8 +45,7 @@ __global__ __launch_bounds__(NT) void k_cone_jacobi(DevPlan d, const int32_t* ta
     if (i < K && j < K) {
       const int a = i > j ? i : j, bq = i > j ? j : i;
       const int64_t sl = s0 + packed_index(a, bq, K);
-      const double xv = d.x[d.slot2ent[sl]];
-      yv = 0.5 * (d.s[sl] - d.z[sl] - d.v[sl] + xv);
+      yv = slot_arg(d, d.s[sl], d.z[sl], d.v[sl], d.xh[d.slot2ent[sl]]);
       if (a != bq) yv *= kInvSqrt2;
     }
     A[i * KMAX + j] = (T)yv;
@@ -67,12 +68,14 @@ __global__ __launch_bounds__(NT) void k_cone_jacobi(DevPlan d, const int32_t* ta
     }
     const int64_t sl = s0 + t;
     const double sv = d.s[sl], zv = d.z[sl], vv = d.v[sl];
-    const double xv = d.x[d.slot2ent[sl]];
-    const double yvec = 0.5 * (sv - zv - vv + xv);          // svec(Y) entry
+    const int e = d.slot2ent[sl];
+    const double xh = d.xh[e];
+    const double xv = d.relax ? d.x[e] : xh;                 // (H x+) at the slot
+    const double yvec = slot_arg(d, sv, zv, vv, xh);          // svec(Y) entry
     const double sc = (a == bq) ? 1.0 : kSqrt2;
     const double sp = pos ? acc * sc : yvec - acc * sc;      // svec(Pi_+(Y))
     const double zn = sp - yvec;
-    const double vn = 0.5 * (sv + zv + vv - xv);
+    const double vn = slot_vnew(d, sv, zv, vv, xh);
     d.s[sl] = sp;
     d.z[sl] = zn;
     d.v[sl] = vn;

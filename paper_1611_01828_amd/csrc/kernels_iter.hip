@@ -21,22 +21,32 @@
 // cone kernels.  Residual norms reuse these intermediates: A x+ = w' + y +
 // omega_3 b + gamma (b + zt_y), A^T y+ = -A^T w' - gamma A^T zt_y and
 // H^T v+ = H^T(s+z+v)/2 - D x+ / 2.
+//
+// Relaxed steps 2-3 (alpha != 1, O'Donoghue et al. 2016): x+, y+, v+ and the
+// tau argument are u + alpha (u_hat - u), so each product of the new iterate
+// is the same blend of the product of u_hat above and that of the previous
+// iterate; A x, A^T y and H^T v of the previous iterate are summed in k_spmv_a,
+// k_spmv_at and k_r0, which read those index lists anyway (RELAX templates).
 #include "device.h"
 
 namespace cdcs {
 
+template <bool RELAX>
 __global__ __launch_bounds__(kThreads) void k_r0(DevPlan d) {
   const int4 bd = d.eblk[blockIdx.x];
   const int inst = bd.x;
   if (d.st[inst * kNst + ST_FROZEN]) return;
   const double om3 = d.sc[inst * kNsc + SC_TAU] + d.sc[inst * kNsc + SC_KAPPA];
   for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
-    double acc = 0.0;
+    double acc = 0.0, accv = 0.0;
     const int k1 = d.ent_sptr[e + 1];
     for (int k = d.ent_sptr[e]; k < k1; ++k) {
       const int sl = d.ent_slots[k];
-      acc += d.s[sl] + d.z[sl] + d.v[sl];
+      const double vv = d.v[sl];
+      acc += d.s[sl] + d.z[sl] + vv;
+      if (RELAX) accv += vv;
     }
+    if (RELAX) d.hvo[e] = accv;
     const double hs = 0.5 * acc;
     const double r0 = d.x[e] - om3 * d.c[e] + hs;
     d.hsum[e] = hs;
@@ -45,6 +55,7 @@ __global__ __launch_bounds__(kThreads) void k_r0(DevPlan d) {
 }
 
 // one wavefront per constraint row
+template <bool RELAX>
 __global__ __launch_bounds__(kThreads) void k_spmv_a(DevPlan d) {
   const int4 bd = d.rblk[blockIdx.x];
   const int inst = bd.x;
@@ -52,11 +63,20 @@ __global__ __launch_bounds__(kThreads) void k_spmv_a(DevPlan d) {
   const double om3 = d.sc[inst * kNsc + SC_TAU] + d.sc[inst * kNsc + SC_KAPPA];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int r = bd.y + wid; r < bd.z; r += kThreads / 64) {
-    double acc = 0.0;
+    double acc = 0.0, accx = 0.0;
     const int q1 = d.a_ptr[r + 1];
-    for (int q = d.a_ptr[r] + lane; q < q1; q += 64) acc += d.a_val[q] * d.q[d.a_col[q]];
+    for (int q = d.a_ptr[r] + lane; q < q1; q += 64) {
+      const int col = d.a_col[q];
+      const double av = d.a_val[q];
+      acc += av * d.q[col];
+      if (RELAX) accx += av * d.x[col];   // x is still the previous iterate here
+    }
     acc = wave_sum(acc);
-    if (lane == 0) d.g[r] = acc - d.y[r] - om3 * d.b[r];
+    if (RELAX) accx = wave_sum(accx);
+    if (lane == 0) {
+      d.g[r] = acc - d.y[r] - om3 * d.b[r];
+      if (RELAX) d.axo[r] = accx;
+    }
   }
 }
 
@@ -145,6 +165,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(DevPlan d) {
   if (tid == 0) d.sc[inst * kNsc + SC_BW] = bw;
 }
 
+template <bool RELAX>
 __global__ __launch_bounds__(kThreads) void k_spmv_at(DevPlan d) {
   __shared__ double red[kThreads / 64 + 1];
   const int4 bd = d.eblk[blockIdx.x];
@@ -152,9 +173,15 @@ __global__ __launch_bounds__(kThreads) void k_spmv_at(DevPlan d) {
   if (d.st[inst * kNst + ST_FROZEN]) return;
   double cpx = 0.0;
   for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
-    double acc = 0.0;
+    double acc = 0.0, accy = 0.0;
     const int q1 = d.at_ptr[e + 1];
-    for (int q = d.at_ptr[e]; q < q1; ++q) acc += d.at_val[q] * d.w[d.at_row[q]];
+    for (int q = d.at_ptr[e]; q < q1; ++q) {
+      const int row = d.at_row[q];
+      const double av = d.at_val[q];
+      acc += av * d.w[row];
+      if (RELAX) accy += av * d.y[row];   // y is still the previous iterate here
+    }
+    if (RELAX) d.atyo[e] = accy;
     const double px = d.q[e] - d.pinv[e] * acc;
     d.atw[e] = acc;
     d.px[e] = px;
@@ -181,16 +208,18 @@ __global__ __launch_bounds__(64) void k_scalar1(DevPlan d) {
     const double cx = acc - gam * sc[SC_CTZX];       // c^T x+
     const double by = -bw - gam * sc[SC_BTZY];       // b^T y+
     const double ut = om3 + cx - by;
-    const double tn = fmax(0.0, ut - kap);
+    const double ub = d.relax ? tau + d.alpha * (ut - tau) : ut;   // relaxed tau argument
+    const double tn = fmax(0.0, ub - kap);
     sc[SC_CPX] = acc;
     sc[SC_GAMMA] = gam;
     sc[SC_OMEGA3] = om3;
     sc[SC_UTAU] = ut;
     sc[SC_TAU] = tn;
-    sc[SC_KAPPA] = kap - ut + tn;
+    sc[SC_KAPPA] = kap - ub + tn;
   }
 }
 
+template <bool RELAX>
 __global__ __launch_bounds__(kThreads) void k_update_e(DevPlan d) {
   __shared__ double red[kThreads / 64 + 1];
   const int4 bd = d.eblk[blockIdx.x];
@@ -198,11 +227,23 @@ __global__ __launch_bounds__(kThreads) void k_update_e(DevPlan d) {
   if (d.st[inst * kNst + ST_FROZEN]) return;
   const double* sc = d.sc + inst * kNsc;
   const double gam = sc[SC_GAMMA], tau = sc[SC_TAU];
+  const double al = d.alpha;
   double d2 = 0.0, p2 = 0.0, cx = 0.0;
   for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
-    const double xn = d.px[e] - gam * d.zt_x[e];
-    // A^T y+ + H^T v+  (dual-feasibility row of eq. DualFeasible)
-    const double lin = -d.atw[e] - gam * d.atzy[e] + d.hsum[e] - d.halfD[e] * xn;
+    const double xh = d.px[e] - gam * d.zt_x[e];   // u_hat_x
+    double xn, lin;
+    if (!RELAX) {
+      xn = xh;
+      // A^T y+ + H^T v+  (dual-feasibility row of eq. DualFeasible)
+      lin = -d.atw[e] - gam * d.atzy[e] + d.hsum[e] - d.halfD[e] * xn;
+    } else {
+      const double xo = d.x[e], ao = d.atyo[e], ho = d.hvo[e];
+      xn = xo + al * (xh - xo);
+      const double aty = ao + al * ((-d.atw[e] - gam * d.atzy[e]) - ao);
+      const double hv = ho + al * ((d.hsum[e] - d.halfD[e] * xh) - ho);
+      lin = aty + hv;
+      d.xh[e] = xh;
+    }
     const double ce = d.c[e];
     const double dr = lin - tau * ce;
     d.x[e] = xn;
@@ -221,6 +262,7 @@ __global__ __launch_bounds__(kThreads) void k_update_e(DevPlan d) {
   }
 }
 
+template <bool RELAX>
 __global__ __launch_bounds__(kThreads) void k_update_r(DevPlan d) {
   __shared__ double red[kThreads / 64 + 1];
   const int4 bd = d.rblk[blockIdx.x];
@@ -228,12 +270,18 @@ __global__ __launch_bounds__(kThreads) void k_update_r(DevPlan d) {
   if (d.st[inst * kNst + ST_FROZEN]) return;
   const double* sc = d.sc + inst * kNsc;
   const double gam = sc[SC_GAMMA], tau = sc[SC_TAU], om3 = sc[SC_OMEGA3];
+  const double al = d.alpha;
   double p2 = 0.0, a2 = 0.0, by = 0.0;
   for (int r = bd.y + threadIdx.x; r < bd.z; r += kThreads) {
-    const double br = d.b[r], ztr = d.zt_y[r], wr = d.w[r];
-    // A x+ = A p_x - gamma A zt_x = (w' + y + omega_3 b) + gamma (b + zt_y)
-    const double ax = wr + d.y[r] + om3 * br + gam * (br + ztr);
-    const double yn = -wr - gam * ztr;
+    const double br = d.b[r], ztr = d.zt_y[r], wr = d.w[r], yo = d.y[r];
+    // A u_hat_x = A p_x - gamma A zt_x = (w' + y + omega_3 b) + gamma (b + zt_y)
+    double ax = wr + yo + om3 * br + gam * (br + ztr);
+    double yn = -wr - gam * ztr;                     // u_hat_y
+    if (RELAX) {
+      const double ao = d.axo[r];
+      ax = ao + al * (ax - ao);
+      yn = yo + al * (yn - yo);
+    }
     d.y[r] = yn;
     const double pr = ax - tau * br;
     p2 += pr * pr;
@@ -315,25 +363,30 @@ __global__ __launch_bounds__(64) void k_scalar2(DevPlan d, double eps_tol, int32
 }
 
 void launch_r0(const DevPlan& d, hipStream_t st) {
-  hipLaunchKernelGGL(k_r0, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
+  if (d.relax) hipLaunchKernelGGL(k_r0<true>, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
+  else hipLaunchKernelGGL(k_r0<false>, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
 }
 void launch_spmv_a(const DevPlan& d, hipStream_t st) {
-  hipLaunchKernelGGL(k_spmv_a, dim3(d.n_rblk), dim3(kThreads), 0, st, d);
+  if (d.relax) hipLaunchKernelGGL(k_spmv_a<true>, dim3(d.n_rblk), dim3(kThreads), 0, st, d);
+  else hipLaunchKernelGGL(k_spmv_a<false>, dim3(d.n_rblk), dim3(kThreads), 0, st, d);
 }
 void launch_trsv(const DevPlan& d, hipStream_t st) {
   hipLaunchKernelGGL(k_trsv, dim3(d.B), dim3(kTrsvThreads), 0, st, d);
 }
 void launch_spmv_at(const DevPlan& d, hipStream_t st) {
-  hipLaunchKernelGGL(k_spmv_at, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
+  if (d.relax) hipLaunchKernelGGL(k_spmv_at<true>, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
+  else hipLaunchKernelGGL(k_spmv_at<false>, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
 }
 void launch_scalar1(const DevPlan& d, hipStream_t st) {
   hipLaunchKernelGGL(k_scalar1, dim3(d.B), dim3(64), 0, st, d);
 }
 void launch_update_e(const DevPlan& d, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_e, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
+  if (d.relax) hipLaunchKernelGGL(k_update_e<true>, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
+  else hipLaunchKernelGGL(k_update_e<false>, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
 }
 void launch_update_r(const DevPlan& d, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_r, dim3(d.n_rblk), dim3(kThreads), 0, st, d);
+  if (d.relax) hipLaunchKernelGGL(k_update_r<true>, dim3(d.n_rblk), dim3(kThreads), 0, st, d);
+  else hipLaunchKernelGGL(k_update_r<false>, dim3(d.n_rblk), dim3(kThreads), 0, st, d);
 }
 void launch_scalar2(const DevPlan& d, double eps_tol, int32_t max_iter, int32_t stop, hipStream_t st) {
   hipLaunchKernelGGL(k_scalar2, dim3(d.B), dim3(64), 0, st, d, eps_tol, max_iter, stop);

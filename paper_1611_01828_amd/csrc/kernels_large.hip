@@ -112,12 +112,13 @@ __device__ __forceinline__ bool task_info(const LargeArgs& a, int task, int& K, 
   return true;
 }
 
-// svec(Y) entry of packed slot t of the task (ADMM: (s - z - v + H x+)/2)
+// svec(Y) entry of packed slot t of the task (ADMM: the argument of the
+// projection of step 2, slot_arg)
 template <bool ADMM>
 __device__ __forceinline__ double yvec_of(const LargeArgs& a, int64_t base, int t) {
   if (ADMM) {
     const int64_t sl = base + t;
-    return 0.5 * (a.d.s[sl] - a.d.z[sl] - a.d.v[sl] + a.d.x[a.d.slot2ent[sl]]);
+    return slot_arg(a.d, a.d.s[sl], a.d.z[sl], a.d.v[sl], a.d.xh[a.d.slot2ent[sl]]);
   }
   return a.pin[base + t];
 }
@@ -1273,9 +1274,11 @@ __global__ __launch_bounds__(256) void k_large_recon(LargeArgs a) {
       if (ADMM) {
         const int64_t sl = base + t;
         const double sv = a.d.s[sl], zv = a.d.z[sl], vv = a.d.v[sl];
-        const double xv = a.d.x[a.d.slot2ent[sl]];
+        const int e = a.d.slot2ent[sl];
+        const double xh = a.d.xh[e];
+        const double xv = a.d.relax ? a.d.x[e] : xh;   // (H x+) at the slot
         const double zn = sp - y;
-        const double vn = 0.5 * (sv + zv + vv - xv);
+        const double vn = slot_vnew(a.d, sv, zv, vv, xh);
         a.d.s[sl] = sp;
         a.d.z[sl] = zn;
         a.d.v[sl] = vn;
