@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <thread>
 #include <vector>
@@ -530,7 +531,8 @@ int pack_and_upload(cdcs_handle* h) {
   std::vector<int32_t> fmode(B), perm(M, 0), lptr, lcol, uptr, ucol, flev_off(B + 1, 0), flev_ptr,
       flev_rows, blev_off(B + 1, 0), blev_ptr, blev_rows;
   std::vector<int64_t> fdoff(B, 0);
-  std::vector<double> Ld, fdiag(M, 1.0), lval, uval;
+  std::vector<double> Ld, Ldt, fdiag(M, 1.0), lval, uval;
+  int32_t dense_m = 0;
   for (int32_t i = 0; i < B; ++i) {
     const Factor& f = I[i].fac;
     const int32_t ro = h->row_off[i];
@@ -538,6 +540,10 @@ int pack_and_upload(cdcs_handle* h) {
     if (f.dense) {
       fdoff[i] = (int64_t)Ld.size();
       Ld.insert(Ld.end(), f.Ld.begin(), f.Ld.end());
+      Ldt.resize(Ld.size());
+      for (int32_t c = 0; c < f.m; ++c)
+        for (int32_t r = 0; r < f.m; ++r) Ldt[fdoff[i] + (size_t)r * f.m + c] = f.Ld[(size_t)c * f.m + r];
+      dense_m = std::max(dense_m, f.m);
       for (int32_t r = 0; r < f.m; ++r) lptr.push_back((int32_t)lcol.size());
       lptr.push_back((int32_t)lcol.size());
       for (int32_t r = 0; r < f.m; ++r) uptr.push_back((int32_t)ucol.size());
@@ -566,7 +572,8 @@ int pack_and_upload(cdcs_handle* h) {
   flev_ptr.push_back((int32_t)flev_rows.size());
   blev_ptr.push_back((int32_t)blev_rows.size());
   if ((rc = dev_upload(h, (int32_t**)&d.f_mode, fmode)) || (rc = dev_upload(h, (int64_t**)&d.f_dense_off, fdoff)) ||
-      (rc = dev_upload(h, (double**)&d.f_Ld, Ld)) || (rc = dev_upload(h, (int32_t**)&d.f_perm, perm)) ||
+      (rc = dev_upload(h, (double**)&d.f_Ld, Ld)) || (rc = dev_upload(h, (double**)&d.f_Ldt, Ldt)) ||
+      (rc = dev_upload(h, (int32_t**)&d.f_perm, perm)) ||
       (rc = dev_upload(h, (double**)&d.f_diag, fdiag)) || (rc = dev_upload(h, (int32_t**)&d.f_lptr, lptr)) ||
       (rc = dev_upload(h, (int32_t**)&d.f_lcol, lcol)) || (rc = dev_upload(h, (double**)&d.f_lval, lval)) ||
       (rc = dev_upload(h, (int32_t**)&d.f_uptr, uptr)) || (rc = dev_upload(h, (int32_t**)&d.f_ucol, ucol)) ||
@@ -577,6 +584,9 @@ int pack_and_upload(cdcs_handle* h) {
       (rc = dev_upload(h, (int32_t**)&d.f_blev_ptr, blev_ptr)) ||
       (rc = dev_upload(h, (int32_t**)&d.f_blev_rows, blev_rows)))
     return rc;
+  // rows per thread of the dense sweeps (256 threads; the dense form has m <= 2048)
+  d.trsv_rows = dense_m <= 256 ? 1 : dense_m <= 512 ? 2 : dense_m <= 1024 ? 4 : 8;
+  if (dense_m > 2048) return set_error(CDCS_E_ARG, "dense factor of order > 2048");
   // blocks
   std::vector<int4> eblk, rblk;
   std::vector<int32_t> eblk_off(B + 1, 0), rblk_off(B + 1, 0);
@@ -590,6 +600,47 @@ int pack_and_upload(cdcs_handle* h) {
   }
   d.n_eblk = (int32_t)eblk.size();
   d.n_rblk = (int32_t)rblk.size();
+  // A^T as sliced ELL over the entry blocks (k_spmv_at): per block, entries
+  // sorted by nonzero count (descending, stable), chunks of 64 lanes, each
+  // chunk column-interleaved and zero-padded (row 0, value 0) to its first
+  // entry's count
+  {
+    std::vector<int32_t> choff(eblk.size()), chlen, sent, srow, order;
+    std::vector<int64_t> chptr;
+    std::vector<double> sval;
+    int64_t pos = 0;
+    auto cnt = [&](int32_t e) { return atptr[e + 1] - atptr[e]; };
+    for (size_t bi = 0; bi < eblk.size(); ++bi) {
+      const int32_t e0 = eblk[bi].y, e1 = eblk[bi].z;
+      choff[bi] = (int32_t)chlen.size();
+      order.resize(e1 - e0);
+      std::iota(order.begin(), order.end(), e0);
+      std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return cnt(a) > cnt(c); });
+      for (int32_t c0 = 0; c0 < e1 - e0; c0 += 64) {
+        const int32_t n = std::min<int32_t>(64, e1 - e0 - c0);
+        const int32_t len = cnt(order[c0]);
+        chptr.push_back(pos);
+        chlen.push_back(len);
+        for (int32_t l = 0; l < 64; ++l) sent.push_back(l < n ? order[c0 + l] : -1);
+        for (int32_t k = 0; k < len; ++k)
+          for (int32_t l = 0; l < 64; ++l) {
+            int32_t r = 0;
+            double v = 0.0;
+            if (l < n && k < cnt(order[c0 + l])) {
+              r = atrow[atptr[order[c0 + l]] + k];
+              v = atval[atptr[order[c0 + l]] + k];
+            }
+            srow.push_back(r);
+            sval.push_back(v);
+          }
+        pos += (int64_t)len * 64;
+      }
+    }
+    if ((rc = dev_upload(h, (int32_t**)&d.at_choff, choff)) || (rc = dev_upload(h, (int64_t**)&d.at_chptr, chptr)) ||
+        (rc = dev_upload(h, (int32_t**)&d.at_chlen, chlen)) || (rc = dev_upload(h, (int32_t**)&d.at_sent, sent)) ||
+        (rc = dev_upload(h, (int32_t**)&d.at_srow, srow)) || (rc = dev_upload(h, (double**)&d.at_sval, sval)))
+      return rc;
+  }
   std::vector<int64_t> ent_off64(h->ent_off);
   if ((rc = dev_upload(h, (int4**)&d.eblk, eblk)) || (rc = dev_upload(h, (int4**)&d.rblk, rblk)) ||
       (rc = dev_upload(h, (int32_t**)&d.eblk_off, eblk_off)) ||

@@ -80,10 +80,23 @@ struct DevPlan {
   const int32_t* at_ptr;      // A^T, CSR over global rows
   const int32_t* at_row;
   const double* at_val;
+  // A^T again, sliced ELL for k_spmv_at: the entries of every entry block,
+  // sorted by their count of nonzeros (descending), are cut into chunks of
+  // 64; chunk c stores its k-th nonzeros of the 64 lanes at
+  // at_chptr[c] + 64 k + lane (zero-padded to the chunk's longest, its
+  // first), so that a wave reads 64 consecutive values per step.
+  const int32_t* at_choff;    // n_eblk: first chunk of each entry block
+  const int64_t* at_chptr;    // chunks: offset into at_srow / at_sval
+  const int32_t* at_chlen;    // chunks: nonzeros of the chunk's longest entry
+  const int32_t* at_sent;     // chunks x 64: the lane's entry, or -1
+  const int32_t* at_srow;
+  const double* at_sval;
   // m x m factor per instance
   const int32_t* f_mode;      // 0 dense, 1 sparse
   const int64_t* f_dense_off; // offset of the dense column-major factor
   const double* f_Ld;
+  const double* f_Ldt;        // the transposes of the dense factors (same offsets)
+  int32_t trsv_rows;          // rows per thread the dense sweeps need (1, 2, 4 or 8)
   const int32_t* f_perm;      // at row_off (local indices)
   const double* f_diag;       // at row_off
   const int32_t* f_lptr;      // at row_off + inst (m+1 each), values global into lcol

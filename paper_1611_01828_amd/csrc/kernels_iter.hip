@@ -54,22 +54,38 @@ __global__ __launch_bounds__(kThreads) void k_r0(DevPlan d) {
   }
 }
 
-// one wavefront per constraint row
+// one wavefront per constraint row: workgroup (b, y) takes rows
+// 4 y .. 4 y + 3 of row block b
 template <bool RELAX>
 __global__ __launch_bounds__(kThreads) void k_spmv_a(DevPlan d) {
   const int4 bd = d.rblk[blockIdx.x];
   const int inst = bd.x;
-  if (d.st[inst * kNst + ST_FROZEN]) return;
-  const double om3 = d.sc[inst * kNsc + SC_TAU] + d.sc[inst * kNsc + SC_KAPPA];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int r = bd.y + wid; r < bd.z; r += kThreads / 64) {
+  const int r = bd.y + blockIdx.y * (kThreads / 64) + wid;
+  if (r >= bd.z || d.st[inst * kNst + ST_FROZEN]) return;
+  const double om3 = d.sc[inst * kNsc + SC_TAU] + d.sc[inst * kNsc + SC_KAPPA];
+  {
+    // batches of kBatch nonzeros per lane with clamped indices, so that all
+    // loads of a batch are in flight together (a bounds test per load would
+    // serialise them); each lane still sums its nonzeros q, q + 64, ... in order
+    constexpr int kBatch = 8;
     double acc = 0.0, accx = 0.0;
-    const int q1 = d.a_ptr[r + 1];
-    for (int q = d.a_ptr[r] + lane; q < q1; q += 64) {
-      const int col = d.a_col[q];
-      const double av = d.a_val[q];
-      acc += av * d.q[col];
-      if (RELAX) accx += av * d.x[col];   // x is still the previous iterate here
+    const int q0 = d.a_ptr[r], q1 = d.a_ptr[r + 1];
+    for (int qb = q0; qb < q1; qb += 64 * kBatch) {
+      int col[kBatch];
+      double av[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int qc = min(qb + 64 * u + lane, q1 - 1);
+        col[u] = d.a_col[qc];
+        av[u] = d.a_val[qc];
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const double m = (qb + 64 * u + lane < q1) ? av[u] : 0.0;
+        acc += m * d.q[col[u]];
+        if (RELAX) accx += m * d.x[col[u]];   // x is still the previous iterate here
+      }
     }
     acc = wave_sum(acc);
     if (RELAX) accx = wave_sum(accx);
@@ -84,7 +100,47 @@ __global__ __launch_bounds__(kThreads) void k_spmv_a(DevPlan d) {
 // or Kp = L L^T in a minimum-degree order with level-scheduled rows.
 constexpr int kTrsvThreads = 256;
 constexpr int kTrsvLds = 8192;
+constexpr int kTrsvDense = 2048;   // largest m of the dense form
+static_assert(3 * kTrsvDense <= kTrsvLds, "the dense sweeps keep three vectors in LDS");
 
+// One column-oriented sweep of a dense triangular solve held in LDS:
+// for j in order, x_j = rhs_j / dg_j and rhs_i -= M(i, j) x_j for the rows
+// i after j (forward: M = L, rows below; backward: M = L^T stored as its own
+// column-major matrix, rows above, so that both sweeps read columns).  Thread
+// t owns rows t + 256 r (r < R); the next PD columns it needs are kept in
+// registers, loaded PD columns ahead, so one barrier per column remains.
+template <int R, int PD, bool FWD>
+__device__ __forceinline__ void trsv_sweep(const double* M, int m, double* rhs, double* out, const double* dg) {
+  const int tid = threadIdx.x;
+  double ring[PD][R];
+  auto col_of = [&](int k) { return FWD ? min(k, m - 1) : max(m - 1 - k, 0); };
+#pragma unroll
+  for (int p = 0; p < PD; ++p)
+#pragma unroll
+    for (int r = 0; r < R; ++r) ring[p][r] = M[(size_t)col_of(p) * m + min(tid + kTrsvThreads * r, m - 1)];
+  for (int k0 = 0; k0 < m; k0 += PD) {
+#pragma unroll
+    for (int p = 0; p < PD; ++p) {
+      const int k = k0 + p;
+      if (k < m) {
+        const int j = FWD ? k : m - 1 - k;
+        const double xj = rhs[j] / dg[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = tid + kTrsvThreads * r;
+          if (i < m && (FWD ? i > j : i < j)) rhs[i] -= ring[p][r] * xj;
+        }
+        if (tid == 0) out[j] = xj;
+        const int jn = col_of(k + PD);
+#pragma unroll
+        for (int r = 0; r < R; ++r) ring[p][r] = M[(size_t)jn * m + min(tid + kTrsvThreads * r, m - 1)];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int R, int PD>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv(DevPlan d) {
   __shared__ double zl[kTrsvLds];
   __shared__ double red[kTrsvThreads / 64 + 1];
@@ -94,24 +150,19 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(DevPlan d) {
   const int m = d.row_off[inst + 1] - r0;
   const int tid = threadIdx.x;
   if (d.f_mode[inst] == 0) {
+    // zl: right-hand side (then the result); zf: forward result; dg: diagonal
     const double* L = d.f_Ld + d.f_dense_off[inst];
-    for (int i = tid; i < m; i += kTrsvThreads) zl[i] = d.g[r0 + i];
-    __syncthreads();
-    // forward, column oriented: z_j = g_j / L_jj ; g_i -= L_ij z_j (i > j)
-    for (int j = 0; j < m; ++j) {
-      const double zj = zl[j] / L[(size_t)j * m + j];
-      __syncthreads();
-      for (int i = j + 1 + tid; i < m; i += kTrsvThreads) zl[i] -= L[(size_t)j * m + i] * zj;
-      if (tid == 0) zl[j] = zj;
-      __syncthreads();
+    const double* Lt = d.f_Ldt + d.f_dense_off[inst];
+    double* zf = zl + kTrsvDense;
+    double* dg = zl + 2 * kTrsvDense;
+    for (int i = tid; i < m; i += kTrsvThreads) {
+      zl[i] = d.g[r0 + i];
+      dg[i] = L[(size_t)i * m + i];
     }
-    // backward with L^T, column oriented: w_j = z_j / L_jj ; z_i -= L_ji w_j (i < j)
-    for (int j = m - 1; j >= 0; --j) {
-      const double wj = zl[j] / L[(size_t)j * m + j];
-      __syncthreads();
-      for (int i = tid; i < j; i += kTrsvThreads) zl[i] -= L[(size_t)i * m + j] * wj;
-      if (tid == 0) zl[j] = wj;
-      __syncthreads();
+    __syncthreads();
+    if (m > 0) {
+      trsv_sweep<R, PD, true>(L, m, zl, zf, dg);     // L z = g
+      trsv_sweep<R, PD, false>(Lt, m, zf, zl, dg);   // L^T w = z
     }
     double bw = 0.0;
     for (int i = tid; i < m; i += kTrsvThreads) {
@@ -165,22 +216,34 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(DevPlan d) {
   if (tid == 0) d.sc[inst * kNsc + SC_BW] = bw;
 }
 
+// A^T w' from the sliced-ELL copy of A^T: each wave takes chunks of 64
+// entries of the block and steps through their nonzeros together (each
+// entry's nonzeros in ascending row order, as in the CSR form).
 template <bool RELAX>
 __global__ __launch_bounds__(kThreads) void k_spmv_at(DevPlan d) {
   __shared__ double red[kThreads / 64 + 1];
   const int4 bd = d.eblk[blockIdx.x];
   const int inst = bd.x;
   if (d.st[inst * kNst + ST_FROZEN]) return;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nch = (bd.z - bd.y + 63) >> 6;
+  const int c0 = d.at_choff[blockIdx.x];
   double cpx = 0.0;
-  for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
+  for (int c = wid; c < nch; c += kThreads / 64) {
+    const int ch = c0 + c;
+    const int e = d.at_sent[(size_t)ch * 64 + lane];
+    const int len = d.at_chlen[ch];
+    const int32_t* srow = d.at_srow + d.at_chptr[ch] + lane;
+    const double* sval = d.at_sval + d.at_chptr[ch] + lane;
     double acc = 0.0, accy = 0.0;
-    const int q1 = d.at_ptr[e + 1];
-    for (int q = d.at_ptr[e]; q < q1; ++q) {
-      const int row = d.at_row[q];
-      const double av = d.at_val[q];
+#pragma unroll 4
+    for (int k = 0; k < len; ++k) {
+      const int row = srow[(size_t)k * 64];
+      const double av = sval[(size_t)k * 64];
       acc += av * d.w[row];
       if (RELAX) accy += av * d.y[row];   // y is still the previous iterate here
     }
+    if (e < 0) continue;
     if (RELAX) d.atyo[e] = accy;
     const double px = d.q[e] - d.pinv[e] * acc;
     d.atw[e] = acc;
@@ -367,11 +430,17 @@ void launch_r0(const DevPlan& d, hipStream_t st) {
   else hipLaunchKernelGGL(k_r0<false>, dim3(d.n_eblk), dim3(kThreads), 0, st, d);
 }
 void launch_spmv_a(const DevPlan& d, hipStream_t st) {
-  if (d.relax) hipLaunchKernelGGL(k_spmv_a<true>, dim3(d.n_rblk), dim3(kThreads), 0, st, d);
-  else hipLaunchKernelGGL(k_spmv_a<false>, dim3(d.n_rblk), dim3(kThreads), 0, st, d);
+  const dim3 grid(d.n_rblk, kRowChunk / (kThreads / 64));
+  if (d.relax) hipLaunchKernelGGL(k_spmv_a<true>, grid, dim3(kThreads), 0, st, d);
+  else hipLaunchKernelGGL(k_spmv_a<false>, grid, dim3(kThreads), 0, st, d);
 }
 void launch_trsv(const DevPlan& d, hipStream_t st) {
-  hipLaunchKernelGGL(k_trsv, dim3(d.B), dim3(kTrsvThreads), 0, st, d);
+  switch (d.trsv_rows) {
+    case 1: hipLaunchKernelGGL((k_trsv<1, 8>), dim3(d.B), dim3(kTrsvThreads), 0, st, d); break;
+    case 2: hipLaunchKernelGGL((k_trsv<2, 8>), dim3(d.B), dim3(kTrsvThreads), 0, st, d); break;
+    case 4: hipLaunchKernelGGL((k_trsv<4, 4>), dim3(d.B), dim3(kTrsvThreads), 0, st, d); break;
+    default: hipLaunchKernelGGL((k_trsv<8, 4>), dim3(d.B), dim3(kTrsvThreads), 0, st, d); break;
+  }
 }
 void launch_spmv_at(const DevPlan& d, hipStream_t st) {
   if (d.relax) hipLaunchKernelGGL(k_spmv_at<true>, dim3(d.n_eblk), dim3(kThreads), 0, st, d);

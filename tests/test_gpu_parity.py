@@ -172,6 +172,32 @@ def test_iterates_large_cliques(lib, torch_cuda):
     _log(f"  worst rel {w:.2e}")
 
 
+@pytest.mark.parametrize("m", [300, 600, 1100])
+def test_iterates_dense_factor_orders(lib, torch_cuda, m):
+    """Dense m x m factors of 300, 600 and 1100 rows: the dense triangular
+    sweeps with 2, 4 and 8 rows per thread (constraints of 25 entries each
+    make I + A P^-1 A^T about half full)."""
+    _log(f"iterates dense factor m={m}")
+    inst = configs.small_block_arrow(3, n=100, block=10, arrow=5, m=m, per_row=25)
+    w = _iterate_parity(lib, inst, 20)
+    _log(f"  worst rel {w:.2e}")
+
+
+def test_batch_mixed_dense_orders(lib, torch_cuda):
+    """A 20-row and a 600-row dense factor in one batch (the small one then
+    runs with the sweep shape of the large one)."""
+    _log("batch of dense factors m=20 and m=600")
+    insts = [configs.config0(), configs.small_block_arrow(3, n=100, block=10, arrow=5, m=600, per_row=25)]
+    b = lib.Solver(insts)
+    b.iterate(15)
+    for i, inst in enumerate(insts):
+        s = lib.Solver(inst)
+        s.iterate(15)
+        u1, v1 = s.get_state()
+        u2, v2 = b.get_state(i)
+        assert _rel(np.concatenate([u2, v2]), np.concatenate([u1, v1])) <= 1e-12
+
+
 def test_iterates_config2(lib, torch_cuda):
     _log("iterates config2")
     w = _iterate_parity(lib, configs.config2(), 20)
