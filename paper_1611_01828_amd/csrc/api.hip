@@ -89,6 +89,10 @@ struct cdcs_handle {
   // runs beside the small-clique Jacobi kernels: both write disjoint cliques
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // one stream per Jacobi bucket after the first non-empty one, so that the
+  // buckets run side by side (forked from and joined back into `stream`)
+  hipStream_t jst[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_jjoin[3] = {nullptr, nullptr, nullptr};
   cdcs_settings set{};
   int32_t B = 0;
   std::vector<Instance> inst;
@@ -254,12 +258,13 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
   { PhaseTimer t(h, PH_UPDATE_E); launch_update_e(d, st); }
   { PhaseTimer t(h, PH_UPDATE_R); launch_update_r(d, st); }
   const int kmaxs[4] = {16, 32, 64, kJacobiMax};
-  const bool small = h->ntasks[0] || h->ntasks[1] || h->ntasks[2] || h->ntasks[3];
-  const bool fork = h->ntasks[4] && small;
+  int nsmall = 0;
+  for (int bk = 0; bk < 4; ++bk) nsmall += h->ntasks[bk] ? 1 : 0;
+  const bool fork = h->ntasks[4] && nsmall;
+  if (fork || (nsmall > 1 && !h->ntasks[4])) HIPCHK(hipEventRecord(h->ev_fork, st));
   hipStream_t lst = st;
   if (fork) {
     lst = h->aux;
-    HIPCHK(hipEventRecord(h->ev_fork, st));
     HIPCHK(hipStreamWaitEvent(lst, h->ev_fork, 0));
   }
   if (h->ntasks[4]) {
@@ -271,10 +276,28 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
                              h->set.timing ? &hook : nullptr);
     }
   }
+  // Jacobi buckets: without large cliques the first non-empty one on
+  // `stream` and the others each on a stream of its own; beside the large
+  // cliques' chain of short launches they stay in sequence on `stream`,
+  // leaving compute units free for that chain (the critical path)
+  const int nside = h->ntasks[4] ? 0 : nsmall - 1;
+  int side = 0;
   for (int bk = 0; bk < 4; ++bk)
     if (h->ntasks[bk]) {
-      PhaseTimer t(h, PH_CONE16 + bk);
-      launch_cone_jacobi(d, h->tasks[bk], h->ntasks[bk], kmaxs[bk], h->jvar[bk], h->set.eig_fp32, st);
+      hipStream_t bs = st;
+      if (bk > 0 && side < nside) {
+        bs = h->jst[side];
+        HIPCHK(hipStreamWaitEvent(bs, h->ev_fork, 0));
+      }
+      {
+        PhaseTimer t(h, PH_CONE16 + bk, bs);
+        launch_cone_jacobi(d, h->tasks[bk], h->ntasks[bk], kmaxs[bk], h->jvar[bk], h->set.eig_fp32, bs);
+      }
+      if (bs != st) {
+        HIPCHK(hipEventRecord(h->ev_jjoin[side], bs));
+        HIPCHK(hipStreamWaitEvent(st, h->ev_jjoin[side], 0));
+        ++side;
+      }
     }
   if (fork) {
     HIPCHK(hipEventRecord(h->ev_join, lst));
@@ -732,6 +755,8 @@ const char* cdcs_last_error(void) { return g_last_error.c_str(); }
 void cdcs_destroy(cdcs_handle* h) {
   if (!h) return;
   if (h->aux) (void)hipStreamSynchronize(h->aux);
+  for (int i = 0; i < 3; ++i)
+    if (h->jst[i]) (void)hipStreamSynchronize(h->jst[i]);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
   for (int i = 0; i < 2; ++i)
@@ -744,6 +769,10 @@ void cdcs_destroy(cdcs_handle* h) {
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->aux) (void)hipStreamDestroy(h->aux);
+  for (int i = 0; i < 3; ++i) {
+    if (h->ev_jjoin[i]) (void)hipEventDestroy(h->ev_jjoin[i]);
+    if (h->jst[i]) (void)hipStreamDestroy(h->jst[i]);
+  }
   if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
@@ -773,9 +802,13 @@ int cdcs_setup_batch(int32_t count, const cdcs_problem* prob, const cdcs_setting
     }
     h->own_stream = true;
   }
-  if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+  bool made = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < 3 && made; ++i)
+    made = hipStreamCreateWithFlags(&h->jst[i], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&h->ev_jjoin[i], hipEventDisableTiming) == hipSuccess;
+  if (!made) {
     cdcs_destroy(h);
     return set_error(CDCS_E_DEVICE, "stream/event creation failed");
   }

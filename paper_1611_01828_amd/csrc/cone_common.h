@@ -68,6 +68,11 @@ template <int KMAX, int NT, typename T = double>
 __device__ void jacobi_lds(T* A, T* V, int K, int KP, T* rc, T* rs, T* rt, int* rp, int* rq, double* red) {
   const int tid = threadIdx.x;
   const int half = KP / 2;
+  // The work items of a round, idx = tid + NT u split as (idx / half,
+  // idx % half), are stepped without a division: (a0, b0) for u = 0 and
+  // (sa, sb) per step, computed once.
+  const int a0 = tid / half, b0 = tid - a0 * half;
+  const int sa = NT / half, sb = NT - sa * half;
   // off(A)^2 <= tol ||A||_F^2: (1e-16)^2 in FP64; in FP32 a little above
   // (2^-23)^2 so that rounding cannot keep the sweeps going
   const double tol = sizeof(T) == 8 ? 1e-32 : 1e-13;
@@ -82,15 +87,18 @@ __device__ void jacobi_lds(T* A, T* V, int K, int KP, T* rc, T* rs, T* rt, int* 
     off = block_sum<NT>(off, red);
     tot = block_sum<NT>(tot, red);
     if (!(off > tol * tot)) break;   // also stops on 0 or NaN
+    // round-robin positions (tid + r) mod (KP - 1) and (KP - 1 - tid + r)
+    // mod (KP - 1), stepped once per round
+    int pm = tid % (KP - 1), qm = (KP - 1 - tid) % (KP - 1);
     for (int r = 0; r < KP - 1; ++r) {
       if (tid < half) {
         int p, q;
         if (tid == 0) {
           p = 0;
-          q = 1 + (r % (KP - 1));
+          q = 1 + pm;   // r mod (KP - 1)
         } else {
-          p = 1 + ((tid + r) % (KP - 1));
-          q = 1 + ((KP - 1 - tid + r) % (KP - 1));
+          p = 1 + pm;
+          q = 1 + qm;
         }
         if (p > q) {
           const int tmp = p;
@@ -105,10 +113,12 @@ __device__ void jacobi_lds(T* A, T* V, int K, int KP, T* rc, T* rs, T* rt, int* 
         rs[tid] = s;
         rt[tid] = t;
       }
+      pm = (pm + 1 == KP - 1) ? 0 : pm + 1;
+      qm = (qm + 1 == KP - 1) ? 0 : qm + 1;
       __syncthreads();
       // A <- J^T A J on disjoint 2x2 blocks; V <- V J
-      for (int idx = tid; idx < half * half; idx += NT) {
-        const int a = idx / half, bq = idx - (idx / half) * half;
+      for (int idx = tid, a = a0, bq = b0; idx < half * half;
+           idx += NT, a += sa + (bq + sb >= half), bq += sb - (bq + sb >= half ? half : 0)) {
         const int pa = rp[a], qa = rq[a], pb = rp[bq], qb = rq[bq];
         if (a == bq) {
           const T t = rt[a];
@@ -129,8 +139,8 @@ __device__ void jacobi_lds(T* A, T* V, int K, int KP, T* rc, T* rs, T* rt, int* 
           A[qa * KMAX + qb] = y10 * sb + y11 * cb;
         }
       }
-      for (int idx = tid; idx < KP * half; idx += NT) {
-        const int i = idx / half, bq = idx - (idx / half) * half;
+      for (int idx = tid, i = a0, bq = b0; idx < KP * half;
+           idx += NT, i += sa + (bq + sb >= half), bq += sb - (bq + sb >= half ? half : 0)) {
         const int pb = rp[bq], qb = rq[bq];
         const T cb = rc[bq], sb = rs[bq];
         const T vp = V[i * KMAX + pb], vq = V[i * KMAX + qb];
