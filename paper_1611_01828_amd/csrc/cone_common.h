@@ -60,12 +60,29 @@ __device__ __forceinline__ void schur2(T app, T aqq, T apq, T& c, T& s, T& t) {
 
 using namespace jac;
 
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<double> { using type = double2; };
+template <>
+struct Pair2<float> { using type = float2; };
+
+// The rotations of one round, one per disjoint pair: (c, s) together and
+// p | q << 16 in one word, so that a work item reads each pair's rotation
+// with two LDS loads.
+template <int KMAX, typename T>
+struct JacRot {
+  typename Pair2<T>::type cs[KMAX / 2];
+  T t[KMAX / 2];      // tan(theta), for the 2x2 diagonal blocks
+  int pq[KMAX / 2];
+};
+
 // Cyclic Jacobi on the KP x KP (KP even, zero padded) matrix in LDS, in the
 // working precision T (double, or float for the FP32 variant; the
 // convergence sums are kept in double).  On return A holds the eigenvalues
 // on its diagonal and V the eigenvectors.
 template <int KMAX, int NT, typename T = double>
-__device__ void jacobi_lds(T* A, T* V, int K, int KP, T* rc, T* rs, T* rt, int* rp, int* rq, double* red) {
+__device__ void jacobi_lds(T* A, T* V, int K, int KP, JacRot<KMAX, T>& rot, double* red) {
   const int tid = threadIdx.x;
   const int half = KP / 2;
   // The work items of a round, idx = tid + NT u split as (idx / half,
@@ -107,45 +124,49 @@ __device__ void jacobi_lds(T* A, T* V, int K, int KP, T* rc, T* rs, T* rt, int* 
         }
         T c, s, t;
         schur2<T>(A[p * KMAX + p], A[q * KMAX + q], A[p * KMAX + q], c, s, t);
-        rp[tid] = p;
-        rq[tid] = q;
-        rc[tid] = c;
-        rs[tid] = s;
-        rt[tid] = t;
+        rot.pq[tid] = p | (q << 16);
+        rot.cs[tid].x = c;
+        rot.cs[tid].y = s;
+        rot.t[tid] = t;
       }
       pm = (pm + 1 == KP - 1) ? 0 : pm + 1;
       qm = (qm + 1 == KP - 1) ? 0 : qm + 1;
       __syncthreads();
-      // A <- J^T A J on disjoint 2x2 blocks; V <- V J
+      // A <- J^T A J on disjoint 2x2 blocks; V <- V J (neighbouring work
+      // items share the row pair and walk along rows of A and V)
       for (int idx = tid, a = a0, bq = b0; idx < half * half;
            idx += NT, a += sa + (bq + sb >= half), bq += sb - (bq + sb >= half ? half : 0)) {
-        const int pa = rp[a], qa = rq[a], pb = rp[bq], qb = rq[bq];
+        const int pqa = rot.pq[a], pqb = rot.pq[bq];
+        const int pa = pqa & 0xffff, qa = pqa >> 16, pb = pqb & 0xffff, qb = pqb >> 16;
         if (a == bq) {
-          const T t = rt[a];
+          const T t = rot.t[a];
           const T apq = A[pa * KMAX + qa];
           A[pa * KMAX + pa] -= t * apq;
           A[qa * KMAX + qa] += t * apq;
           A[pa * KMAX + qa] = T(0);
           A[qa * KMAX + pa] = T(0);
         } else {
-          const T ca = rc[a], sa = rs[a], cb = rc[bq], sb = rs[bq];
+          const auto ra = rot.cs[a], rb = rot.cs[bq];
+          const T ca = ra.x, sa_ = ra.y, cb = rb.x, sb_ = rb.y;
           const T x00 = A[pa * KMAX + pb], x01 = A[pa * KMAX + qb];
           const T x10 = A[qa * KMAX + pb], x11 = A[qa * KMAX + qb];
-          const T y00 = ca * x00 - sa * x10, y01 = ca * x01 - sa * x11;
-          const T y10 = sa * x00 + ca * x10, y11 = sa * x01 + ca * x11;
-          A[pa * KMAX + pb] = y00 * cb - y01 * sb;
-          A[pa * KMAX + qb] = y00 * sb + y01 * cb;
-          A[qa * KMAX + pb] = y10 * cb - y11 * sb;
-          A[qa * KMAX + qb] = y10 * sb + y11 * cb;
+          const T y00 = ca * x00 - sa_ * x10, y01 = ca * x01 - sa_ * x11;
+          const T y10 = sa_ * x00 + ca * x10, y11 = sa_ * x01 + ca * x11;
+          A[pa * KMAX + pb] = y00 * cb - y01 * sb_;
+          A[pa * KMAX + qb] = y00 * sb_ + y01 * cb;
+          A[qa * KMAX + pb] = y10 * cb - y11 * sb_;
+          A[qa * KMAX + qb] = y10 * sb_ + y11 * cb;
         }
       }
       for (int idx = tid, i = a0, bq = b0; idx < KP * half;
            idx += NT, i += sa + (bq + sb >= half), bq += sb - (bq + sb >= half ? half : 0)) {
-        const int pb = rp[bq], qb = rq[bq];
-        const T cb = rc[bq], sb = rs[bq];
+        const int pqb = rot.pq[bq];
+        const int pb = pqb & 0xffff, qb = pqb >> 16;
+        const auto rb = rot.cs[bq];
+        const T cb = rb.x, sb_ = rb.y;
         const T vp = V[i * KMAX + pb], vq = V[i * KMAX + qb];
-        V[i * KMAX + pb] = cb * vp - sb * vq;
-        V[i * KMAX + qb] = sb * vp + cb * vq;
+        V[i * KMAX + pb] = cb * vp - sb_ * vq;
+        V[i * KMAX + qb] = sb_ * vp + cb * vq;
       }
       __syncthreads();
     }

@@ -49,8 +49,7 @@ template <int KMAX, int NT>
 __global__ __launch_bounds__(NT) void k_adj_eig(AdjPlan ap, const int32_t* tasks) {
   __shared__ double A[KMAX * KMAX];
   __shared__ double V[KMAX * KMAX];
-  __shared__ double rc[KMAX / 2], rs[KMAX / 2], rt[KMAX / 2];
-  __shared__ int rp[KMAX / 2], rq[KMAX / 2];
+  __shared__ JacRot<KMAX, double> rot;
   __shared__ double red[NT / 64 + 1];
   const DevPlan& d = ap.d;
   const int k = tasks[blockIdx.x];
@@ -70,7 +69,7 @@ __global__ __launch_bounds__(NT) void k_adj_eig(AdjPlan ap, const int32_t* tasks
     V[i * KMAX + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi_lds<KMAX, NT>(A, V, K, KP, rc, rs, rt, rp, rq, red);
+  jacobi_lds<KMAX, NT>(A, V, K, KP, rot, red);
   double* out = const_cast<double*>(ap.eig) + ap.eig_off[k];
   for (int idx = threadIdx.x; idx < K * K; idx += NT) {
     const int i = idx / K, l = idx - (idx / K) * K;

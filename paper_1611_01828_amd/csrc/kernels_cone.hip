@@ -26,8 +26,7 @@ template <int KMAX, int NT, typename T>
 __global__ __launch_bounds__(NT) void k_cone_jacobi(DevPlan d, const int32_t* tasks) {
   __shared__ T A[KMAX * KMAX];
   __shared__ T V[KMAX * KMAX];
-  __shared__ T rc[KMAX / 2], rs[KMAX / 2], rt[KMAX / 2];
-  __shared__ int rp[KMAX / 2], rq[KMAX / 2];
+  __shared__ JacRot<KMAX, T> rot;
   __shared__ int sel[KMAX];
   __shared__ int meta[2];
   __shared__ double red[NT / 64 + 1];
@@ -52,7 +51,7 @@ __global__ __launch_bounds__(NT) void k_cone_jacobi(DevPlan d, const int32_t* ta
     V[i * KMAX + j] = (i == j) ? T(1) : T(0);
   }
   __syncthreads();
-  jacobi_lds<KMAX, NT, T>(A, V, K, KP, rc, rs, rt, rp, rq, red);
+  jacobi_lds<KMAX, NT, T>(A, V, K, KP, rot, red);
   choose_side<NT, T>(A, K, KMAX, sel, meta);
   const int nsel = meta[0], pos = meta[1];
   // epilogue over packed slots
@@ -97,8 +96,7 @@ __global__ __launch_bounds__(NT) void k_psd_jacobi(const int32_t* sizes, const i
                                                    double* out) {
   __shared__ T A[KMAX * KMAX];
   __shared__ T V[KMAX * KMAX];
-  __shared__ T rc[KMAX / 2], rs[KMAX / 2], rt[KMAX / 2];
-  __shared__ int rp[KMAX / 2], rq[KMAX / 2];
+  __shared__ JacRot<KMAX, T> rot;
   __shared__ int sel[KMAX];
   __shared__ int meta[2];
   __shared__ double red[NT / 64 + 1];
@@ -119,7 +117,7 @@ __global__ __launch_bounds__(NT) void k_psd_jacobi(const int32_t* sizes, const i
     V[i * KMAX + j] = (i == j) ? T(1) : T(0);
   }
   __syncthreads();
-  jacobi_lds<KMAX, NT, T>(A, V, K, KP, rc, rs, rt, rp, rq, red);
+  jacobi_lds<KMAX, NT, T>(A, V, K, KP, rot, red);
   choose_side<NT, T>(A, K, KMAX, sel, meta);
   const int nsel = meta[0], pos = meta[1];
   const int nslot = K * (K + 1) / 2;
