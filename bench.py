@@ -83,25 +83,49 @@ def phase_work(inst_sizes, prob_dims):
     return out
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when the summary is missing or the kernel source changed since."""
+def measured_traffic(kernel, summary="trd_symv_config1_traffic.md", source="kernels_large.hip"):
+    """HBM bytes per launch of `kernel` from a committed counter summary
+    (profiles/<summary>, one `<!-- traffic: {...} -->` record per kernel), or
+    None when it is missing or the kernel's source file changed since."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", f"{kernel}_config1_traffic.md")
-    src = os.path.join(ROOT, "paper_1611_01828_amd", "csrc", "kernels_large.hip")
+    path = os.path.join(ROOT, "profiles", summary)
+    src = os.path.join(ROOT, "paper_1611_01828_amd", "csrc", source)
     try:
         text = open(path).read()
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    m = re.search(r"<!-- traffic: (\{.*\}) -->", text)
-    if not m:
-        return None
-    rec = json.loads(m.group(1))
-    if rec.get("source_sha256") != digest:
-        return None
-    return rec.get("bytes_per_launch")
+    for m in re.finditer(r"<!-- traffic: (\{.*\}) -->", text):
+        rec = json.loads(m.group(1))
+        if rec.get("kernel") == kernel and rec.get("source_sha256") == digest:
+            return rec.get("bytes_per_launch")
+    return None
+
+
+def affine_work(insts, dims):
+    """Algorithmic HBM bytes of one launch of each streaming phase of the
+    affine step over a batch (every operand read or written once; gathers of
+    vectors that stay in cache counted once).  dims: per instance (nE, ns, m, p)."""
+    nE = sum(d[0] for d in dims)
+    ns = sum(d[1] for d in dims)
+    M = sum(d[2] for d in dims)
+    nnz = sum(len(inst.A[3]) for inst in insts)
+    tri = sum(8.0 * d[2] * (d[2] + 1) for d in dims)       # L for the forward sweep, L^T for the backward
+    return {
+        # s, z, v and the slot lists; x, c, P^-1 in; H^T(s+z+v)/2 and P^-1 r0 out
+        "r0_scatter": 8.0 * 3 * ns + 4.0 * ns + 4.0 * nE + 8.0 * 3 * nE + 8.0 * 2 * nE,
+        # A (value + column index), P^-1 r0 once, y and b in, g' out
+        "spmv_A": 12.0 * nnz + 8.0 * nE + 8.0 * 3 * M,
+        # the dense factor twice, g' in, w' out
+        "trsv": tri + 8.0 * 2 * M,
+        # A^T (value + row index), w' once, q, P^-1, c in; A^T w' and p_x out
+        "spmv_At": 12.0 * nnz + 8.0 * M + 8.0 * 3 * nE + 8.0 * 2 * nE,
+        # p_x, zt_x, A^T w', A^T zt_y, H^T(s+z+v)/2, D/2, c in; x out
+        "update_x": 8.0 * 7 * nE + 8.0 * nE,
+        # b, zt_y, w', y in; y out
+        "update_y": 8.0 * 4 * M + 8.0 * M,
+    }
 
 
 def timed_solve(cdcs, torch, inst, label, **settings):
@@ -351,10 +375,34 @@ def bench_batch(args, cdcs, configs):
         p.close()
     plain = len(sample) * args.steps / plain_t
     print(f"[bench] plain per instance: {plain:.0f} instance-iterations/s", file=sys.stderr, flush=True)
+    # the streaming phases of the affine step against the HBM roofline
+    # (per-launch durations from HIP events on the launch stream)
+    tm = cdcs.Solver(insts, timing=1)
+    tm.iterate(args.warmup)
+    tm.reset_phase_times()
+    tm.iterate(args.steps)
+    torch.cuda.synchronize()
+    phases = tm.phase_times()
+    dims = [tm.dims(i) for i in range(len(insts))]
+    tm.close()
+    work = affine_work(insts, dims)
+    affine = []
+    for name, nbytes in work.items():
+        ms, n = phases.get(name, (0.0, 0))
+        if not n:
+            continue
+        gbs = nbytes / (ms / n * 1e-3) / 1e9
+        affine.append({"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                       "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": nbytes,
+                       "avg_launch_ms": round(ms / n, 5),
+                       "traffic": measured_traffic(name, "affine_config3_traffic.md", "kernels_iter.hip")})
+    print(f"[bench] affine-step phases: {affine}", file=sys.stderr, flush=True)
     out = {"metric": "batched instance-iterations/s (256 block-arrow SDPs)", "value": fp64["value"],
            "unit": "instance-iter/s", "plain_value": round(plain, 1),
            "speedup_vs_plain": round(fp64["value"] / plain, 2), "steps": args.steps, "dtype": "f64",
-           "fp64": fp64, "fp64_autotuned": tuned, "fp32_eig_autotuned": fp32}
+           "fp64": fp64, "fp64_autotuned": tuned, "fp32_eig_autotuned": fp32,
+           "roofline_affine": affine,
+           "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1]}}
     print(json.dumps(out))
 
 
