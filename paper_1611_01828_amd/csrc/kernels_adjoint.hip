@@ -78,13 +78,28 @@ __global__ __launch_bounds__(NT) void k_adj_eig(AdjPlan ap, const int32_t* tasks
   for (int l = threadIdx.x; l < K; l += NT) out[K * K + l] = A[l * KMAX + l];
 }
 
+// A^T u at the 64 entries of sliced-ELL chunk ch (one per lane; see k_spmv_at)
+__device__ __forceinline__ double at_chunk_dot(const DevPlan& d, int ch, int lane, const double* u) {
+  const int len = d.at_chlen[ch];
+  const int32_t* srow = d.at_srow + d.at_chptr[ch] + lane;
+  const double* sval = d.at_sval + d.at_chptr[ch] + lane;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < len; ++k) acc += sval[(size_t)k * 64] * u[srow[(size_t)k * 64]];
+  return acc;
+}
+
 // 2. t and p = P^{-1} t
 __global__ __launch_bounds__(kThreads) void k_adj_rhs(AdjPlan ap) {
   const DevPlan& d = ap.d;
   const int4 bd = d.eblk[blockIdx.x];
-  for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
-    double aty = 0.0;
-    for (int q = d.at_ptr[e]; q < d.at_ptr[e + 1]; ++q) aty += d.at_val[q] * ap.mu_y[d.at_row[q]];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nch = (bd.z - bd.y + 63) >> 6;
+  for (int c = wid; c < nch; c += kThreads / 64) {
+    const int ch = d.at_choff[blockIdx.x] + c;
+    const int e = d.at_sent[(size_t)ch * 64 + lane];
+    const double aty = at_chunk_dot(d, ch, lane, ap.mu_y);
+    if (e < 0) continue;
     double hs = 0.0;
     for (int k = d.ent_sptr[e]; k < d.ent_sptr[e + 1]; ++k) {
       const int sl = d.ent_slots[k];
@@ -102,8 +117,21 @@ __global__ __launch_bounds__(kThreads) void k_adj_ap(AdjPlan ap) {
   const int4 bd = d.rblk[blockIdx.x];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int r = bd.y + wid; r < bd.z; r += kThreads / 64) {
+    // batches of 8 clamped loads per lane in flight (as in k_spmv_a)
     double acc = 0.0;
-    for (int q = d.a_ptr[r] + lane; q < d.a_ptr[r + 1]; q += 64) acc += d.a_val[q] * d.q[d.a_col[q]];
+    const int q0 = d.a_ptr[r], q1 = d.a_ptr[r + 1];
+    for (int qb = q0; qb < q1; qb += 64 * 8) {
+      int col[8];
+      double av[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int qc = min(qb + 64 * u + lane, q1 - 1);
+        col[u] = d.a_col[qc];
+        av[u] = d.a_val[qc];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += ((qb + 64 * u + lane < q1) ? av[u] : 0.0) * d.q[col[u]];
+    }
     acc = wave_sum(acc);
     if (lane == 0) d.g[r] = acc;
   }
@@ -119,9 +147,13 @@ __global__ __launch_bounds__(kThreads) void k_adj_a(AdjPlan ap) {
   const DevPlan& d = ap.d;
   const int4 bd = d.eblk[blockIdx.x];
   double ea = 0.0;
-  for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
-    double acc = 0.0;
-    for (int q = d.at_ptr[e]; q < d.at_ptr[e + 1]; ++q) acc += d.at_val[q] * d.w[d.at_row[q]];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nch = (bd.z - bd.y + 63) >> 6;
+  for (int c = wid; c < nch; c += kThreads / 64) {
+    const int ch = d.at_choff[blockIdx.x] + c;
+    const int e = d.at_sent[(size_t)ch * 64 + lane];
+    const double acc = at_chunk_dot(d, ch, lane, d.w);
+    if (e < 0) continue;
     const double a = d.q[e] - d.pinv[e] * acc;
     d.px[e] = a;
     ea += ap.ev[e] * a;

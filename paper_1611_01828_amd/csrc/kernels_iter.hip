@@ -38,13 +38,27 @@ __global__ __launch_bounds__(kThreads) void k_r0(DevPlan d) {
   if (d.st[inst * kNst + ST_FROZEN]) return;
   const double om3 = d.sc[inst * kNsc + SC_TAU] + d.sc[inst * kNsc + SC_KAPPA];
   for (int e = bd.y + threadIdx.x; e < bd.z; e += kThreads) {
+    // the entry's slots in batches of 4 with clamped indices, so that a
+    // batch's loads are in flight together; terms added in slot order
     double acc = 0.0, accv = 0.0;
-    const int k1 = d.ent_sptr[e + 1];
-    for (int k = d.ent_sptr[e]; k < k1; ++k) {
-      const int sl = d.ent_slots[k];
-      const double vv = d.v[sl];
-      acc += d.s[sl] + d.z[sl] + vv;
-      if (RELAX) accv += vv;
+    const int k0 = d.ent_sptr[e], k1 = d.ent_sptr[e + 1];
+    for (int kb = k0; kb < k1; kb += 4) {
+      int sl[4];
+      double sv[4], zv[4], vv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sl[u] = d.ent_slots[min(kb + u, k1 - 1)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sv[u] = d.s[sl[u]];
+        zv[u] = d.z[sl[u]];
+        vv[u] = d.v[sl[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (kb + u < k1) {
+          acc += sv[u] + zv[u] + vv[u];
+          if (RELAX) accv += vv[u];
+        }
     }
     if (RELAX) d.hvo[e] = accv;
     const double hs = 0.5 * acc;
