@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CDCS_ABI_VERSION 3
+#define CDCS_ABI_VERSION 4
 
 /* outcomes (cdcs_info.status) */
 enum {
@@ -122,6 +122,14 @@ typedef struct {
                           A^T over y and of H^T over v of the previous iterate
                           inside the existing kernels, and 4 vectors (3 nE,
                           1 m) of device memory; otherwise CDCS_E_ARG. */
+  int32_t eig_warm;    /* 1 = start the Jacobi eigen-decomposition of every clique of up to 96
+                          vertices from its eigenvectors of the previous iteration (Y is
+                          rotated to V^T Y V, nearly diagonal once the iterates settle, and
+                          the sweeps continue from there); the projection is the same up to
+                          rounding (it is unique).  Cold starts: the first iteration, the
+                          first after cdcs_set_state, and every 64th.  Costs sum_k K_k^2
+                          values of device memory.  A resumed run then matches an
+                          uninterrupted one to rounding, not bit for bit.  0 = off. */
 } cdcs_settings;
 
 typedef struct {
@@ -134,7 +142,7 @@ typedef struct {
 } cdcs_info;
 
 /* Fill s with eps_tol = 1e-4, max_iter = 2000, check_every = 1, timing = 0,
- * use_graph = 0, eig_fp32 = 0, autotune = 0, alpha = 1. */
+ * use_graph = 0, eig_fp32 = 0, autotune = 0, alpha = 1, eig_warm = 0. */
 void cdcs_default_settings(cdcs_settings* s);
 
 /* Build the cached data of step 1 (the m x m factor of the matrix of eq.

@@ -37,7 +37,7 @@ class Problem(C.Structure):
 class Settings(C.Structure):
     _fields_ = [("eps_tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("timing", C.c_int32), ("use_graph", C.c_int32), ("eig_fp32", C.c_int32),
-                ("autotune", C.c_int32), ("alpha", C.c_double)]
+                ("autotune", C.c_int32), ("alpha", C.c_double), ("eig_warm", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -50,7 +50,7 @@ class Info(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-ABI_VERSION = 3   # the layout of the structures above
+ABI_VERSION = 4   # the layout of the structures above
 
 EXPORTS = [
     "cdcs_default_settings", "cdcs_setup", "cdcs_setup_batch", "cdcs_iterate", "cdcs_solve",

@@ -691,6 +691,24 @@ int pack_and_upload(cdcs_handle* h) {
   if ((rc = dev_upload(h, (int32_t**)&d.clq_size, csize)) || (rc = dev_upload(h, (int32_t**)&d.clq_inst, cinst)) ||
       (rc = dev_upload(h, (int64_t**)&d.clq_slot, cslot)))
     return rc;
+  // warm-started Jacobi: K^2 stored eigenvector entries per Jacobi clique
+  d.warm_v = nullptr;
+  d.warm_off = nullptr;
+  if (h->set.eig_warm) {
+    std::vector<int64_t> woff(P, 0);
+    int64_t tot = 0;
+    for (int32_t g = 0; g < P; ++g)
+      if (csize[g] <= kJacobiMax) {
+        woff[g] = tot;
+        tot += (int64_t)csize[g] * csize[g];
+      }
+    const size_t esz = h->set.eig_fp32 ? sizeof(float) : sizeof(double);
+    double* wv = nullptr;
+    if ((rc = dev_zeros(h, &wv, (size_t)((tot * esz + sizeof(double) - 1) / sizeof(double)))) ||
+        (rc = dev_upload(h, (int64_t**)&d.warm_off, woff)))
+      return rc;
+    d.warm_v = wv;
+  }
   for (int bkt = 0; bkt < 5; ++bkt) {
     h->ntasks[bkt] = (int32_t)bk[bkt].size();
     if ((rc = dev_upload(h, &h->tasks[bkt], bk[bkt]))) return rc;
@@ -746,6 +764,7 @@ void cdcs_default_settings(cdcs_settings* s) {
   s->eig_fp32 = 0;
   s->autotune = 0;
   s->alpha = 1.0;
+  s->eig_warm = 0;
 }
 
 int cdcs_abi_version(void) { return CDCS_ABI_VERSION; }
@@ -791,6 +810,7 @@ int cdcs_setup_batch(int32_t count, const cdcs_problem* prob, const cdcs_setting
     return set_error(CDCS_E_ARG, "settings: eig_fp32 must be 0 or 1 and autotune 0, 1 or 2");
   if (!(set.alpha > 0.0 && set.alpha < 2.0))
     return set_error(CDCS_E_ARG, "settings: alpha must lie in (0, 2)");
+  if (set.eig_warm != 0 && set.eig_warm != 1) return set_error(CDCS_E_ARG, "settings: eig_warm must be 0 or 1");
   const auto t0 = std::chrono::steady_clock::now();
   cdcs_handle* h = new cdcs_handle();
   h->stream = (hipStream_t)stream;
@@ -1017,6 +1037,7 @@ int cdcs_set_state(cdcs_handle* h, int32_t inst, const double* u, const double* 
   HIPCHK(hipMemcpy(st, h->d.st + (size_t)inst * kNst, sizeof(st), hipMemcpyDeviceToHost));
   st[ST_STATUS] = CDCS_RUNNING;
   st[ST_FROZEN] = 0;
+  st[ST_WARM] = 0;   // stored eigenvectors belong to another iterate
   HIPCHK(hipMemcpy(h->d.st + (size_t)inst * kNst, st, sizeof(st), hipMemcpyHostToDevice));
   return 0;
 }

@@ -173,6 +173,97 @@ __device__ void jacobi_lds(T* A, T* V, int K, int KP, JacRot<KMAX, T>& rot, doub
   }
 }
 
+// A <- V^T A V on the leading K x K blocks in LDS (warm start of the Jacobi
+// iteration from the eigenvectors V of a nearby matrix), then symmetrised.
+// Each thread keeps its entries of a product in registers until all threads
+// have read the operand it overwrites.
+template <int KMAX, int NT, typename T>
+__device__ void similarity_lds(T* A, const T* V, int K) {
+  constexpr int NO = (KMAX * KMAX + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  T acc[NO];
+  // A V
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const int idx = tid + o * NT;
+    if (idx < K * K) {
+      const int i = idx / K, j = idx - (idx / K) * K;
+      T sum = T(0);
+      for (int l = 0; l < K; ++l) sum += A[i * KMAX + l] * V[l * KMAX + j];
+      acc[o] = sum;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const int idx = tid + o * NT;
+    if (idx < K * K) A[(idx / K) * KMAX + idx - (idx / K) * K] = acc[o];
+  }
+  __syncthreads();
+  // V^T (A V)
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const int idx = tid + o * NT;
+    if (idx < K * K) {
+      const int i = idx / K, j = idx - (idx / K) * K;
+      T sum = T(0);
+      for (int l = 0; l < K; ++l) sum += V[l * KMAX + i] * A[l * KMAX + j];
+      acc[o] = sum;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const int idx = tid + o * NT;
+    if (idx < K * K) A[(idx / K) * KMAX + idx - (idx / K) * K] = acc[o];
+  }
+  __syncthreads();
+  // (B + B^T) / 2: the thread of (i, j), i < j, writes both
+  for (int idx = tid; idx < K * K; idx += NT) {
+    const int i = idx / K, j = idx - (idx / K) * K;
+    if (i < j) {
+      const T m = T(0.5) * (A[i * KMAX + j] + A[j * KMAX + i]);
+      A[i * KMAX + j] = m;
+      A[j * KMAX + i] = m;
+    }
+  }
+  __syncthreads();
+}
+
+// V <- V (3 I - V^T V) / 2 on the leading K x K block (one Newton-Schulz
+// step towards the nearest orthogonal matrix: an orthogonality error e
+// becomes O(e^2)).  G is K x K scratch in LDS.
+template <int KMAX, int NT, typename T>
+__device__ void orthonormalize_lds(T* V, T* G, int K) {
+  constexpr int NO = (KMAX * KMAX + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < K * K; idx += NT) {
+    const int i = idx / K, j = idx - (idx / K) * K;
+    T sum = T(0);
+    for (int l = 0; l < K; ++l) sum += V[l * KMAX + i] * V[l * KMAX + j];
+    G[i * KMAX + j] = sum;
+  }
+  __syncthreads();
+  T acc[NO];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const int idx = tid + o * NT;
+    if (idx < K * K) {
+      const int i = idx / K, j = idx - (idx / K) * K;
+      T sum = T(0);
+      for (int l = 0; l < K; ++l) sum += V[i * KMAX + l] * G[l * KMAX + j];
+      acc[o] = T(1.5) * V[i * KMAX + j] - T(0.5) * sum;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const int idx = tid + o * NT;
+    if (idx < K * K) V[(idx / K) * KMAX + idx - (idx / K) * K] = acc[o];
+  }
+  __syncthreads();
+}
+
 // Select the cheaper side of the spectrum: Pi_+(Y) = sum_{l>0} lam_l v v^T
 // = Y - sum_{l<0} lam_l v v^T.  Fills sel[0..nsel) and returns sign flag
 // (1 = positive side).  Runs on thread 0 only; result broadcast via LDS.

@@ -25,7 +25,11 @@ enum Sc {
 };
 
 // status words per instance
-enum St { ST_STATUS = 0, ST_FROZEN, ST_ITER, kNst = 4 };
+// (ST_WARM: the cliques' stored eigenvectors belong to this instance's
+// previous iteration; cleared at setup and by a restored state)
+enum St { ST_STATUS = 0, ST_FROZEN, ST_ITER, ST_WARM, kNst = 4 };
+
+constexpr int kWarmRestart = 64;     // warm-started Jacobi: a cold start every this many iterations
 
 struct DevPlan {
   int32_t B;
@@ -63,6 +67,11 @@ struct DevPlan {
   double* atyo;               // A^T y (previous iterate)
   double* hvo;                // H^T v (previous iterate)
   double* axo;                // A x   (previous iterate), row space
+  // warm-started Jacobi (null when off): each Jacobi clique's eigenvectors
+  // of the previous iteration, K x K row-major in the working precision, at
+  // warm_off[clique] elements into warm_v
+  void* warm_v;
+  const int64_t* warm_off;
   // slot space
   double* s;
   double* z;

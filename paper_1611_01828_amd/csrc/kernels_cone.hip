@@ -10,6 +10,10 @@
 //   s+  = Pi_+(Y) = V max(Lambda, 0) V^T
 //   z+  = z - u_s + s+ = s+ - Y
 // plus the partial sums ||H_k x+ - s+||^2 and ||v+ - z+||^2 for the residuals.
+// Warm start (d.warm_v set): V starts from the clique's eigenvectors of the
+// previous iteration and Y is rotated to V^T Y V before the sweeps; the
+// rotations then accumulate onto that V, which is stored back for the next
+// iteration.
 // With relaxed steps 2-3 u_s and v+ are the blends of slot_arg / slot_vnew,
 // H_k reads u_hat_x (xh) for them and x+ for the residual.
 //
@@ -26,6 +30,7 @@ template <int KMAX, int NT, typename T>
 __global__ __launch_bounds__(NT) void k_cone_jacobi(DevPlan d, const int32_t* tasks) {
   __shared__ T A[KMAX * KMAX];
   __shared__ T V[KMAX * KMAX];
+  __shared__ T G[sizeof(T) == 4 ? KMAX * KMAX : 1];   // FP32 warm start: V^T V
   __shared__ JacRot<KMAX, T> rot;
   __shared__ int sel[KMAX];
   __shared__ int meta[2];
@@ -51,9 +56,30 @@ __global__ __launch_bounds__(NT) void k_cone_jacobi(DevPlan d, const int32_t* ta
     V[i * KMAX + j] = (i == j) ? T(1) : T(0);
   }
   __syncthreads();
+  T* vstore = nullptr;
+  if (d.warm_v) {
+    vstore = static_cast<T*>(d.warm_v) + d.warm_off[k];
+    const int32_t* sti = d.st + inst * kNst;
+    if (sti[ST_WARM] && sti[ST_ITER] % kWarmRestart != 0) {
+      for (int idx = tid; idx < K * K; idx += NT) {
+        const int i = idx / K, j = idx - (idx / K) * K;
+        V[i * KMAX + j] = vstore[idx];
+      }
+      __syncthreads();
+      // FP32: the stored rotations lose orthogonality at float rounding per
+      // iteration, cumulatively; one Newton-Schulz step restores it
+      if constexpr (sizeof(T) == 4) orthonormalize_lds<KMAX, NT, T>(V, G, K);
+      similarity_lds<KMAX, NT, T>(A, V, K);
+    }
+  }
   jacobi_lds<KMAX, NT, T>(A, V, K, KP, rot, red);
   choose_side<NT, T>(A, K, KMAX, sel, meta);
   const int nsel = meta[0], pos = meta[1];
+  if (vstore)
+    for (int idx = tid; idx < K * K; idx += NT) {
+      const int i = idx / K, j = idx - (idx / K) * K;
+      vstore[idx] = V[i * KMAX + j];
+    }
   // epilogue over packed slots
   const int nslot = K * (K + 1) / 2;
   double ex = 0.0, ev = 0.0;

@@ -434,6 +434,7 @@ __global__ __launch_bounds__(64) void k_scalar2(DevPlan d, double eps_tol, int32
   sc[SC_DINF2] = dinf2;
   const int it = st[ST_ITER] + 1;
   st[ST_ITER] = it;
+  st[ST_WARM] = 1;
   if (stop && status == 0 && it >= max_iter) status = 4;
   st[ST_STATUS] = status;
   if (stop && status != 0) st[ST_FROZEN] = 1;
