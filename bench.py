@@ -301,8 +301,9 @@ def main():
 
 def bench_batch(args, cdcs, configs):
     """Config 3: one batched handle for all instances vs one handle per instance;
-    FP64 with the default and the autotuned Jacobi tiles, and the FP32-eigensolve
-    variant with its errors against FP64."""
+    FP64 with the default and the autotuned Jacobi tiles, the FP32-eigensolve
+    variant with its errors against FP64, and the warm-started Jacobi (FP64 and
+    FP32)."""
     import numpy as np
     import torch
     t0 = time.perf_counter()
@@ -341,6 +342,12 @@ def bench_batch(args, cdcs, configs):
     fp64, inf64 = run("FP64, default tiles")
     tuned, _ = run("FP64, autotuned tiles", autotune=1)
     fp32, inf32 = run("FP32 eigensolves, autotuned tiles", eig_fp32=1, autotune=1)
+    # warm-started Jacobi: the same projections (to rounding), fewer sweeps
+    warm, infw = run("FP64, warm-started Jacobi", eig_warm=1)
+    warm["iterations_vs_fp64"] = {"max_abs_delta": int(max(abs(infw[i]["iter"] - inf64[i]["iter"]) for i in range(len(insts)))),
+                                  "obj_rel_max": float(max(abs(infw[i]["obj_p"] - inf64[i]["obj_p"]) /
+                                                           max(1.0, abs(inf64[i]["obj_p"])) for i in range(len(insts))))}
+    warm32, _ = run("FP32 eigensolves, warm-started Jacobi", eig_fp32=1, eig_warm=1)
     # FP32 against FP64 on every instance that both solved
     both = [i for i in range(len(insts)) if inf64[i]["status"] == cdcs.SOLVED and inf32[i]["status"] == cdcs.SOLVED]
     rel = [abs(inf32[i]["obj_p"] - inf64[i]["obj_p"]) / max(1.0, abs(inf64[i]["obj_p"])) for i in both]
@@ -401,6 +408,7 @@ def bench_batch(args, cdcs, configs):
            "unit": "instance-iter/s", "plain_value": round(plain, 1),
            "speedup_vs_plain": round(fp64["value"] / plain, 2), "steps": args.steps, "dtype": "f64",
            "fp64": fp64, "fp64_autotuned": tuned, "fp32_eig_autotuned": fp32,
+           "fp64_warm_jacobi": warm, "fp32_eig_warm_jacobi": warm32,
            "roofline_affine": affine,
            "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1]}}
     print(json.dumps(out))
