@@ -12,6 +12,10 @@ the CPU oracle timed on a bounded sample of the same workload.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-solve] [--alpha A]
 
+By default the timed region is the paper's whole iteration budget (2000 ADMM
+iterations after one warm-up), since the cost of an iteration varies along
+the solve (more eigenpairs per large clique later, clustered eigenvalues).
+
 Secondary measurements (their own JSON line, not the headline):
   --workload batch   256 block-arrow SDPs in one batched solve vs the plain
                      path run instance by instance
@@ -154,15 +158,23 @@ def timed_solve(cdcs, torch, inst, label, **settings):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed iterations (default: 2000 for maxcut, the paper's iteration limit, "
+                         "whose cost per iteration varies along the solve; 20 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed iterations first (default 1; 3 otherwise)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-4 solve")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--eig-warm", type=int, default=0, choices=[0, 1],
+                    help="warm-start the Jacobi eigen-decompositions (settings.eig_warm)")
     ap.add_argument("--alpha", type=float, default=1.8,
                     help="relaxation of the second solve (1 = skip it; the value is always alpha = 1)")
     ap.add_argument("--workload", choices=["maxcut", "batch", "grad"], default="maxcut")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 2000 if args.workload == "maxcut" else 20
+    if args.warmup is None:
+        args.warmup = 1 if args.workload == "maxcut" else 3
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               f"(independent instances shard across GPUs without exchange; see DESIGN.md)", file=sys.stderr)
@@ -188,33 +200,43 @@ def main():
 
     # timed region: the iteration replayed from a captured HIP graph
     t0 = time.perf_counter()
-    solver = cdcs.Solver(inst, use_graph=1)
+    ew = args.eig_warm
+    solver = cdcs.Solver(inst, use_graph=1, eig_warm=ew)
     setup_s = time.perf_counter() - t0
     dims = solver.dims()
     print(f"[bench] setup {setup_s:.2f}s dims(nE, ns, m, p)={dims}", file=sys.stderr, flush=True)
     solver.iterate(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    solver.iterate(args.steps)
+    left = args.steps
+    while left > 0:                   # chunks of 500, with a progress line between them
+        n = min(500, left)
+        solver.iterate(n)
+        left -= n
+        if left:
+            print(f"[bench] timed: {args.steps - left} iterations, {time.perf_counter() - t0:.1f}s",
+                  file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     its = args.steps / dt
     print(f"[bench] {args.steps} iterations in {dt:.3f}s -> {its:.1f} it/s (graph replay)", file=sys.stderr, flush=True)
     solver.close()
 
-    # per-kernel times: the same iterations launched one by one with a HIP
-    # event pair around every launch on the stream it runs on
-    timed = cdcs.Solver(inst, timing=1)
+    # per-kernel times: the first min(K, 200) of the same iterations launched
+    # one by one with a HIP event pair around every launch on its stream
+    ev_steps = min(args.steps, 200)
+    timed = cdcs.Solver(inst, timing=1, eig_warm=ew)
     timed.iterate(args.warmup)
     timed.reset_phase_times()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    timed.iterate(args.steps)
+    timed.iterate(ev_steps)
     torch.cuda.synchronize()
     dt_ev = time.perf_counter() - t0
     phases = timed.phase_times()
     timed.close()
-    print(f"[bench] event-timed pass: {1e3 * dt_ev / args.steps:.2f} ms/iteration", file=sys.stderr, flush=True)
+    print(f"[bench] event-timed pass ({ev_steps} iterations): {1e3 * dt_ev / ev_steps:.2f} ms/iteration",
+          file=sys.stderr, flush=True)
 
     # dominant kernel and its roofline position (per-launch averages from HIP events)
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()}
@@ -233,17 +255,17 @@ def main():
         roof = {"kernel": dom, "bound": bound, "achieved": round(ach, 4), "peak": peak, "unit": unit,
                 "frac": round(ach / peak, 6), "traffic": measured_traffic(dom),
                 "work_per_launch": amount, "avg_launch_ms": round(per_launch[dom], 5),
-                "launches_per_step": phases[dom][1] / args.steps,
-                "ms_per_step_in_kernel": round(phases[dom][0] / args.steps, 4)}
+                "launches_per_step": phases[dom][1] / ev_steps,
+                "ms_per_step_in_kernel": round(phases[dom][0] / ev_steps, 4)}
 
     tol = tol_relaxed = None
     if not args.no_solve:
-        tol = timed_solve(cdcs, torch, inst, "solve")
+        tol = timed_solve(cdcs, torch, inst, "solve", eig_warm=ew)
         tol["setup_s"] = round(setup_s, 3)
         if args.alpha != 1.0:
             # the over-relaxed form of the same ADMM: its cost per iteration
             # (graph replay, as the value) and its time to the tolerance
-            rs = cdcs.Solver(inst, use_graph=1, alpha=args.alpha)
+            rs = cdcs.Solver(inst, use_graph=1, alpha=args.alpha, eig_warm=ew)
             rs.iterate(args.warmup)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -251,7 +273,8 @@ def main():
             torch.cuda.synchronize()
             rit = args.steps / (time.perf_counter() - t0)
             rs.close()
-            tol_relaxed = timed_solve(cdcs, torch, inst, f"relaxed solve (alpha {args.alpha})", alpha=args.alpha)
+            tol_relaxed = timed_solve(cdcs, torch, inst, f"relaxed solve (alpha {args.alpha})", alpha=args.alpha,
+                                      eig_warm=ew)
             tol_relaxed = {"alpha": args.alpha, "iter_per_s": round(rit, 3), **tol_relaxed}
 
     cpu = None
@@ -288,13 +311,14 @@ def main():
         "config": {"workload": "max-cut relaxation, G(n=2000, M=6000) random graph, C=-L, A_i=e_i e_i^T, b=1, "
                                "min-degree chordal extension",
                    "n": inst.n, "m": inst.m, "cliques": len(sizes), "max_clique": max(sizes),
-                   "nE": dims[0], "ns": dims[1], "eps_tol": 1e-4},
+                   "nE": dims[0], "ns": dims[1], "eps_tol": 1e-4, "eig_warm": ew},
         "roofline": roof,
         "cpu_baseline": cpu,
         "time_to_1e-4": tol,
         "time_to_1e-4_relaxed": tol_relaxed,
-        "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1]},
-        "event_timed_ms_per_step": round(1e3 * dt_ev / args.steps, 4),
+        "phases_ms_per_step": {k: round(v[0] / ev_steps, 4) for k, v in phases.items() if v[1]},
+        "event_timed_ms_per_step": round(1e3 * dt_ev / ev_steps, 4),
+        "event_timed_steps": ev_steps,
     }
     print(json.dumps(out))
 
