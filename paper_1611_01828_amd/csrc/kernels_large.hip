@@ -1002,13 +1002,15 @@ __global__ __launch_bounds__(64) void k_eig_single_wide(LargeArgs a) {
 //     Members are taken in order; for each, lane 0 factors T - lambda I and
 //     runs the sequential solves on LU factors and an iterate held in LDS, and
 //     after every solve the wave orthogonalises the iterate against the
-//     cluster's earlier members (twice) and normalises it.  The finished
+//     cluster's earlier members (classical Gram-Schmidt, twice) and
+//     normalises it.  The finished
 //     vector goes to its column of Z (scale 1).
 template <bool ADMM>
 __global__ __launch_bounds__(64) void k_eig_cluster(LargeArgs a) {
   __shared__ double sd[1024], se[1024];
   __shared__ double F[6 * 1024];
   __shared__ double slam[512];
+  __shared__ double sdot[512];
   __shared__ int span[2];
   int K;
   int64_t base;
@@ -1053,14 +1055,35 @@ __global__ __launch_bounds__(64) void k_eig_cluster(LargeArgs a) {
     for (int it = 0; it < 3; ++it) {
       if (lane == 0) (void)tri_solve<8>(f, 1, (size_t)K, K, z, 1, 1.0);
       __syncthreads();
-      for (int pass = 0; pass < 2; ++pass)
-        for (int p = c0; p < t; ++p) {
-          const double* q = w.Z + (size_t)p * K;
-          double dot = 0.0;
-          for (int i = lane; i < K; i += 64) dot += q[i] * z[i];
-          dot = wave_sum(dot);
-          for (int i = lane; i < K; i += 64) z[i] -= dot * q[i];
+      // classical Gram-Schmidt applied twice against the cluster's finished
+      // members: all their dot products with z first (16 at a time, loads in
+      // flight together), then one update, instead of one dependent
+      // dot-and-update round per member
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int p0 = c0; p0 < t; p0 += 16) {
+          const int np = min(16, t - p0);
+          double dots[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) dots[u] = 0.0;
+          for (int i = lane; i < K; i += 64) {
+            const double zi = z[i];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) dots[u] += w.Z[(size_t)(p0 + min(u, np - 1)) * K + i] * zi;
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const double s = wave_sum(dots[u]);
+            if (lane == 0 && u < np) sdot[p0 - c0 + u] = s;
+          }
         }
+        __syncthreads();
+        for (int i = lane; i < K; i += 64) {
+          double acc = 0.0;
+          for (int p = c0; p < t; ++p) acc += sdot[p - c0] * w.Z[(size_t)p * K + i];
+          z[i] -= acc;
+        }
+        __syncthreads();
+      }
       double nn = 0.0;
       for (int i = lane; i < K; i += 64) nn += z[i] * z[i];
       const double sc = 1.0 / sqrt(wave_sum(nn));
