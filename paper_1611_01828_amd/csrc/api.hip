@@ -554,12 +554,12 @@ int pack_and_upload(cdcs_handle* h) {
   std::vector<int32_t> fmode(B), perm(M, 0), lptr, lcol, uptr, ucol, flev_off(B + 1, 0), flev_ptr,
       flev_rows, blev_off(B + 1, 0), blev_ptr, blev_rows;
   std::vector<int64_t> fdoff(B, 0);
-  std::vector<double> Ld, Ldt, fdiag(M, 1.0), lval, uval;
+  std::vector<double> Ld, Ldt, Kinv, fdiag(M, 1.0), lval, uval;
   int32_t dense_m = 0;
   for (int32_t i = 0; i < B; ++i) {
     const Factor& f = I[i].fac;
     const int32_t ro = h->row_off[i];
-    fmode[i] = f.dense ? 0 : 1;
+    fmode[i] = f.dense ? (f.Kinv.empty() ? 0 : 2) : 1;
     if (f.dense) {
       fdoff[i] = (int64_t)Ld.size();
       Ld.insert(Ld.end(), f.Ld.begin(), f.Ld.end());
@@ -567,6 +567,8 @@ int pack_and_upload(cdcs_handle* h) {
       for (int32_t c = 0; c < f.m; ++c)
         for (int32_t r = 0; r < f.m; ++r) Ldt[fdoff[i] + (size_t)r * f.m + c] = f.Ld[(size_t)c * f.m + r];
       dense_m = std::max(dense_m, f.m);
+      Kinv.resize(Ld.size());
+      if (!f.Kinv.empty()) std::copy(f.Kinv.begin(), f.Kinv.end(), Kinv.begin() + fdoff[i]);
       for (int32_t r = 0; r < f.m; ++r) lptr.push_back((int32_t)lcol.size());
       lptr.push_back((int32_t)lcol.size());
       for (int32_t r = 0; r < f.m; ++r) uptr.push_back((int32_t)ucol.size());
@@ -596,6 +598,7 @@ int pack_and_upload(cdcs_handle* h) {
   blev_ptr.push_back((int32_t)blev_rows.size());
   if ((rc = dev_upload(h, (int32_t**)&d.f_mode, fmode)) || (rc = dev_upload(h, (int64_t**)&d.f_dense_off, fdoff)) ||
       (rc = dev_upload(h, (double**)&d.f_Ld, Ld)) || (rc = dev_upload(h, (double**)&d.f_Ldt, Ldt)) ||
+      (rc = dev_upload(h, (double**)&d.f_Kinv, Kinv)) ||
       (rc = dev_upload(h, (int32_t**)&d.f_perm, perm)) ||
       (rc = dev_upload(h, (double**)&d.f_diag, fdiag)) || (rc = dev_upload(h, (int32_t**)&d.f_lptr, lptr)) ||
       (rc = dev_upload(h, (int32_t**)&d.f_lcol, lcol)) || (rc = dev_upload(h, (double**)&d.f_lval, lval)) ||
@@ -749,6 +752,7 @@ int pack_and_upload(cdcs_handle* h) {
 }
 
 bool valid_inst(const cdcs_handle* h, int32_t inst) { return h && inst >= 0 && inst < h->B; }
+
 
 }  // namespace
 

@@ -101,10 +101,11 @@ struct DevPlan {
   const int32_t* at_srow;
   const double* at_sval;
   // m x m factor per instance
-  const int32_t* f_mode;      // 0 dense, 1 sparse
+  const int32_t* f_mode;      // 0 dense, 1 sparse, 2 dense with K^{-1} cached (small m)
   const int64_t* f_dense_off; // offset of the dense column-major factor
   const double* f_Ld;
   const double* f_Ldt;        // the transposes of the dense factors (same offsets)
+  const double* f_Kinv;       // mode 2: K^{-1} = L^{-T} L^{-1}, m x m (same offsets)
   int32_t trsv_rows;          // rows per thread the dense sweeps need (1, 2, 4 or 8)
   const int32_t* f_perm;      // at row_off (local indices)
   const double* f_diag;       // at row_off

@@ -163,6 +163,30 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(DevPlan d) {
   const int r0 = d.row_off[inst];
   const int m = d.row_off[inst + 1] - r0;
   const int tid = threadIdx.x;
+  if (d.f_mode[inst] == 2) {
+    // w' = K^{-1} g' with K^{-1} cached at setup: a product with no chain of
+    // dependent column steps; K^{-1} read column by column (coalesced), g'
+    // broadcast from LDS, loads 32 columns at a time (clamped, then masked)
+    const double* Ki = d.f_Kinv + d.f_dense_off[inst];
+    for (int i = tid; i < m; i += kTrsvThreads) zl[i] = d.g[r0 + i];
+    __syncthreads();
+    double bw = 0.0;
+    for (int i = tid; i < m; i += kTrsvThreads) {
+      double acc = 0.0;
+      for (int j0 = 0; j0 < m; j0 += 32) {
+        double kv[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) kv[u] = Ki[(size_t)min(j0 + u, m - 1) * m + i];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) acc += (j0 + u < m) ? kv[u] * zl[min(j0 + u, m - 1)] : 0.0;
+      }
+      d.w[r0 + i] = acc;
+      bw += d.b[r0 + i] * acc;
+    }
+    bw = block_sum<kTrsvThreads>(bw, red);
+    if (tid == 0) d.sc[inst * kNsc + SC_BW] = bw;
+    return;
+  }
   if (d.f_mode[inst] == 0) {
     // zl: right-hand side (then the result); zf: forward result; dg: diagonal
     const double* L = d.f_Ld + d.f_dense_off[inst];

@@ -17,11 +17,15 @@ struct Error {
 };
 
 // Cholesky factor of K = I + A P^{-1} A^T for one instance (m x m).
+constexpr int32_t kInvOrder = 512;
+
 struct Factor {
   int32_t m = 0;
   bool dense = true;
-  // dense: column-major lower m x m
+  // dense: column-major lower m x m; for m <= kInvOrder also K^{-1} (m x m,
+  // both triangles), so that the device solve is one matrix-vector product
   std::vector<double> Ld;
+  std::vector<double> Kinv;
   // sparse: Kp = K[perm][:, perm] = L L^T
   std::vector<int32_t> perm;
   std::vector<double> diag;                       // L_ii

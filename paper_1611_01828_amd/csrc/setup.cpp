@@ -151,6 +151,27 @@ int factor_K(int32_t m, const std::vector<int32_t>& aptr, const std::vector<int3
       for (int32_t k = 0; k < j; ++k) L[(size_t)j * m + k] = 0.0;   // clear upper
     }
     f.Ld.swap(L);
+    if (m <= kInvOrder) {
+      // K^{-1} = L^{-T} L^{-1}: X = L^{-1} column by column (L x = e_c by
+      // forward substitution), then X^T X
+      std::vector<double> X((size_t)m * m, 0.0);
+      for (int32_t c = 0; c < m; ++c) {
+        double* x = &X[(size_t)c * m];
+        x[c] = 1.0;
+        for (int32_t j = c; j < m; ++j) {
+          x[j] /= f.Ld[(size_t)j * m + j];
+          for (int32_t i = j + 1; i < m; ++i) x[i] -= f.Ld[(size_t)j * m + i] * x[j];
+        }
+      }
+      f.Kinv.assign((size_t)m * m, 0.0);
+      for (int32_t c = 0; c < m; ++c)
+        for (int32_t r = c; r < m; ++r) {
+          double s = 0.0;
+          for (int32_t k = r; k < m; ++k) s += X[(size_t)r * m + k] * X[(size_t)c * m + k];
+          f.Kinv[(size_t)c * m + r] = s;
+          f.Kinv[(size_t)r * m + c] = s;
+        }
+    }
     return 0;
   }
   // sparse: minimum-degree order, structure from the elimination game
