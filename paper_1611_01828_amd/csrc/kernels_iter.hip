@@ -256,17 +256,28 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(DevPlan d) {
 
 // A^T w' from the sliced-ELL copy of A^T: each wave takes chunks of 64
 // entries of the block and steps through their nonzeros together (each
-// entry's nonzeros in ascending row order, as in the CSR form).
+// entry's nonzeros in ascending row order, as in the CSR form).  The chunks
+// hold the block's entries in sorted order, so the per-entry operands and
+// results go through LDS: read and written in entry order (coalesced),
+// addressed in chunk order.
 template <bool RELAX>
 __global__ __launch_bounds__(kThreads) void k_spmv_at(DevPlan d) {
+  static_assert(kEntChunk <= 1024, "an entry block fits the LDS staging");
   __shared__ double red[kThreads / 64 + 1];
+  __shared__ double s0[1024], s1[1024];   // q then p_x; P^{-1} then A^T w'
+  __shared__ double s2[RELAX ? 1024 : 1];  // A^T y of the previous iterate
   const int4 bd = d.eblk[blockIdx.x];
   const int inst = bd.x;
   if (d.st[inst * kNst + ST_FROZEN]) return;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int nch = (bd.z - bd.y + 63) >> 6;
+  const int n = bd.z - bd.y;
+  const int nch = (n + 63) >> 6;
   const int c0 = d.at_choff[blockIdx.x];
-  double cpx = 0.0;
+  for (int l = threadIdx.x; l < n; l += kThreads) {
+    s0[l] = d.q[bd.y + l];
+    s1[l] = d.pinv[bd.y + l];
+  }
+  __syncthreads();
   for (int c = wid; c < nch; c += kThreads / 64) {
     const int ch = c0 + c;
     const int e = d.at_sent[(size_t)ch * 64 + lane];
@@ -282,10 +293,19 @@ __global__ __launch_bounds__(kThreads) void k_spmv_at(DevPlan d) {
       if (RELAX) accy += av * d.y[row];   // y is still the previous iterate here
     }
     if (e < 0) continue;
-    if (RELAX) d.atyo[e] = accy;
-    const double px = d.q[e] - d.pinv[e] * acc;
-    d.atw[e] = acc;
+    const int l = e - bd.y;
+    if (RELAX) s2[l] = accy;
+    s0[l] = s0[l] - s1[l] * acc;   // p_x
+    s1[l] = acc;
+  }
+  __syncthreads();
+  double cpx = 0.0;
+  for (int l = threadIdx.x; l < n; l += kThreads) {
+    const int e = bd.y + l;
+    const double px = s0[l];
     d.px[e] = px;
+    d.atw[e] = s1[l];
+    if (RELAX) d.atyo[e] = s2[l];
     cpx += d.c[e] * px;
   }
   cpx = block_sum<kThreads>(cpx, red);
