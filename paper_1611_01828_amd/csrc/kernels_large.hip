@@ -999,12 +999,14 @@ __global__ __launch_bounds__(64) void k_eig_single_wide(LargeArgs a) {
 // (d) eigenvectors of the clustered eigenvalues (the isolated ones are (c)):
 //     one 64-lane workgroup per cluster (the c-th run of eigenvalues whose
 //     consecutive gaps are at most 1e-5 ||T||, found by a scan of lam).
-//     Members are taken in order; for each, lane 0 factors T - lambda I and
-//     runs the sequential solves on LU factors and an iterate held in LDS, and
-//     after every solve the wave orthogonalises the iterate against the
-//     cluster's earlier members (classical Gram-Schmidt, twice) and
-//     normalises it.  The finished
-//     vector goes to its column of Z (scale 1).
+//     Each member's factorisation of T - lambda I, start vector and first
+//     solve depend on no other member: they run first, one lane per member,
+//     on the element-major scratch of the wide form.  Then the members are
+//     taken in order: factors and iterate are copied to LDS, and three times
+//     the wave orthogonalises the iterate against the cluster's finished
+//     members (classical Gram-Schmidt, twice) and normalises it, with lane 0's
+//     sequential solves in between.  The finished vector goes to its column of
+//     Z (scale 1).
 template <bool ADMM>
 __global__ __launch_bounds__(64) void k_eig_cluster(LargeArgs a) {
   __shared__ double sd[1024], se[1024];
@@ -1046,15 +1048,28 @@ __global__ __launch_bounds__(64) void k_eig_cluster(LargeArgs a) {
   const int c0 = span[0], c1 = span[1];
   if (c0 < 0) return;
   const double tiny = kEps * tnorm;
+  // (i) per member, one lane each: factors, start vector, first solve
+  //     (entry i of array a of member t at (a K + i) r + t; a = 5: iterate)
+  double* X = w.S;
+  const size_t KR = (size_t)K * r;
+  for (int t = c0 + lane; t < c1; t += 64) {
+    tri_factor(sd, se, K, slam[t], tiny, X + t, r, KR);
+    double* zt = X + 5 * KR + t;
+    for (int i = 0; i < K; ++i) zt[(size_t)i * r] = hash_unit((uint32_t)t, (uint32_t)i);
+    (void)tri_solve<32>(X + t, r, KR, K, zt, r, 1.0);
+  }
+  __syncthreads();
+  // (ii) members in order
   double* f = F;              // LU arrays a = 0..4 at f[a K + i]
   double* z = F + 5 * K;      // the member's iterate
   for (int t = c0; t < c1; ++t) {
-    if (lane == 0) tri_factor(sd, se, K, slam[t], tiny, f, 1, (size_t)K);
-    for (int i = lane; i < K; i += 64) z[i] = hash_unit((uint32_t)t, (uint32_t)i);
+    for (int idx = lane; idx < 6 * K; idx += 64) F[idx] = X[(size_t)idx * r + t];
     __syncthreads();
     for (int it = 0; it < 3; ++it) {
-      if (lane == 0) (void)tri_solve<8>(f, 1, (size_t)K, K, z, 1, 1.0);
-      __syncthreads();
+      if (it > 0) {
+        if (lane == 0) (void)tri_solve<8>(f, 1, (size_t)K, K, z, 1, 1.0);
+        __syncthreads();
+      }
       // classical Gram-Schmidt applied twice against the cluster's finished
       // members: all their dot products with z first (16 at a time, loads in
       // flight together), then one update, instead of one dependent
