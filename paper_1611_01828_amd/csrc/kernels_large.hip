@@ -521,18 +521,26 @@ __global__ __launch_bounds__(kTT) void k_trd_trail(LargeArgs a, int p) {
   const int tid = threadIdx.x;
   // A22 -= V Wp^T + Wp V^T on a 128 x 64 tile (both triangles), panel rows
   // staged in LDS, 4 x 4 outputs per thread
+  // (staging and the final read-modify-write use clamped indices: loads
+  // that sit behind a bounds test compile into one round trip each)
   const int r0 = jn + (tile % ntr) * 128, c0 = jn + (tile / ntr) * 64;
-  for (int idx = tid; idx < 128 * kNB; idx += kTT) {
-    const int rr = idx & 127, l = idx >> 7;
-    const bool ok = (r0 + rr < K) && l < nb;
-    pr_v[l][rr] = ok ? b.V[(size_t)l * ld + r0 + rr] : 0.0;
-    pr_w[l][rr] = ok ? b.Wp[(size_t)l * ld + r0 + rr] : 0.0;
+#pragma unroll
+  for (int k = 0; k < 128 * kNB / kTT; ++k) {
+    const int idx = tid + k * kTT, rr = idx & 127, l = idx >> 7;
+    const size_t o = (size_t)l * ld + min(r0 + rr, K - 1);
+    const double vv = b.V[o], ww = b.Wp[o];
+    const bool ok = r0 + rr < K;
+    pr_v[l][rr] = ok ? vv : 0.0;
+    pr_w[l][rr] = ok ? ww : 0.0;
   }
-  for (int idx = tid; idx < 64 * kNB; idx += kTT) {
-    const int cc = idx & 63, l = idx >> 6;
-    const bool ok = (c0 + cc < K) && l < nb;
-    pc_v[l][cc] = ok ? b.V[(size_t)l * ld + c0 + cc] : 0.0;
-    pc_w[l][cc] = ok ? b.Wp[(size_t)l * ld + c0 + cc] : 0.0;
+#pragma unroll
+  for (int k = 0; k < 64 * kNB / kTT; ++k) {
+    const int idx = tid + k * kTT, cc = idx & 63, l = idx >> 6;
+    const size_t o = (size_t)l * ld + min(c0 + cc, K - 1);
+    const double vv = b.V[o], ww = b.Wp[o];
+    const bool ok = c0 + cc < K;
+    pc_v[l][cc] = ok ? vv : 0.0;
+    pc_w[l][cc] = ok ? ww : 0.0;
   }
   __syncthreads();
   const int tr = tid & 31, tc = tid >> 5;     // rows tr + 32 u, columns 4 tc + q
@@ -555,13 +563,19 @@ __global__ __launch_bounds__(kTT) void k_trd_trail(LargeArgs a, int p) {
       for (int q = 0; q < 4; ++q) acc[u][q] += rv * cw[q] + rw * cv[q];
     }
   }
+  double old[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      old[u][q] = W[(size_t)min(c0 + 4 * tc + q, K - 1) * ld + min(r0 + tr + 32 * u, K - 1)];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int r = r0 + tr + 32 * u;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int c = c0 + 4 * tc + q;
-      if (r < K && c < K) W[(size_t)c * ld + r] -= acc[u][q];
+      if (r < K && c < K) W[(size_t)c * ld + r] = old[u][q] - acc[u][q];
     }
   }
 }
