@@ -199,7 +199,8 @@ __global__ __launch_bounds__(256) void k_large_gather(LargeArgs a) {
 //    the symv are unconditional and aligned (double2 over the padded
 //    leading dimension, zero padding rows, v zero outside its support).
 // ---------------------------------------------------------------------------
-constexpr int kSymvCols = 32;   // columns per symv workgroup (4 waves x 8)
+constexpr int kSymvCols = 32;   // columns per symv workgroup (4 waves; 64 measured slower: 218 VGPRs)
+constexpr int kWaveCols = kSymvCols / 4;
 constexpr int kSymvRows = 256;  // rows per symv workgroup (2 steps of 128 per lane pair)
 constexpr int kMaxRB = 1024 / kSymvRows;
 constexpr int kUpdRows = 64;    // rows per update workgroup (4 waves split the panel sums)
@@ -257,7 +258,7 @@ __device__ __forceinline__ int trd_nrb(int j, int ld) { return (ld - trd_r0(j) +
 // the first useful load shows in its duration.  For the same reason both
 // kernels issue all their global loads before the first barrier.
 template <bool ADMM>
-__global__ __launch_bounds__(256) void k_trd_symv(LargeArgs a, int p, int i, int ncy) {
+__global__ __launch_bounds__(256, 4) void k_trd_symv(LargeArgs a, int p, int i, int ncy) {
   __shared__ __align__(16) double vbuf[1024];
   __shared__ double red[256 / 64 + 1];
   __shared__ double part[4];
@@ -274,26 +275,26 @@ __global__ __launch_bounds__(256) void k_trd_symv(LargeArgs a, int p, int i, int
   const double* W = w.W;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const bool lead = blockIdx.y == 0;
-  // (1) this wave's operands: columns cbase + 8 wid + u of
+  // (1) this wave's operands: columns cbase + kWaveCols wid + u of
   //     [A22 | Wp(:, 0:i) | V(:, 0:i)] on rows rbase + [0, kSymvRows); W, V
   //     and Wp live in one workspace, every column addressed by its offset
   //     from W (V = W + 2 ld^2, Wp = V + kNB ld).  They do not depend on v.
   const int rbase = trd_r0(j) + rb * kSymvRows;
-  const int cg = cbase + wid * 8;
-  int coff[8];
+  const int cg = cbase + wid * kWaveCols;
+  int coff[kWaveCols];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
+  for (int u = 0; u < kWaveCols; ++u) {
     const int q = min(cg + u, nall - 1);
     coff[u] = (q < ncol) ? (j + 1 + q) * ld
                          : 2 * ld * ld + ((q < ncol + i) ? (kNB + q - ncol) * ld : (q - ncol - i) * ld);
   }
   constexpr int NK = kSymvRows / 128;
-  double2 av[NK][8];
+  double2 av[NK][kWaveCols];
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     const int rr = min(rbase + 2 * lane + 128 * k, ld - 2);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) av[k][u] = *reinterpret_cast<const double2*>(W + coff[u] + rr);
+    for (int u = 0; u < kWaveCols; ++u) av[k][u] = *reinterpret_cast<const double2*>(W + coff[u] + rr);
   }
   // (2) column j: this workgroup's rows and columns of v, and ||x||^2 for
   //     x = A(j+1:K, j) (left in shares by the update of column j - 1, or
@@ -304,9 +305,9 @@ __global__ __launch_bounds__(256) void k_trd_symv(LargeArgs a, int p, int i, int
   double xrow[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) xrow[q] = W[(size_t)j * ld + min(rbase + tid + 256 * q, K - 1)];
-  double xcol[8];
+  double xcol[kWaveCols];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) xcol[u] = W[(size_t)j * ld + min(j + 1 + cg + u, K - 1)];
+  for (int u = 0; u < kWaveCols; ++u) xcol[u] = W[(size_t)j * ld + min(j + 1 + cg + u, K - 1)];
   double ss = 0.0;
   if (i == 0) {
     for (int r = j + 2 + tid; r < K; r += 256) {
@@ -351,9 +352,9 @@ __global__ __launch_bounds__(256) void k_trd_symv(LargeArgs a, int p, int i, int
   double yv = 0.0;
   if (cg < nall) {
     // (4) y = A22 v and the panel dots on this block of rows
-    double acc[8];
+    double acc[kWaveCols];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+    for (int u = 0; u < kWaveCols; ++u) acc[u] = 0.0;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       const int r = rbase + 2 * lane + 128 * k;
@@ -361,10 +362,10 @@ __global__ __launch_bounds__(256) void k_trd_symv(LargeArgs a, int p, int i, int
       const double2 vv = *reinterpret_cast<const double2*>(vbuf + rr);
       const double m = (r < ld) ? 1.0 : 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += m * (av[k][u].x * vv.x + av[k][u].y * vv.y);
+      for (int u = 0; u < kWaveCols; ++u) acc[u] += m * (av[k][u].x * vv.x + av[k][u].y * vv.y);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < kWaveCols; ++u) {
       const double sum = wave_sum(acc[u]);
       const int q = cg + u;
       if (q < ncol) yv += sum * vof(j + 1 + q, xcol[u]);
