@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "ADMM iters/s + time-to-1e-4 residual; batched & grad vs plain; % HBM/FP64 roofline"
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 PEAK_HBM_GBS = 8000.0
+JACOBI_MAX = 64              # cliques up to this order: Jacobi in LDS; larger: the tridiagonal path
 
 
 def trd_tail_start(K, tail=136, nb=32):
@@ -51,8 +52,8 @@ def phase_work(inst_sizes, prob_dims):
     symv and one update launch per column step of the panels (all large
     cliques in lockstep, each until its last <= 136 columns), one trailing
     update per panel of 32 and one LDS tail launch."""
-    large = sorted((k for k in inst_sizes if k > 96), reverse=True)
-    small = [k for k in inst_sizes if k <= 96]
+    large = sorted((k for k in inst_sizes if k > JACOBI_MAX), reverse=True)
+    small = [k for k in inst_sizes if k <= JACOBI_MAX]
     nE, ns, m, p = prob_dims
     out = {}
     if large:

@@ -104,7 +104,7 @@ typedef struct {
   int32_t check_every; /* cdcs_solve reads the status words back every this many iterations */
   int32_t timing;      /* 1 = time each kernel phase with HIP events (cdcs_get_phase_times) */
   int32_t use_graph;   /* 1 = replay the iteration from a captured HIP graph */
-  int32_t eig_fp32;    /* 1 = eigen-decompose cliques of up to 96 vertices in FP32 (Jacobi in
+  int32_t eig_fp32;    /* 1 = eigen-decompose cliques of up to 64 vertices in FP32 (Jacobi in
                           FP32; gather, Y and the update of s, z, v stay FP64); larger cliques
                           always FP64.  The iterates then differ from the FP64 method by ~1e-7
                           relative per conic step. */
@@ -122,7 +122,7 @@ typedef struct {
                           A^T over y and of H^T over v of the previous iterate
                           inside the existing kernels, and 4 vectors (3 nE,
                           1 m) of device memory; otherwise CDCS_E_ARG. */
-  int32_t eig_warm;    /* 1 = start the Jacobi eigen-decomposition of every clique of up to 96
+  int32_t eig_warm;    /* 1 = start the Jacobi eigen-decomposition of every clique of up to 64
                           vertices from its eigenvectors of the previous iteration (Y is
                           rotated to V^T Y V, nearly diagonal once the iterates settle, and
                           the sweeps continue from there); the projection is the same up to

@@ -257,11 +257,11 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
   { PhaseTimer t(h, PH_SCALAR1); launch_scalar1(d, st); }
   { PhaseTimer t(h, PH_UPDATE_E); launch_update_e(d, st); }
   { PhaseTimer t(h, PH_UPDATE_R); launch_update_r(d, st); }
-  const int kmaxs[4] = {16, 32, 64, kJacobiMax};
+  const int kmaxs[4] = {16, 32, 64, 96};   // bucket orders (the last is empty while kJacobiMax = 64)
   int nsmall = 0;
   for (int bk = 0; bk < 4; ++bk) nsmall += h->ntasks[bk] ? 1 : 0;
   const bool fork = h->ntasks[4] && nsmall;
-  if (fork || (nsmall > 1 && !h->ntasks[4])) HIPCHK(hipEventRecord(h->ev_fork, st));
+  if (fork || (nsmall > 1 && !(h->ntasks[4] && h->kmax_large > 136))) HIPCHK(hipEventRecord(h->ev_fork, st));
   hipStream_t lst = st;
   if (fork) {
     lst = h->aux;
@@ -276,11 +276,13 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
                              h->set.timing ? &hook : nullptr);
     }
   }
-  // Jacobi buckets: without large cliques the first non-empty one on
-  // `stream` and the others each on a stream of its own; beside the large
-  // cliques' chain of short launches they stay in sequence on `stream`,
-  // leaving compute units free for that chain (the critical path)
-  const int nside = h->ntasks[4] ? 0 : nsmall - 1;
+  // Jacobi buckets: the first non-empty one on `stream` and the others each
+  // on a stream of its own; beside a large clique's chain of per-column
+  // launches (cliques above the 136 columns the LDS tail holds) they stay in
+  // sequence on `stream`, leaving compute units free for that chain (the
+  // critical path)
+  const bool chain = h->ntasks[4] && h->kmax_large > 136;
+  const int nside = chain ? 0 : nsmall - 1;
   int side = 0;
   for (int bk = 0; bk < 4; ++bk)
     if (h->ntasks[bk]) {
@@ -319,7 +321,7 @@ constexpr int kTuneReps = 3;
 
 int autotune(cdcs_handle* h) {
   hipStream_t st = h->stream;
-  const int kmaxs[4] = {16, 32, 64, kJacobiMax};
+  const int kmaxs[4] = {16, 32, 64, 96};   // bucket orders (the last is empty while kJacobiMax = 64)
   for (int bk = 0; bk < 4; ++bk) {
     const auto& all = h->bucket_sizes[bk];
     if (all.empty()) continue;
@@ -1383,7 +1385,7 @@ int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32
 
 int cdcs_get_tuning(const cdcs_handle* h, int32_t* out, int32_t cap) {
   if (!h || !out || cap < 16) return set_error(CDCS_E_ARG, "cdcs_get_tuning: need a handle and 16 outputs");
-  const int kmaxs[4] = {16, 32, 64, kJacobiMax};
+  const int kmaxs[4] = {16, 32, 64, 96};   // bucket orders (the last is empty while kJacobiMax = 64)
   for (int b = 0; b < 4; ++b) {
     out[4 * b + 0] = kmaxs[b];
     out[4 * b + 1] = jacobi_threads(kmaxs[b], h->jvar[b]);
@@ -1473,7 +1475,7 @@ int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets
       return rc;
     }
   }
-  const int kmaxs[4] = {16, 32, 64, kJacobiMax};
+  const int kmaxs[4] = {16, 32, 64, 96};   // bucket orders (the last is empty while kJacobiMax = 64)
   for (int b = 0; b < 4; ++b)
     launch_psd_project((int32_t*)dsz, (int64_t*)doff, (int32_t*)dtask[b], (int32_t)bk[b].size(), kmaxs[b], in, out,
                        st);

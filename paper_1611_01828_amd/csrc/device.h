@@ -15,7 +15,7 @@ namespace cdcs {
 constexpr int kThreads = 256;        // block size of the streaming kernels
 constexpr int kEntChunk = 1024;      // entries per entry block
 constexpr int kRowChunk = 64;        // constraint rows per row block (4 waves)
-constexpr int kJacobiMax = 96;       // largest clique handled by the LDS Jacobi kernel
+constexpr int kJacobiMax = 64;       // largest clique handled by the LDS Jacobi kernel (larger: tridiagonal path)
 
 // per-instance scalar slots (double sc[B * kNsc])
 enum Sc {

@@ -1,5 +1,6 @@
 // Conic step (eq. Step2, PSD part) fused with the dual update (eq. Step3)
-// for cliques of up to 96 vertices: one workgroup per clique, the block held
+// for the cliques routed to it (up to kJacobiMax = 64 vertices; the shapes
+// of a 96-vertex bucket are kept): one workgroup per clique, the block held
 // in LDS and diagonalised by cyclic two-sided Jacobi (Jacobi 1846; the
 // symmetric 2x2 Schur rotation and round-robin parallel ordering of Golub &
 // Van Loan, Matrix Computations, Sections 8.5.2-8.5.5).

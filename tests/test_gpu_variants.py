@@ -1,7 +1,7 @@
 """The FP32-eigensolve variant and the Jacobi tile autotuner (through the C-ABI).
 
 FP32 variant (settings eig_fp32 = 1): the Jacobi eigen-decompositions of
-cliques up to 96 vertices run in FP32, everything else in FP64.  Bars, against
+cliques up to 64 vertices run in FP32, everything else in FP64.  Bars, against
 the FP64 oracle on the same seeded inputs:
   * iterates k = 1..50 within 1e-4 relative (FP32 rounding, ~1e-7 per conic
     step, accumulates at most linearly in a nonexpansive iteration), and not
@@ -61,7 +61,7 @@ def test_fp32_eig_iterates_config0(lib):
 
 
 def test_fp32_eig_iterates_uneven_cliques(lib):
-    """Cliques of every Jacobi bucket (4..96 vertices)."""
+    """Cliques of every Jacobi bucket (4..64 vertices) beside tridiagonal-path ones (65..96)."""
     _log("FP32 eig: iterates config2 (cliques 4..96)")
     w, _ = _worst_iterate_error(lib, configs.config2(), 20, eig_fp32=1)
     _log(f"  worst rel {w:.2e}")

@@ -69,7 +69,7 @@ def test_warm_iterates_small_odd_sizes(lib):
 
 
 def test_warm_iterates_config2(lib):
-    """Cliques of every Jacobi bucket (4..96 vertices)."""
+    """Cliques of every Jacobi bucket (4..64 vertices) beside tridiagonal-path ones (65..96)."""
     _log("warm iterates config2")
     w = _iterate_parity(lib, configs.config2(), 20)
     _log(f"  worst rel {w:.2e}")
