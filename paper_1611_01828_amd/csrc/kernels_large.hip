@@ -1148,6 +1148,31 @@ __device__ __forceinline__ double bt_v(const double* W, int ld, int K, int j0, i
 
 __device__ __forceinline__ double* bt_tbuf(const Ws& w) { return w.S; }   // 32 x 32 per panel
 
+// Stage rows [row0, row0 + kBtCR) of the panel's 32 reflectors into Vc.
+// Every load is unconditional, from a clamped address inside the task's W
+// (column j0 + min(a, nbp - 1) <= K - 3, row <= K - 1), and the empty asm
+// statements take each loaded value as an operand, so the compiler cannot
+// move a load under its lane condition: the thread's loads are in flight
+// together instead of one round trip each.  The value is selected after.
+__device__ __forceinline__ void bt_stage(double (*Vc)[33], const double* W, int ld, int K, int j0, int nbp,
+                                         int row0, int tid) {
+  constexpr int NQ = kBtCR * 32 / 1024;
+  double x[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int idx = tid + 1024 * q, as = idx / kBtCR, rl = idx - as * kBtCR;
+    x[q] = W[(size_t)(j0 + min(as, nbp - 1)) * ld + min(row0 + rl, K - 1)];
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) asm volatile("" : "+v"(x[q]));
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int idx = tid + 1024 * q, as = idx / kBtCR, rl = idx - as * kBtCR, row = row0 + rl;
+    const bool zero = as >= nbp || row >= K || row <= j0 + as;
+    Vc[rl][as] = zero ? 0.0 : ((row == j0 + as + 1) ? 1.0 : x[q]);
+  }
+}
+
 template <bool ADMM>
 __global__ __launch_bounds__(1024) void k_bt_tfactor(LargeArgs a) {
   __shared__ double Vc[32][33];
@@ -1219,11 +1244,7 @@ __global__ __launch_bounds__(1024) void k_bt_apply(LargeArgs a) {
     // pass 1: S = V_p^T Z
     double sp = 0.0;
     for (int row0 = j0 + 1; row0 < K; row0 += kBtCR) {
-#pragma unroll
-      for (int q = 0; q < kBtCR * 32 / 1024; ++q) {
-        const int idx = tid + 1024 * q, as = idx / kBtCR, rl = idx - as * kBtCR;
-        Vc[rl][as] = bt_v(w.W, ld, K, j0, nbp, as, row0 + rl);
-      }
+      bt_stage(Vc, w.W, ld, K, j0, nbp, row0, tid);
       __syncthreads();
       const int nr = min(kBtCR, K - row0);
       for (int rr = h1; rr < nr; rr += 4) sp += Vc[rr][a1] * Zs[cl1][row0 + rr];
@@ -1241,11 +1262,7 @@ __global__ __launch_bounds__(1024) void k_bt_apply(LargeArgs a) {
     __syncthreads();
     // pass 2: Z -= V_p S
     for (int row0 = j0 + 1; row0 < K; row0 += kBtCR) {
-#pragma unroll
-      for (int q = 0; q < kBtCR * 32 / 1024; ++q) {
-        const int idx = tid + 1024 * q, as = idx / kBtCR, rl = idx - as * kBtCR;
-        Vc[rl][as] = bt_v(w.W, ld, K, j0, nbp, as, row0 + rl);
-      }
+      bt_stage(Vc, w.W, ld, K, j0, nbp, row0, tid);
       __syncthreads();
 #pragma unroll
       for (int hh = 0; hh < kBtCR / 128; ++hh) {
