@@ -603,9 +603,23 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
   double* W = w.W;
   const int tid = threadIdx.x;
   const int r = tid % kTailR, h = tid / kTailR;   // h == kTailG: idle
-  for (int idx = tid; idx < n * n; idx += kTailT) {
-    const int c = idx / n, rr = idx - c * n;
-    A[c * n + rr] = W[(size_t)(j0 + c) * ld + j0 + rr];
+  {
+    // all of the thread's loads in flight together, from clamped in-range
+    // addresses (entry min(idx, n^2 - 1) of the n x n block)
+    constexpr int NL = (kTail * kTail + kTailT - 1) / kTailT;
+    double x[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int idx = min(tid + kTailT * q, n * n - 1), c = idx / n, rr = idx - c * n;
+      x[q] = W[(size_t)(j0 + c) * ld + j0 + rr];
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) asm volatile("" : "+v"(x[q]));
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int idx = tid + kTailT * q;
+      if (idx < n * n) A[idx] = x[q];
+    }
   }
   __syncthreads();
   const int lane = tid & 63;
@@ -1308,19 +1322,29 @@ __global__ __launch_bounds__(256) void k_large_recon(LargeArgs a) {
   const int tid = threadIdx.x;
   const int ty = tid / 8, tx = tid % 8;          // 32 rows x (8 threads x 4 columns)
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  constexpr int NI = kTile * kTile / 256;
+  static_assert(NI * 256 == kTile * kTile, "recon staging");
   for (int l0 = 0; l0 < r; l0 += kTile) {
-    for (int idx = tid; idx < kTile * kTile; idx += 256) {
-      const int ii = idx % kTile, ll = idx / kTile;
-      const int l = l0 + ll;
-      double va = 0.0, vb = 0.0;
-      if (l < r) {
-        const double* zl = w.Z + (size_t)l * K;
-        const double lm = w.lam[l];
-        if (a0 + ii < K) va = zl[a0 + ii] * lm;
-        if (b0 + ii < K) vb = zl[b0 + ii];
-      }
-      Va[ii][ll] = va;
-      Vb[ii][ll] = vb;
+    // every load from a clamped in-range address (column <= r - 1 < K,
+    // row <= K - 1), issued together; the empty asm statements keep the
+    // compiler from moving them under their lane conditions
+    double za[NI], zb[NI], lm[NI];
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      const int idx = tid + 256 * q, ii = idx % kTile, l = min(l0 + idx / kTile, r - 1);
+      const double* zl = w.Z + (size_t)l * K;
+      za[q] = zl[min(a0 + ii, K - 1)];
+      zb[q] = zl[min(b0 + ii, K - 1)];
+      lm[q] = w.lam[l];
+    }
+#pragma unroll
+    for (int q = 0; q < NI; ++q) asm volatile("" : "+v"(za[q]), "+v"(zb[q]), "+v"(lm[q]));
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      const int idx = tid + 256 * q, ii = idx % kTile, ll = idx / kTile;
+      const bool lv = l0 + ll < r;
+      Va[ii][ll] = (lv && a0 + ii < K) ? za[q] * lm[q] : 0.0;
+      Vb[ii][ll] = (lv && b0 + ii < K) ? zb[q] : 0.0;
     }
     __syncthreads();
 #pragma unroll 4
