@@ -261,7 +261,17 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
   int nsmall = 0;
   for (int bk = 0; bk < 4; ++bk) nsmall += h->ntasks[bk] ? 1 : 0;
   const bool fork = h->ntasks[4] && nsmall;
-  if (fork || (nsmall > 1 && !(h->ntasks[4] && h->kmax_large > 136))) HIPCHK(hipEventRecord(h->ev_fork, st));
+  // A large clique's chain of per-column launches (the columns above the 136
+  // the LDS tail holds) is the critical path once it is long: beside it the
+  // Jacobi buckets stay in sequence on `stream`, leaving compute units free
+  // for the chain (random max-cut G(2000, 6000): 544 columns, ~10 ms per
+  // iteration).  A chain of at most kLongChain columns takes about as long
+  // as one Jacobi bucket or less (max-cut on the 40 x 50 periodic grid: 32
+  // columns, ~0.35 ms, beside a 1.6 ms bucket of cliques up to 64), so the
+  // buckets then run side by side.  The same fork and joins serve both.
+  constexpr int32_t kLongChain = 128;
+  const bool chain = h->ntasks[4] && h->kmax_large - 136 > kLongChain;
+  if (fork || (nsmall > 1 && !chain)) HIPCHK(hipEventRecord(h->ev_fork, st));
   hipStream_t lst = st;
   if (fork) {
     lst = h->aux;
@@ -277,11 +287,7 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
     }
   }
   // Jacobi buckets: the first non-empty one on `stream` and the others each
-  // on a stream of its own; beside a large clique's chain of per-column
-  // launches (cliques above the 136 columns the LDS tail holds) they stay in
-  // sequence on `stream`, leaving compute units free for that chain (the
-  // critical path)
-  const bool chain = h->ntasks[4] && h->kmax_large > 136;
+  // on a stream of its own, unless a long per-column chain runs beside them
   const int nside = chain ? 0 : nsmall - 1;
   int side = 0;
   for (int bk = 0; bk < 4; ++bk)

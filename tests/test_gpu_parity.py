@@ -210,6 +210,14 @@ def test_iterates_config1(lib, torch_cuda):
     _log(f"  worst rel {w:.2e}")
 
 
+def test_iterates_grid_companion(lib, torch_cuda):
+    """Max-cut on the periodic 40 x 50 grid: 1487 Jacobi cliques, 11 in the LDS
+    tail, one of 147 vertices through the per-column chain."""
+    _log("iterates grid companion (max-cut 40x50 periodic grid, 1499 cliques)")
+    w = _iterate_parity(lib, configs.grid_maxcut(1), 20)
+    _log(f"  worst rel {w:.2e}")
+
+
 def test_solve_config0_matches_oracle(lib, torch_cuda):
     _log("solve config0")
     inst = configs.config0()
