@@ -136,6 +136,40 @@ def affine_work(insts, dims):
     }
 
 
+def measure_peaks(torch):
+    """Measured ceilings on this GPU: device-to-device copy bandwidth of a
+    1 GiB tensor (HBM-resident) and of a 32 MiB tensor copied repeatedly
+    (resident in the 256 MB last-level cache), read + write bytes over the
+    HIP-event time; and the FP64 rate of an 8192^3 matrix product (the
+    vendor BLAS), the practical FP64 ceiling."""
+    def ev_time(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3 / reps
+    out = {}
+    for label, nbytes, reps in (("copy_hbm_GBs", 1 << 30, 10), ("copy_cache_GBs", 32 << 20, 200)):
+        x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        out[label] = round(2 * nbytes / ev_time(lambda: y.copy_(x), reps) / 1e9, 1)
+        del x, y
+    n = 8192
+    g = torch.Generator(device="cuda").manual_seed(0)
+    a = torch.rand(n, n, dtype=torch.float64, device="cuda", generator=g)
+    b = torch.rand(n, n, dtype=torch.float64, device="cuda", generator=g)
+    c = torch.empty_like(a)
+    out["dgemm_TFLOPs"] = round(2 * n ** 3 / ev_time(lambda: torch.matmul(a, b, out=c), 3) / 1e12, 2)
+    del a, b, c
+    torch.cuda.empty_cache()
+    print(f"[bench] measured peaks: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def timed_solve(cdcs, torch, inst, label, **settings):
     """Wall time of a fresh cdcs_solve (graph replay, status read every 10 iterations)."""
     import threading
@@ -267,6 +301,11 @@ def main():
                 "launches_per_step": phases[dom][1] / ev_steps,
                 "ms_per_step_in_kernel": round(phases[dom][0] / ev_steps, 4)}
 
+    peaks = measure_peaks(torch)
+    if roof is not None:
+        ref = peaks["copy_hbm_GBs"] if roof["unit"] == "GB/s" else peaks["dgemm_TFLOPs"]
+        roof["frac_vs_measured"] = round(roof["achieved"] / ref, 6)
+
     tol = tol_relaxed = None
     if not args.no_solve:
         tol = timed_solve(cdcs, torch, inst, "solve", eig_warm=ew)
@@ -333,6 +372,7 @@ def main():
                    "n": inst.n, "m": inst.m, "cliques": len(sizes), "max_clique": max(sizes),
                    "nE": dims[0], "ns": dims[1], "eps_tol": 1e-4, "eig_warm": ew},
         "roofline": roof,
+        "measured_peaks": peaks,
         "cpu_baseline": cpu,
         "time_to_1e-4": tol,
         "time_to_1e-4_relaxed": tol_relaxed,
@@ -447,13 +487,16 @@ def bench_batch(args, cdcs, configs):
                        "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": nbytes,
                        "avg_launch_ms": round(ms / n, 5),
                        "traffic": measured_traffic(name, "affine_config3_traffic.md", "kernels_iter.hip")})
+    peaks = measure_peaks(torch)
+    for e in affine:
+        e["frac_vs_measured"] = round(e["achieved"] / peaks["copy_hbm_GBs"], 4)
     print(f"[bench] affine-step phases: {affine}", file=sys.stderr, flush=True)
     out = {"metric": "batched instance-iterations/s (256 block-arrow SDPs)", "value": fp64["value"],
            "unit": "instance-iter/s", "plain_value": round(plain, 1),
            "speedup_vs_plain": round(fp64["value"] / plain, 2), "steps": args.steps, "dtype": "f64",
            "fp64": fp64, "fp64_autotuned": tuned, "fp32_eig_autotuned": fp32,
            "fp64_warm_jacobi": warm, "fp32_eig_warm_jacobi": warm32,
-           "roofline_affine": affine,
+           "roofline_affine": affine, "measured_peaks": peaks,
            "phases_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phases.items() if v[1]}}
     print(json.dumps(out))
 
