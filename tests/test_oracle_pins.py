@@ -235,6 +235,26 @@ def test_maxcut_even_cycle_and_complete_graph():
     assert abs(val + n * n) <= 1e-6 * n * n
 
 
+@pytest.mark.parametrize("rows,cols", [(4, 6), (3, 4), (3, 5)])
+def test_maxcut_periodic_grid(rows, cols):
+    """The periodic grid (torus C_rows x C_cols, the generator of the config 1
+    companion at a small size) is vertex-transitive, so its max-cut SDP value
+    is the eigenvalue bound n lambda_max(L) / 4 (Delorme & Poljak 1993), with
+    lambda_max(L) = lambda_max(L(C_rows)) + lambda_max(L(C_cols)) for the
+    Cartesian product and lambda_max(L(C_k)) = 2 - 2 cos(2 pi floor(k/2) / k).
+    min <-L, X> is -4 times that value: -n lambda_max(L).  With both sides
+    even the graph is bipartite and the value is -4 |E|."""
+    inst = configs.grid_maxcut(0, rows=rows, cols=cols)
+    res = hsde.solve(inst, eps_tol=1e-9, max_iter=40000)
+    assert res.status == hsde.SOLVED
+    val = hsde.recover(res)["obj_p"]
+    lam = sum(2 - 2 * math.cos(2 * math.pi * (k // 2) / k) for k in (rows, cols))
+    want = -rows * cols * lam
+    if rows % 2 == 0 and cols % 2 == 0:
+        assert abs(want + 4 * len(inst.meta["edges"])) <= 1e-12
+    assert abs(val - want) <= 1e-6 * abs(want)
+
+
 def test_decomposed_equals_undecomposed():
     inst = configs.small_block_arrow(3, n=12, block=3, arrow=2, m=4)
     whole = configs.SDPInstance(inst.n, inst.m, inst.C, inst.A, inst.b,
