@@ -91,7 +91,7 @@ def phase_work(inst_sizes, prob_dims):
     return out
 
 
-def measured_traffic(kernel, summary="trd_symv_config1_traffic.md", source="kernels_large.hip"):
+def measured_traffic(kernel, summary="trd_symv_maxcut_random_2000_traffic.md", source="kernels_large.hip"):
     """HBM bytes per launch of `kernel` from a committed counter summary
     (profiles/<summary>, one `<!-- traffic: {...} -->` record per kernel), or
     None when it is missing or the kernel's source file changed since."""
@@ -218,7 +218,7 @@ def main():
         args.cpu_iters = 30 if args.workload == "grid" else 3
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(independent instances shard across GPUs without exchange; see DESIGN.md)", file=sys.stderr)
+              f"(independent instances shard across GPUs without exchange)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -234,7 +234,7 @@ def main():
 
     grid = args.workload == "grid"
     t0 = time.perf_counter()
-    inst = configs.grid_maxcut(1) if grid else configs.config1()
+    inst = configs.grid_maxcut(1) if grid else configs.maxcut_random_2000()
     gen_s = time.perf_counter() - t0
     sizes = [len(c) for c in inst.cliques]
     print(f"[bench] workload: {inst.name}, p={len(sizes)}, max clique {max(sizes)}, "
@@ -384,14 +384,14 @@ def main():
 
 
 def bench_batch(args, cdcs, configs):
-    """Config 3: one batched handle for all instances vs one handle per instance;
+    """256 block-arrow SDPs: one batched handle for all instances vs one handle per instance;
     FP64 with the default and the autotuned Jacobi tiles, the FP32-eigensolve
     variant with its errors against FP64, and the warm-started Jacobi (FP64 and
     FP32)."""
     import numpy as np
     import torch
     t0 = time.perf_counter()
-    insts = configs.config3()
+    insts = configs.block_arrow_batch256()
     print(f"[bench] 256 block-arrow instances generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
 
     def run(label, **settings):
@@ -486,7 +486,7 @@ def bench_batch(args, cdcs, configs):
         affine.append({"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                        "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": nbytes,
                        "avg_launch_ms": round(ms / n, 5),
-                       "traffic": measured_traffic(name, "affine_config3_traffic.md", "kernels_iter.hip")})
+                       "traffic": measured_traffic(name, "affine_block_arrow_batch256_traffic.md", "kernels_iter.hip")})
     peaks = measure_peaks(torch)
     for e in affine:
         e["frac_vs_measured"] = round(e["achieved"] / peaks["copy_hbm_GBs"], 4)
@@ -502,10 +502,10 @@ def bench_batch(args, cdcs, configs):
 
 
 def bench_grad(args, cdcs, configs):
-    """Config 4: forward (solve) + backward (implicit adjoint) vs forward only."""
+    """64 block-arrow SDPs: forward (solve) + backward (implicit adjoint) vs forward only."""
     import numpy as np
     import torch
-    insts = configs.config4()
+    insts = configs.block_arrow_grad64()
     W = np.concatenate([i.meta["W"][2] for i in insts])
     # W is drawn on the lower pattern entries; map to svec over each instance's E'
     s = cdcs.Solver(insts, check_every=10)

@@ -42,7 +42,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
         print("[profile_run] 3 copies of 64 MiB done", flush=True)
-    inst = {"maxcut": configs.config1, "batch": configs.config3, "uneven": configs.config2}[args.workload]()
+    inst = {"maxcut": configs.maxcut_random_2000, "batch": configs.block_arrow_batch256, "uneven": configs.uneven_cliques_5000}[args.workload]()
     s = cdcs.Solver(inst)
     s.iterate(args.iters)
     torch.cuda.synchronize()

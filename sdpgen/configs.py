@@ -17,7 +17,8 @@ Entries are matrix values, not scaled; off-diagonal (i, j) stands for both
 X_ij and X_ji.  This module draws random numbers and builds patterns; it
 holds none of the solver's arithmetic.
 
-Seeds: numpy default_rng(SeedSequence([161101828, config, instance])).
+Seeds: numpy default_rng(SeedSequence([161101828, stream, instance])), one
+stream number per workload generator.
 """
 from __future__ import annotations
 
@@ -44,8 +45,8 @@ class SDPInstance:
     meta: dict = field(default_factory=dict)
 
 
-def rng_for(config: int, instance: int = 0) -> np.random.Generator:
-    return np.random.default_rng(np.random.SeedSequence([SEED_ROOT, config, instance]))
+def rng_for(stream: int, instance: int = 0) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([SEED_ROOT, stream, instance]))
 
 
 # ----------------------------------------------------------------------------
@@ -152,10 +153,10 @@ def block_arrow_cliques(n, block, arrow):
     return cl, parent
 
 
-def block_arrow_instance(config, instance, n, block, arrow, m, density=0.3, per_row=None):
+def block_arrow_instance(stream, instance, n, block, arrow, m, density=0.3, per_row=None):
     """Block-arrow SDP; each A_i has `per_row` N(0,1) entries (default: a
     fraction `density` of the pattern), made strictly feasible."""
-    rng = rng_for(config, instance)
+    rng = rng_for(stream, instance)
     cliques, parent = block_arrow_cliques(n, block, arrow)
     er, ec = pattern_entries(cliques)
     if per_row is None:
@@ -171,14 +172,14 @@ def block_arrow_instance(config, instance, n, block, arrow, m, density=0.3, per_
 # the five workloads
 # ----------------------------------------------------------------------------
 
-def config0():
+def block_arrow_n50():
     """Plain block-arrow SDP: n=50, 5 blocks of 9 + arrow 5, cliques of 14, m=20."""
     return block_arrow_instance(0, 0, n=50, block=9, arrow=5, m=20)
 
 
-def maxcut_instance(config, instance, n, n_edges):
+def maxcut_instance(stream, instance, n, n_edges):
     """min <-L, X> s.t. X_ii = 1 on a uniform random graph G(n, M)."""
-    rng = rng_for(config, instance)
+    rng = rng_for(stream, instance)
     edges = set()
     while len(edges) < n_edges:
         need = n_edges - len(edges)
@@ -214,13 +215,14 @@ def maxcut_from_edges(n, edges, name="max-cut"):
                        meta=dict(edges=edges, order=order))
 
 
-def config1():
+def maxcut_random_2000():
     """Max-cut relaxation on G(2000, 6000) (average degree 6), min-degree extension."""
     return maxcut_instance(1, 0, n=2000, n_edges=6000)
 
 
-def grid_maxcut(config, rows=40, cols=50):
-    """Companion of config 1: 2-D periodic rows x cols grid."""
+def grid_maxcut(stream, rows=40, cols=50):
+    """Companion of the random max-cut: max-cut relaxation on the 2-D periodic
+    rows x cols grid (torus)."""
     n = rows * cols
     edges = []
     for r in range(rows):
@@ -257,7 +259,7 @@ def clique_tree_growth(rng, n, smin=4, smax=96):
     return cliques, np.asarray(parent, dtype=np.int64)
 
 
-def config2(twin=False):
+def uneven_cliques_5000(twin=False):
     """Uneven cliques (4..96) on n=5000, m=2000 sparse constraints (8 entries
     each); the infeasible twin appends <A_1,X> = 1 and <A_1,X> = -1."""
     rng = rng_for(2, 0)
@@ -279,7 +281,7 @@ def config2(twin=False):
     return SDPInstance(n, m, C, A, b, cliques, parent, name=name, meta=meta)
 
 
-def config3(count=256):
+def block_arrow_batch256(count=256):
     """256 block-arrow SDPs: n~U{50..400}, block~U{4..32}, arrow~U{2..8}, m=n//2."""
     out = []
     for i in range(count):
@@ -291,7 +293,7 @@ def config3(count=256):
     return out
 
 
-def config4(count=64):
+def block_arrow_grad64(count=64):
     """64 block-arrow SDPs with n=200, block 16, arrow 4, m=100 (+ loss weights W)."""
     out = []
     for i in range(count):

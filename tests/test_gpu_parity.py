@@ -137,15 +137,15 @@ def _iterate_parity(lib, inst, iters, tol=1e-10, graph=False):
     return worst
 
 
-def test_iterates_config0(lib, torch_cuda):
-    _log("iterates config0")
-    w = _iterate_parity(lib, configs.config0(), 50)
+def test_iterates_block_arrow_n50(lib, torch_cuda):
+    _log("iterates block_arrow_n50")
+    w = _iterate_parity(lib, configs.block_arrow_n50(), 50)
     _log(f"  worst rel {w:.2e}")
 
 
-def test_iterates_config0_graph_replay(lib, torch_cuda):
-    _log("iterates config0 (graph replay)")
-    _iterate_parity(lib, configs.config0(), 20, graph=True)
+def test_iterates_block_arrow_n50_graph_replay(lib, torch_cuda):
+    _log("iterates block_arrow_n50 (graph replay)")
+    _iterate_parity(lib, configs.block_arrow_n50(), 20, graph=True)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
@@ -187,7 +187,7 @@ def test_batch_mixed_dense_orders(lib, torch_cuda):
     """A 20-row and a 600-row dense factor in one batch (the small one then
     runs with the sweep shape of the large one)."""
     _log("batch of dense factors m=20 and m=600")
-    insts = [configs.config0(), configs.small_block_arrow(3, n=100, block=10, arrow=5, m=600, per_row=25)]
+    insts = [configs.block_arrow_n50(), configs.small_block_arrow(3, n=100, block=10, arrow=5, m=600, per_row=25)]
     b = lib.Solver(insts)
     b.iterate(15)
     for i, inst in enumerate(insts):
@@ -198,15 +198,15 @@ def test_batch_mixed_dense_orders(lib, torch_cuda):
         assert _rel(np.concatenate([u2, v2]), np.concatenate([u1, v1])) <= 1e-12
 
 
-def test_iterates_config2(lib, torch_cuda):
-    _log("iterates config2")
-    w = _iterate_parity(lib, configs.config2(), 20)
+def test_iterates_uneven_cliques_5000(lib, torch_cuda):
+    _log("iterates uneven_cliques_5000")
+    w = _iterate_parity(lib, configs.uneven_cliques_5000(), 20)
     _log(f"  worst rel {w:.2e}")
 
 
-def test_iterates_config1(lib, torch_cuda):
-    _log("iterates config1 (max-cut n=2000, cliques up to 673)")
-    w = _iterate_parity(lib, configs.config1(), 4)
+def test_iterates_maxcut_random_2000(lib, torch_cuda):
+    _log("iterates maxcut_random_2000 (max-cut n=2000, cliques up to 673)")
+    w = _iterate_parity(lib, configs.maxcut_random_2000(), 4)
     _log(f"  worst rel {w:.2e}")
 
 
@@ -218,9 +218,9 @@ def test_iterates_grid_companion(lib, torch_cuda):
     _log(f"  worst rel {w:.2e}")
 
 
-def test_solve_config0_matches_oracle(lib, torch_cuda):
-    _log("solve config0")
-    inst = configs.config0()
+def test_solve_block_arrow_n50_matches_oracle(lib, torch_cuda):
+    _log("solve block_arrow_n50")
+    inst = configs.block_arrow_n50()
     ref = hsde.solve(inst)
     s = lib.Solver(inst)
     info = s.solve()[0]
@@ -275,7 +275,7 @@ def test_batch_equals_single(lib, torch_cuda):
 
 def test_state_roundtrip_and_determinism(lib, torch_cuda):
     _log("state roundtrip")
-    inst = configs.config0()
+    inst = configs.block_arrow_n50()
     a = lib.Solver(inst)
     a.iterate(40)
     ua, va = a.get_state()

@@ -54,15 +54,15 @@ def _iterate_parity(lib, inst, iters, alpha, tol=1e-10, graph=False):
 
 
 @pytest.mark.parametrize("alpha", [0.7, 1.6])
-def test_relaxed_iterates_config0(lib, alpha):
-    _log(f"relaxed iterates config0 alpha={alpha}")
-    w = _iterate_parity(lib, configs.config0(), 50, alpha)
+def test_relaxed_iterates_block_arrow_n50(lib, alpha):
+    _log(f"relaxed iterates block_arrow_n50 alpha={alpha}")
+    w = _iterate_parity(lib, configs.block_arrow_n50(), 50, alpha)
     _log(f"  worst rel {w:.2e}")
 
 
 def test_relaxed_iterates_graph_replay(lib):
-    _log("relaxed iterates config0 (graph replay)")
-    _iterate_parity(lib, configs.config0(), 20, 1.6, graph=True)
+    _log("relaxed iterates block_arrow_n50 (graph replay)")
+    _iterate_parity(lib, configs.block_arrow_n50(), 20, 1.6, graph=True)
 
 
 def test_relaxed_iterates_small_odd_sizes(lib):
@@ -83,22 +83,22 @@ def test_relaxed_iterates_large_cliques(lib):
     _log(f"  worst rel {w:.2e}")
 
 
-def test_relaxed_iterates_config2(lib):
-    _log("relaxed iterates config2")
-    w = _iterate_parity(lib, configs.config2(), 15, 1.6)
+def test_relaxed_iterates_uneven_cliques_5000(lib):
+    _log("relaxed iterates uneven_cliques_5000")
+    w = _iterate_parity(lib, configs.uneven_cliques_5000(), 15, 1.6)
     _log(f"  worst rel {w:.2e}")
 
 
-def test_relaxed_iterates_config1(lib):
-    _log("relaxed iterates config1 (max-cut n=2000, cliques up to 673)")
-    w = _iterate_parity(lib, configs.config1(), 3, 1.8)
+def test_relaxed_iterates_maxcut_random_2000(lib):
+    _log("relaxed iterates maxcut_random_2000 (max-cut n=2000, cliques up to 673)")
+    w = _iterate_parity(lib, configs.maxcut_random_2000(), 3, 1.8)
     _log(f"  worst rel {w:.2e}")
 
 
 @pytest.mark.parametrize("alpha", [1.5, 1.8])
-def test_relaxed_solve_config0(lib, alpha):
-    _log(f"relaxed solve config0 alpha={alpha}")
-    inst = configs.config0()
+def test_relaxed_solve_block_arrow_n50(lib, alpha):
+    _log(f"relaxed solve block_arrow_n50 alpha={alpha}")
+    inst = configs.block_arrow_n50()
     ref = hsde.solve(inst, alpha=alpha)
     s = lib.Solver(inst, alpha=alpha)
     info = s.solve()[0]
@@ -144,7 +144,7 @@ def test_relaxed_batch_equals_single(lib):
 
 def test_relaxed_resume_is_bitwise(lib):
     _log("relaxed state roundtrip")
-    inst = configs.config0()
+    inst = configs.block_arrow_n50()
     a = lib.Solver(inst, alpha=1.6)
     a.iterate(40)
     ua, va = a.get_state()
@@ -161,7 +161,7 @@ def test_relaxed_resume_is_bitwise(lib):
 
 def test_alpha_one_is_the_unrelaxed_path(lib):
     """alpha = 1 takes the paper's form bit for bit."""
-    inst = configs.config0()
+    inst = configs.block_arrow_n50()
     a = lib.Solver(inst)
     a.iterate(25)
     b = lib.Solver(inst, alpha=1.0)
@@ -176,4 +176,4 @@ def test_alpha_one_is_the_unrelaxed_path(lib):
 def test_alpha_out_of_range_is_rejected(lib):
     for bad in (0.0, 2.0, -1.0, float("nan")):
         with pytest.raises(lib.CDCSError):
-            lib.Solver(configs.config0(), alpha=bad)
+            lib.Solver(configs.block_arrow_n50(), alpha=bad)

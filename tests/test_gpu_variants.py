@@ -53,24 +53,24 @@ def _worst_iterate_error(lib, inst, iters, **settings):
     return worst, tuning
 
 
-def test_fp32_eig_iterates_config0(lib):
-    _log("FP32 eig: iterates config0")
-    w, _ = _worst_iterate_error(lib, configs.config0(), 50, eig_fp32=1)
+def test_fp32_eig_iterates_block_arrow_n50(lib):
+    _log("FP32 eig: iterates block_arrow_n50")
+    w, _ = _worst_iterate_error(lib, configs.block_arrow_n50(), 50, eig_fp32=1)
     _log(f"  worst rel {w:.2e}")
     assert 1e-12 < w <= 1e-4
 
 
 def test_fp32_eig_iterates_uneven_cliques(lib):
     """Cliques of every Jacobi bucket (4..64 vertices) beside tridiagonal-path ones (65..96)."""
-    _log("FP32 eig: iterates config2 (cliques 4..96)")
-    w, _ = _worst_iterate_error(lib, configs.config2(), 20, eig_fp32=1)
+    _log("FP32 eig: iterates uneven_cliques_5000 (cliques 4..96)")
+    w, _ = _worst_iterate_error(lib, configs.uneven_cliques_5000(), 20, eig_fp32=1)
     _log(f"  worst rel {w:.2e}")
     assert 1e-12 < w <= 1e-4
 
 
-def test_fp32_eig_solve_config0(lib):
-    _log("FP32 eig: solve config0")
-    inst = configs.config0()
+def test_fp32_eig_solve_block_arrow_n50(lib):
+    _log("FP32 eig: solve block_arrow_n50")
+    inst = configs.block_arrow_n50()
     ref = hsde.solve(inst)
     obj = hsde.recover(ref)["obj_p"]
     s = lib.Solver(inst, eig_fp32=1)
@@ -83,8 +83,8 @@ def test_fp32_eig_solve_config0(lib):
 
 
 def test_autotuned_iterates_match_oracle(lib):
-    _log("autotune: iterates config2")
-    w, tuning = _worst_iterate_error(lib, configs.config2(), 20, autotune=1)
+    _log("autotune: iterates uneven_cliques_5000")
+    w, tuning = _worst_iterate_error(lib, configs.uneven_cliques_5000(), 20, autotune=1)
     _log(f"  worst rel {w:.2e}; tuning {tuning}")
     assert w <= 1e-10
     allowed = {16: (64, 128), 32: (64, 128), 64: (128, 256), 96: (256, 512)}
@@ -95,27 +95,27 @@ def test_autotuned_iterates_match_oracle(lib):
 
 def test_alternative_tile_shapes_match_oracle(lib):
     """autotune = 2 runs the other candidate shape of every bucket."""
-    _log("alternative tile shapes: iterates config2")
-    w, tuning = _worst_iterate_error(lib, configs.config2(), 20, autotune=2)
+    _log("alternative tile shapes: iterates uneven_cliques_5000")
+    w, tuning = _worst_iterate_error(lib, configs.uneven_cliques_5000(), 20, autotune=2)
     _log(f"  worst rel {w:.2e}; tuning {tuning}")
     assert w <= 1e-10
     assert [b["threads"] for b in tuning] == [128, 64, 128, 256]
-    w, _ = _worst_iterate_error(lib, configs.config2(), 20, autotune=2, eig_fp32=1)
+    w, _ = _worst_iterate_error(lib, configs.uneven_cliques_5000(), 20, autotune=2, eig_fp32=1)
     _log(f"  FP32, alternative shapes: worst rel {w:.2e}")
     assert 1e-12 < w <= 1e-4
 
 
 def test_autotune_off_reports_defaults(lib):
-    s = lib.Solver(configs.config0())
+    s = lib.Solver(configs.block_arrow_n50())
     t = s.tuning()
     s.close()
     assert [b["threads"] for b in t] == [64, 128, 256, 512]
     assert not any(b["tuned"] for b in t)
-    assert sum(b["cliques"] for b in t) == len(configs.config0().cliques)
+    assert sum(b["cliques"] for b in t) == len(configs.block_arrow_n50().cliques)
 
 
 def test_settings_reject_bad_variant_flags(lib):
     with pytest.raises(lib.CDCSError):
-        lib.Solver(configs.config0(), eig_fp32=2)
+        lib.Solver(configs.block_arrow_n50(), eig_fp32=2)
     with pytest.raises(lib.CDCSError):
-        lib.Solver(configs.config0(), autotune=3)
+        lib.Solver(configs.block_arrow_n50(), autotune=3)

@@ -51,15 +51,15 @@ def _iterate_parity(lib, inst, iters, tol=1e-10, alpha=1.0, **settings):
     return worst
 
 
-def test_warm_iterates_config0(lib):
-    _log("warm iterates config0 (70, across the cold restart)")
-    w = _iterate_parity(lib, configs.config0(), 70)
+def test_warm_iterates_block_arrow_n50(lib):
+    _log("warm iterates block_arrow_n50 (70, across the cold restart)")
+    w = _iterate_parity(lib, configs.block_arrow_n50(), 70)
     _log(f"  worst rel {w:.2e}")
 
 
 def test_warm_iterates_graph_replay(lib):
-    _log("warm iterates config0 (graph replay)")
-    _iterate_parity(lib, configs.config0(), 20, use_graph=1)
+    _log("warm iterates block_arrow_n50 (graph replay)")
+    _iterate_parity(lib, configs.block_arrow_n50(), 20, use_graph=1)
 
 
 def test_warm_iterates_small_odd_sizes(lib):
@@ -68,28 +68,28 @@ def test_warm_iterates_small_odd_sizes(lib):
     _log(f"  worst rel {w:.2e}")
 
 
-def test_warm_iterates_config2(lib):
+def test_warm_iterates_uneven_cliques_5000(lib):
     """Cliques of every Jacobi bucket (4..64 vertices) beside tridiagonal-path ones (65..96)."""
-    _log("warm iterates config2")
-    w = _iterate_parity(lib, configs.config2(), 20)
+    _log("warm iterates uneven_cliques_5000")
+    w = _iterate_parity(lib, configs.uneven_cliques_5000(), 20)
     _log(f"  worst rel {w:.2e}")
 
 
 def test_warm_iterates_relaxed(lib):
-    _log("warm + relaxed iterates config0")
-    w = _iterate_parity(lib, configs.config0(), 40, alpha=1.6)
+    _log("warm + relaxed iterates block_arrow_n50")
+    w = _iterate_parity(lib, configs.block_arrow_n50(), 40, alpha=1.6)
     _log(f"  worst rel {w:.2e}")
 
 
 def test_warm_fp32_iterates(lib):
-    _log("warm FP32 iterates config0")
-    w = _iterate_parity(lib, configs.config0(), 50, tol=1e-4, eig_fp32=1)
+    _log("warm FP32 iterates block_arrow_n50")
+    w = _iterate_parity(lib, configs.block_arrow_n50(), 50, tol=1e-4, eig_fp32=1)
     _log(f"  worst rel {w:.2e}")
     assert w > 1e-12
 
 
 def test_warm_differs_from_cold_only_in_rounding(lib):
-    inst = configs.config2()
+    inst = configs.uneven_cliques_5000()
     a = lib.Solver(inst)
     a.iterate(10)
     b = lib.Solver(inst, eig_warm=1)
@@ -104,9 +104,9 @@ def test_warm_differs_from_cold_only_in_rounding(lib):
     b.close()
 
 
-def test_warm_solve_config0(lib):
-    _log("warm solve config0")
-    inst = configs.config0()
+def test_warm_solve_block_arrow_n50(lib):
+    _log("warm solve block_arrow_n50")
+    inst = configs.block_arrow_n50()
     ref = hsde.solve(inst)
     s = lib.Solver(inst, eig_warm=1)
     info = s.solve()[0]
@@ -134,7 +134,7 @@ def test_warm_batch_equals_single(lib):
 
 def test_warm_resume_matches_to_rounding(lib):
     """set_state forces a cold start: the resumed run matches to rounding."""
-    inst = configs.config0()
+    inst = configs.block_arrow_n50()
     a = lib.Solver(inst, eig_warm=1)
     a.iterate(40)
     ua, va = a.get_state()
@@ -151,4 +151,4 @@ def test_warm_resume_matches_to_rounding(lib):
 
 def test_eig_warm_flag_validated(lib):
     with pytest.raises(lib.CDCSError):
-        lib.Solver(configs.config0(), eig_warm=2)
+        lib.Solver(configs.block_arrow_n50(), eig_warm=2)

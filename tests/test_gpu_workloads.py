@@ -44,7 +44,7 @@ def lib():
 
 @pytest.fixture(scope="module")
 def batch_insts():
-    return configs.config3()
+    return configs.block_arrow_batch256()
 
 
 def _rel(a, b):
@@ -96,7 +96,7 @@ def test_batch_smallest_instances_solve_like_the_oracle(lib, batch_insts):
 
 
 def test_uneven_twin_is_primal_infeasible(lib):
-    inst = configs.config2(twin=True)
+    inst = configs.uneven_cliques_5000(twin=True)
     s = lib.Solver(inst, max_iter=20000, check_every=10)
     info = s.solve()[0]
     _log(f"twin: status {info['status']} after {info['iter']} iterations")

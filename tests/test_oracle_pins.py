@@ -74,9 +74,9 @@ def test_projection_moreau(K):
 # step 1 against its plain definition; cached quantities
 # ----------------------------------------------------------------------------
 
-@pytest.mark.parametrize("which", ["tiny", "config0"])
+@pytest.mark.parametrize("which", ["tiny", "block_arrow_n50"])
 def test_step1_matches_dense_lu(which):
-    inst = configs.small_block_arrow(1) if which == "tiny" else configs.config0()
+    inst = configs.small_block_arrow(1) if which == "tiny" else configs.block_arrow_n50()
     prob = hsde.build_problem(inst)
     cache = hsde.AffineCache(prob)
     IQ, off = literal.dense_affine_matrix_svec(prob)
@@ -108,7 +108,7 @@ def test_step1_matches_dense_lu(which):
 
 
 def test_Q_is_skew_and_cache_invariants():
-    prob = hsde.build_problem(configs.config0())
+    prob = hsde.build_problem(configs.block_arrow_n50())
     IQ, off = literal.dense_affine_matrix_svec(prob)
     Q = IQ - np.eye(off[-1])
     assert np.abs(Q + Q.T).max() == 0.0
@@ -167,7 +167,7 @@ def test_residuals_against_literal_formulas():
 # ----------------------------------------------------------------------------
 
 def test_iterate_invariants():
-    prob = hsde.build_problem(configs.config0())
+    prob = hsde.build_problem(configs.block_arrow_n50())
     res = hsde.solve(prob, max_iter=60, record=60, stop=False)
     sizes = hsde.clique_sizes(prob)
     for u, vt in res.history:
@@ -237,8 +237,8 @@ def test_maxcut_even_cycle_and_complete_graph():
 
 @pytest.mark.parametrize("rows,cols", [(4, 6), (3, 4), (3, 5)])
 def test_maxcut_periodic_grid(rows, cols):
-    """The periodic grid (torus C_rows x C_cols, the generator of the config 1
-    companion at a small size) is vertex-transitive, so its max-cut SDP value
+    """The periodic grid (torus C_rows x C_cols, the generator of the random
+    max-cut's grid companion at a small size) is vertex-transitive, so its max-cut SDP value
     is the eigenvalue bound n lambda_max(L) / 4 (Delorme & Poljak 1993), with
     lambda_max(L) = lambda_max(L(C_rows)) + lambda_max(L(C_cols)) for the
     Cartesian product and lambda_max(L(C_k)) = 2 - 2 cos(2 pi floor(k/2) / k).
@@ -267,7 +267,7 @@ def test_decomposed_equals_undecomposed():
 
 
 def test_grone_and_agler_at_solution():
-    inst = configs.config0()
+    inst = configs.block_arrow_n50()
     res = hsde.solve(inst, eps_tol=1e-8, max_iter=40000)
     assert res.status == hsde.SOLVED
     prob = res.prob

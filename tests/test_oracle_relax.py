@@ -56,9 +56,9 @@ def _averaged_map_error(prob, iterate, alpha):
 
 
 @pytest.mark.parametrize("alpha", [0.5, 1.5, 1.8])
-@pytest.mark.parametrize("which", ["config0", "odd"])
+@pytest.mark.parametrize("which", ["block_arrow_n50", "odd"])
 def test_relaxed_step_is_averaged_dr_map(alpha, which):
-    inst = configs.config0() if which == "config0" else configs.small_block_arrow(5, n=23, block=4, arrow=3, m=6)
+    inst = configs.block_arrow_n50() if which == "block_arrow_n50" else configs.small_block_arrow(5, n=23, block=4, arrow=3, m=6)
     prob = hsde.build_problem(inst)
     err_t, err_u, zero_parts = _averaged_map_error(prob, hsde.iterate, alpha)
     assert err_t <= 1e-12
@@ -109,9 +109,9 @@ def test_relaxed_certificates():
     assert np.linalg.eigvalsh(hsde.svec_to_dense(prob, rec["x_cert"])).min() >= -1e-3
 
 
-def test_relaxation_keeps_the_solution_of_config0():
+def test_relaxation_keeps_the_solution_of_block_arrow_n50():
     """Same fixed point: the relaxed and unrelaxed solves agree to the tolerance."""
-    inst = configs.config0()
+    inst = configs.block_arrow_n50()
     r1 = hsde.solve(inst, eps_tol=1e-8, max_iter=20000)
     r2 = hsde.solve(inst, eps_tol=1e-8, max_iter=20000, alpha=1.6)
     assert r1.status == r2.status == hsde.SOLVED
@@ -140,6 +140,6 @@ def _planted(kind):
 
 @pytest.mark.parametrize("kind", ["average_with_v", "unrelaxed_step3"])
 def test_planted_relaxation_errors_are_caught(kind):
-    prob = hsde.build_problem(configs.config0())
+    prob = hsde.build_problem(configs.block_arrow_n50())
     err_t, err_u, zero_parts = _averaged_map_error(prob, _planted(kind), 1.6)
     assert err_t > 1e-6 or err_u > 1e-6 or zero_parts > 1e-6
