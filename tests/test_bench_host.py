@@ -83,3 +83,15 @@ def test_gpus_above_one_exit_with_a_message():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_traffic_summaries_named_in_bench_exist():
+    """Every counter summary bench.py reads is a committed file with a record."""
+    import re
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    names = set(re.findall(r'"(\w+_traffic\.md)"', src))
+    assert names, "bench.py names no traffic summary"
+    for name in names:
+        path = os.path.join(ROOT, "profiles", name)
+        assert os.path.exists(path), name
+        assert "<!-- traffic: " in open(path).read(), name
