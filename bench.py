@@ -202,7 +202,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=None, help="untimed iterations first (default 1; 3 otherwise)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-4 solve")
-    ap.add_argument("--cpu-iters", type=int, default=None, help="oracle iterations timed (default 3; 30 for grid)")
+    ap.add_argument("--cpu-iters", type=int, default=None, help="oracle iterations timed (default 10; 30 for grid)")
     ap.add_argument("--eig-warm", type=int, default=0, choices=[0, 1],
                     help="warm-start the Jacobi eigen-decompositions (settings.eig_warm)")
     ap.add_argument("--alpha", type=float, default=1.8,
@@ -215,7 +215,7 @@ def main():
     if args.warmup is None:
         args.warmup = 1 if whole else 3
     if args.cpu_iters is None:
-        args.cpu_iters = 30 if args.workload == "grid" else 3
+        args.cpu_iters = 30 if args.workload == "grid" else 10
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               f"(independent instances shard across GPUs without exchange)", file=sys.stderr)
