@@ -229,6 +229,24 @@ int cdcs_reset_phase_times(cdcs_handle* h);
 int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets,
                      const double* in, double* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same projection
+ * as cdcs_psd_project, with the same arguments, kernels and results, but all
+ * device memory beyond `in` and `out` (the block index lists and the
+ * large-block workspace) lives in a fixed 64 MiB array in the library's
+ * device code, one per GPU, held from module load until the process ends.
+ * No hipMalloc or hipFree is called.  The current device must be the one
+ * `stream` belongs to.  Limit: the index lists (at most 28 bytes per block) plus the
+ * large-block workspace (8 (5 l^2 + 5 l + 16 + T(T+1) + 64) bytes per block
+ * of order K > 64, l = K rounded up to 8, T = ceil(K/32)) must fit in 64 MiB
+ * (e.g. one block of order 1024, or twenty-five of order 256); a larger request
+ * returns CDCS_E_ARG without launching anything.  Every call on one GPU uses
+ * that GPU's single array, so calls that overlap on one GPU (from two
+ * threads, or on two streams without ordering) race; calls ordered on one
+ * stream are safe (each clears the workspace it uses before use). */
+int cdcs_psd_project_noalloc(int32_t count, const int32_t* sizes, const int64_t* offsets,
+                             const double* in, double* out, void* stream);
+
 /* The Jacobi tile shape used per clique-size bucket (the autotuner's choice,
  * or the default): out[4 b + 0..3] = bucket's largest clique order (16, 32,
  * 64, 96), threads per clique, number of cliques in the bucket, 1 if the

@@ -56,7 +56,7 @@ EXPORTS = [
     "cdcs_default_settings", "cdcs_setup", "cdcs_setup_batch", "cdcs_iterate", "cdcs_solve",
     "cdcs_get_dims", "cdcs_get_entries", "cdcs_get_solution", "cdcs_get_certificate",
     "cdcs_get_state", "cdcs_set_state", "cdcs_get_phase_times", "cdcs_reset_phase_times",
-    "cdcs_psd_project", "cdcs_adjoint", "cdcs_get_tuning", "cdcs_last_error", "cdcs_abi_version",
+    "cdcs_psd_project", "cdcs_psd_project_noalloc", "cdcs_adjoint", "cdcs_get_tuning", "cdcs_last_error", "cdcs_abi_version",
     "cdcs_destroy",
 ]
 
@@ -115,6 +115,7 @@ def load(path: str = LIB_PATH):
     lib.cdcs_get_tuning.argtypes = [vp, C.POINTER(C.c_int32), C.c_int32]
     lib.cdcs_reset_phase_times.argtypes = [vp]
     lib.cdcs_psd_project.argtypes = [C.c_int32, _i32p, _i64p, vp, vp, vp]
+    lib.cdcs_psd_project_noalloc.argtypes = [C.c_int32, _i32p, _i64p, vp, vp, vp]
     lib.cdcs_adjoint.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_int32)]
     lib.cdcs_last_error.restype = C.c_char_p
     lib.cdcs_last_error.argtypes = []
@@ -316,3 +317,13 @@ def psd_project(sizes, offsets, inp, out, stream=None):
     _check(load().cdcs_psd_project(len(sizes), _ptr(sizes, C.c_int32), _ptr(offsets, C.c_int64),
                                    C.c_void_p(inp.data_ptr()), C.c_void_p(out.data_ptr()),
                                    C.c_void_p(stream) if stream else None))
+
+
+def psd_project_noalloc(sizes, offsets, inp, out, stream=None):
+    """psd_project through the entry point that allocates no device memory
+    (its scratch is a fixed array in the library, shared by every call on a GPU)."""
+    sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    _check(load().cdcs_psd_project_noalloc(len(sizes), _ptr(sizes, C.c_int32), _ptr(offsets, C.c_int64),
+                                           C.c_void_p(inp.data_ptr()), C.c_void_p(out.data_ptr()),
+                                           C.c_void_p(stream) if stream else None))

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <thread>
@@ -761,6 +762,94 @@ int pack_and_upload(cdcs_handle* h) {
 
 bool valid_inst(const cdcs_handle* h, int32_t inst) { return h && inst >= 0 && inst < h->B; }
 
+// ---------------------------------------------------------------------------
+// the conic step on its own (cdcs_psd_project and its no-allocation variant)
+// ---------------------------------------------------------------------------
+
+// host plan: blocks split into the four Jacobi buckets and the large-clique
+// list (largest first), with the large workspace offsets
+struct ProjPlan {
+  std::vector<int32_t> sizes;
+  std::vector<int64_t> offs;
+  std::vector<int32_t> bk[5];
+  std::vector<int32_t> large_sizes;
+  std::vector<int64_t> woff;
+  int64_t wtot = 0;
+  int32_t kmax_large = 0;
+};
+
+// device copies of the plan's arrays and the large workspace
+struct ProjDev {
+  int32_t* sizes = nullptr;
+  int64_t* offs = nullptr;
+  int32_t* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t* woff = nullptr;
+  int32_t* lsz = nullptr;
+  double* work = nullptr;
+};
+
+int plan_projection(int32_t count, const int32_t* sizes, const int64_t* offsets, ProjPlan* pl) {
+  for (int32_t k = 0; k < count; ++k) {
+    if (sizes[k] < 1 || sizes[k] > 1024 || offsets[k] < 0) return set_error(CDCS_E_ARG, "block size must be 1..1024");
+    pl->bk[bucket_of(sizes[k])].push_back(k);
+  }
+  std::stable_sort(pl->bk[4].begin(), pl->bk[4].end(), [&](int32_t x, int32_t y) { return sizes[x] > sizes[y]; });
+  for (int32_t k : pl->bk[4]) {
+    pl->large_sizes.push_back(sizes[k]);
+    pl->kmax_large = std::max(pl->kmax_large, sizes[k]);
+    pl->woff.push_back(pl->wtot);
+    pl->wtot += large_work_size(sizes[k]);
+  }
+  pl->woff.push_back(pl->wtot);
+  pl->sizes.assign(sizes, sizes + count);
+  pl->offs.assign(offsets, offsets + count);
+  return 0;
+}
+
+void launch_projection(const ProjPlan& pl, const ProjDev& dv, const double* in, double* out, hipStream_t st) {
+  const int kmaxs[4] = {16, 32, 64, 96};   // bucket orders (the last is empty while kJacobiMax = 64)
+  for (int b = 0; b < 4; ++b)
+    launch_psd_project(dv.sizes, dv.offs, dv.tasks[b], (int32_t)pl.bk[b].size(), kmaxs[b], in, out, st);
+  if (!pl.bk[4].empty())
+    launch_psd_project_large(dv.sizes, dv.offs, dv.tasks[4], dv.lsz, pl.large_sizes.data(),
+                             (int32_t)pl.bk[4].size(), pl.kmax_large, in, out, dv.work, dv.woff, st);
+}
+
+__global__ void k_fill_zero(double* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+unsigned fill_blocks(int64_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 2048); }
+
+// Device scratch of cdcs_psd_project_noalloc: every GPU the library runs on
+// holds one copy from module load until the process ends.  Host code never
+// uses the array's name as an address (on the host it is only a stand-in
+// for the symbol): scratch_base() looks its device address up once per
+// device and every later use goes through that pointer.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_base(unsigned char** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(CDCS_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(CDCS_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (unsigned char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
 
 }  // namespace
 
@@ -1428,25 +1517,9 @@ int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets
     return set_error(CDCS_E_ARG, "bad projection arguments");
   if (count == 0) return 0;
   hipStream_t st = (hipStream_t)stream;
-  std::vector<std::vector<int32_t>> bk(5);
-  std::vector<int32_t> large_sizes;
-  std::vector<int64_t> woff;
-  int64_t wtot = 0;
-  int32_t kmax_large = 0;
-  for (int32_t k = 0; k < count; ++k) {
-    if (sizes[k] < 1 || sizes[k] > 1024 || offsets[k] < 0) return set_error(CDCS_E_ARG, "block size must be 1..1024");
-    bk[bucket_of(sizes[k])].push_back(k);
-  }
-  std::stable_sort(bk[4].begin(), bk[4].end(), [&](int32_t x, int32_t y) { return sizes[x] > sizes[y]; });
-  for (int32_t k : bk[4]) {
-    large_sizes.push_back(sizes[k]);
-    kmax_large = std::max(kmax_large, sizes[k]);
-    woff.push_back(wtot);
-    wtot += large_work_size(sizes[k]);
-  }
-  woff.push_back(wtot);
-  std::vector<int32_t> vsz(sizes, sizes + count);
-  std::vector<int64_t> voff(offsets, offsets + count);
+  ProjPlan pl;
+  int rc = plan_projection(count, sizes, offsets, &pl);
+  if (rc) return rc;
   std::vector<void*> tmp;
   auto up = [&](const void* src, size_t bytes, void** dst) -> int {
     void* p = nullptr;
@@ -1460,37 +1533,94 @@ int cdcs_psd_project(int32_t count, const int32_t* sizes, const int64_t* offsets
     *dst = p;
     return 0;
   };
-  int rc = 0;
-  void *dsz, *doff, *dtask[5], *dwork = nullptr, *dwoff = nullptr, *dlsz = nullptr;
+  ProjDev dv;
   auto cleanup = [&]() {
     for (void* p : tmp) (void)hipFree(p);
   };
-  if ((rc = up(vsz.data(), vsz.size() * 4, &dsz)) || (rc = up(voff.data(), voff.size() * 8, &doff))) {
+  if ((rc = up(pl.sizes.data(), pl.sizes.size() * 4, (void**)&dv.sizes)) ||
+      (rc = up(pl.offs.data(), pl.offs.size() * 8, (void**)&dv.offs))) {
     cleanup();
     return rc;
   }
   for (int b = 0; b < 5; ++b)
-    if ((rc = up(bk[b].data(), bk[b].size() * 4, &dtask[b]))) {
+    if ((rc = up(pl.bk[b].data(), pl.bk[b].size() * 4, (void**)&dv.tasks[b]))) {
       cleanup();
       return rc;
     }
-  if (!bk[4].empty()) {
-    if ((rc = up(nullptr, (size_t)wtot * 8, &dwork)) || (rc = up(woff.data(), woff.size() * 8, &dwoff)) ||
-        (rc = up(large_sizes.data(), large_sizes.size() * 4, &dlsz))) {
+  if (!pl.bk[4].empty()) {
+    if ((rc = up(nullptr, (size_t)pl.wtot * 8, (void**)&dv.work)) ||
+        (rc = up(pl.woff.data(), pl.woff.size() * 8, (void**)&dv.woff)) ||
+        (rc = up(pl.large_sizes.data(), pl.large_sizes.size() * 4, (void**)&dv.lsz))) {
       cleanup();
       return rc;
     }
+    hipLaunchKernelGGL(k_fill_zero, dim3(fill_blocks(pl.wtot)), dim3(256), 0, st, dv.work, pl.wtot);
   }
-  const int kmaxs[4] = {16, 32, 64, 96};   // bucket orders (the last is empty while kJacobiMax = 64)
-  for (int b = 0; b < 4; ++b)
-    launch_psd_project((int32_t*)dsz, (int64_t*)doff, (int32_t*)dtask[b], (int32_t)bk[b].size(), kmaxs[b], in, out,
-                       st);
-  if (!bk[4].empty())
-    launch_psd_project_large((int32_t*)dsz, (int64_t*)doff, (int32_t*)dtask[4], (int32_t*)dlsz, large_sizes.data(),
-                             (int32_t)bk[4].size(), kmax_large, in, out, (double*)dwork, (int64_t*)dwoff, st);
+  launch_projection(pl, dv, in, out, st);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   cleanup();
+  if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("projection: ") + hipGetErrorString(e));
+  return 0;
+}
+
+int cdcs_psd_project_noalloc(int32_t count, const int32_t* sizes, const int64_t* offsets, const double* in,
+                             double* out, void* stream) {
+  if (count < 0 || (count > 0 && (!sizes || !offsets || !in || !out)))
+    return set_error(CDCS_E_ARG, "bad projection arguments");
+  if (count == 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  ProjPlan pl;
+  int rc = plan_projection(count, sizes, offsets, &pl);
+  if (rc) return rc;
+  // scratch layout: [sizes | offsets | task lists of the 5 buckets | large
+  // work offsets | large sizes | (256-byte aligned) large workspace]
+  size_t pos = 0;
+  auto place = [&](size_t bytes, size_t align) {
+    pos = (pos + align - 1) / align * align;
+    const size_t at = pos;
+    pos += bytes;
+    return at;
+  };
+  const size_t o_sizes = place(pl.sizes.size() * 4, 8);
+  const size_t o_offs = place(pl.offs.size() * 8, 8);
+  size_t o_tasks[5];
+  for (int b = 0; b < 5; ++b) o_tasks[b] = place(pl.bk[b].size() * 4, 8);
+  const size_t o_woff = place(pl.woff.size() * 8, 8);
+  const size_t o_lsz = place(pl.large_sizes.size() * 4, 8);
+  const size_t meta_bytes = pos;
+  const size_t o_work = place((size_t)pl.wtot * 8, 256);
+  if (pos > kScratchBytes)
+    return set_error(CDCS_E_ARG, "projection needs " + std::to_string(pos) +
+                                     " bytes of device scratch; cdcs_psd_project_noalloc holds " +
+                                     std::to_string(kScratchBytes) + " (use cdcs_psd_project)");
+  unsigned char* base = nullptr;
+  if ((rc = scratch_base(&base))) return rc;
+  // stage the index arrays in one host buffer and copy them in one transfer
+  std::vector<unsigned char> meta(meta_bytes);
+  auto put = [&](size_t at, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(meta.data() + at, src, bytes);
+  };
+  put(o_sizes, pl.sizes.data(), pl.sizes.size() * 4);
+  put(o_offs, pl.offs.data(), pl.offs.size() * 8);
+  for (int b = 0; b < 5; ++b) put(o_tasks[b], pl.bk[b].data(), pl.bk[b].size() * 4);
+  put(o_woff, pl.woff.data(), pl.woff.size() * 8);
+  put(o_lsz, pl.large_sizes.data(), pl.large_sizes.size() * 4);
+  HIPCHK(hipMemcpyAsync(base, meta.data(), meta_bytes, hipMemcpyHostToDevice, st));
+  ProjDev dv;
+  dv.sizes = (int32_t*)(base + o_sizes);
+  dv.offs = (int64_t*)(base + o_offs);
+  for (int b = 0; b < 5; ++b) dv.tasks[b] = (int32_t*)(base + o_tasks[b]);
+  if (!pl.bk[4].empty()) {
+    dv.woff = (int64_t*)(base + o_woff);
+    dv.lsz = (int32_t*)(base + o_lsz);
+    dv.work = (double*)(base + o_work);
+    // the previous call's workspace contents are still there: start from zeros
+    hipLaunchKernelGGL(k_fill_zero, dim3(fill_blocks(pl.wtot)), dim3(256), 0, st, dv.work, pl.wtot);
+  }
+  launch_projection(pl, dv, in, out, st);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("projection: ") + hipGetErrorString(e));
   return 0;
 }
