@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define CDCS_ABI_VERSION 4
+#define CDCS_ABI_VERSION 5
 
 /* outcomes (cdcs_info.status) */
 enum {
@@ -60,6 +60,13 @@ enum {
   CDCS_PRIMAL_INFEASIBLE = 2,
   CDCS_DUAL_INFEASIBLE = 3,
   CDCS_MAX_ITER = 4
+};
+
+/* cdcs_settings.method */
+enum {
+  CDCS_METHOD_SELF_DUAL = 0, /* the ADMM of eqs. Step1-Step3 on the homogeneous self-dual embedding */
+  CDCS_METHOD_PRIMAL = 1,    /* primal-only ADMM of the authors' earlier work (Section 5, CDCS-primal) */
+  CDCS_METHOD_DUAL = 2       /* dual-only ADMM of the authors' earlier work (Section 5, CDCS-dual) */
 };
 
 /* errors (negative return values) */
@@ -130,6 +137,25 @@ typedef struct {
                           first after cdcs_set_state, and every 64th.  Costs sum_k K_k^2
                           values of device memory.  A resumed run then matches an
                           uninterrupted one to rounding, not bit for bit.  0 = off. */
+  int32_t method;      /* CDCS_METHOD_SELF_DUAL (default), or one of the two methods Section 5
+                          compares with: the primal-only and dual-only ADMM of the authors'
+                          earlier chordal-decomposition work (CDCS-primal, CDCS-dual), the
+                          textbook ADMM on the consensus constraint s = H x (primal form,
+                          eq. DecomposedPriaml) or v = z (dual form, eq. DecomposedDual) with
+                          penalty rho.  Their step 1 solves with the m x m matrix A D^-1 A^T
+                          (factorised at setup, D = H^T H; CDCS_E_FACTOR if the constraints are
+                          linearly dependent on the pattern), their step 2 is the same clique
+                          projection.  They stop when eps_p = ||s - Hx|| / max(||s||, ||Hx||)
+                          (primal; dual: ||v - z|| / max(||v||, ||z||)) and eps_d =
+                          rho ||s+ - s|| / ||lam|| (dual: z) are both within eps_tol; they
+                          detect no infeasibility (status SOLVED or MAX_ITER only) and take
+                          alpha = 1, eig_warm = 0 and no adjoint (CDCS_E_ARG otherwise). */
+  double rho;          /* penalty of the primal-only / dual-only methods (> 0; default 1) */
+  int32_t jacobi_max;  /* largest clique order the Jacobi kernels take: 16, 32 or 64 (0 = 64);
+                          larger cliques take the tridiagonal path (reduction in LDS up to 136
+                          vertices, then bisection, inverse iteration and back-transformation).
+                          The projection is the same (it is unique); only the route and its cost
+                          change.  eig_fp32 and eig_warm apply to the Jacobi cliques only. */
 } cdcs_settings;
 
 typedef struct {
@@ -142,7 +168,8 @@ typedef struct {
 } cdcs_info;
 
 /* Fill s with eps_tol = 1e-4, max_iter = 2000, check_every = 1, timing = 0,
- * use_graph = 0, eig_fp32 = 0, autotune = 0, alpha = 1, eig_warm = 0. */
+ * use_graph = 0, eig_fp32 = 0, autotune = 0, alpha = 1, eig_warm = 0,
+ * method = CDCS_METHOD_SELF_DUAL, rho = 1, jacobi_max = 0 (64). */
 void cdcs_default_settings(cdcs_settings* s);
 
 /* Build the cached data of step 1 (the m x m factor of the matrix of eq.
@@ -181,7 +208,7 @@ int cdcs_get_entries(const cdcs_handle* h, int32_t inst, int32_t* row, int32_t* 
 int cdcs_get_solution(const cdcs_handle* h, int32_t inst, double* X, double* y, double* Z,
                       int32_t on_device);
 
-/* Certificate of an infeasible instance: PRIMAL_INFEASIBLE gives
+/* Certificate of an infeasible instance (self-dual method only): PRIMAL_INFEASIBLE gives
  * y_cert = y / b^T y (m) with A^T y_cert + H^T v ~ 0, v ~ z PSD, b^T y_cert = 1
  * (X_cert untouched); DUAL_INFEASIBLE gives X_cert = x / (-c^T x) (nE) with
  * A x ~ 0, H x ~ s PSD, c^T x = -1 (y_cert untouched).  CDCS_E_STATE
@@ -191,7 +218,10 @@ int cdcs_get_certificate(const cdcs_handle* h, int32_t inst, double* y_cert, dou
 
 /* Copy the iterate (u, v~) of instance `inst` out of / into the solver, in
  * the flattened coordinates above (host pointers).  set_state also resets
- * the instance's status to RUNNING; the iteration counter is kept. */
+ * the instance's status to RUNNING; the iteration counter is kept.  With
+ * the primal-only / dual-only methods u = (x, s, y) (nE + ns + m values;
+ * dual: z in place of s, x the multiplier of step 1) and vt = lam (ns values;
+ * dual: lam then v, 2 ns values). */
 int cdcs_get_state(const cdcs_handle* h, int32_t inst, double* u, double* vt);
 int cdcs_set_state(cdcs_handle* h, int32_t inst, const double* u, const double* vt);
 
@@ -213,6 +243,15 @@ int cdcs_set_state(cdcs_handle* h, int32_t inst, const double* u, const double* 
  * (CDCS_E_ARG). */
 int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32_t on_device,
                  int32_t max_iter, double tol, int32_t* iters);
+
+/* Outcome of the last cdcs_adjoint on this handle, per instance (arrays of
+ * the batch's instance count; either may be NULL): resid = the final
+ * relative residual ||g - (I - T'^T) mu|| / ||g|| of the adjoint system,
+ * reason = 0 if it is within tol, 1 if GMRES stopped because the residual
+ * stalled (the gradient is then as accurate as the forward solve allows),
+ * 2 if it stopped at max_iter.  The adjoint itself returns 0 in all three
+ * cases.  CDCS_E_STATE before the first cdcs_adjoint. */
+int cdcs_get_adjoint_info(const cdcs_handle* h, double* resid, int32_t* reason);
 
 /* Accumulated HIP-event time (ms) and launch count per kernel phase since
  * setup or the last reset (timing must be enabled).  names/ms/launches may

@@ -17,12 +17,11 @@ OUT = os.path.join(HERE, "libcdcs.so")
 OBJ = os.path.join(HERE, "_build")
 
 SOURCES = ["setup.cpp", "api.hip", "kernels_iter.hip", "kernels_cone.hip", "kernels_large.hip",
-           "kernels_adjoint.hip"]
+           "kernels_adjoint.hip", "kernels_split.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include")]
 # packed FP32 instructions stay off in every HIP translation unit
-GPU = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-       "-munsafe-fp-atomics"]
+GPU = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def _compile(src):

@@ -37,7 +37,8 @@ class Problem(C.Structure):
 class Settings(C.Structure):
     _fields_ = [("eps_tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("timing", C.c_int32), ("use_graph", C.c_int32), ("eig_fp32", C.c_int32),
-                ("autotune", C.c_int32), ("alpha", C.c_double), ("eig_warm", C.c_int32)]
+                ("autotune", C.c_int32), ("alpha", C.c_double), ("eig_warm", C.c_int32),
+                ("method", C.c_int32), ("rho", C.c_double), ("jacobi_max", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -50,13 +51,15 @@ class Info(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-ABI_VERSION = 4   # the layout of the structures above
+ABI_VERSION = 5   # the layout of the structures above
+
+SELF_DUAL, PRIMAL, DUAL = 0, 1, 2   # settings.method
 
 EXPORTS = [
     "cdcs_default_settings", "cdcs_setup", "cdcs_setup_batch", "cdcs_iterate", "cdcs_solve",
     "cdcs_get_dims", "cdcs_get_entries", "cdcs_get_solution", "cdcs_get_certificate",
     "cdcs_get_state", "cdcs_set_state", "cdcs_get_phase_times", "cdcs_reset_phase_times",
-    "cdcs_psd_project", "cdcs_psd_project_noalloc", "cdcs_adjoint", "cdcs_get_tuning", "cdcs_last_error", "cdcs_abi_version",
+    "cdcs_psd_project", "cdcs_psd_project_noalloc", "cdcs_adjoint", "cdcs_get_adjoint_info", "cdcs_get_tuning", "cdcs_last_error", "cdcs_abi_version",
     "cdcs_destroy",
 ]
 
@@ -116,6 +119,7 @@ def load(path: str = LIB_PATH):
     lib.cdcs_reset_phase_times.argtypes = [vp]
     lib.cdcs_psd_project.argtypes = [C.c_int32, _i32p, _i64p, vp, vp, vp]
     lib.cdcs_psd_project_noalloc.argtypes = [C.c_int32, _i32p, _i64p, vp, vp, vp]
+    lib.cdcs_get_adjoint_info.argtypes = [vp, _dp, _i32p]
     lib.cdcs_adjoint.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_int32)]
     lib.cdcs_last_error.restype = C.c_char_p
     lib.cdcs_last_error.argtypes = []
@@ -188,7 +192,8 @@ def default_settings(**kw) -> Settings:
 
 
 class Solver:
-    """A (batched) HSDE-ADMM solve living on the GPU."""
+    """A (batched) solve living on the GPU: the HSDE-ADMM (method = SELF_DUAL,
+    the default) or the primal-only / dual-only ADMM (method = PRIMAL / DUAL)."""
 
     def __init__(self, instances, settings: Settings | None = None, stream=None, **kw):
         lib = load()
@@ -245,9 +250,14 @@ class Solver:
         return r, c
 
     def get_state(self, i=0):
-        n = self.state_len(i)
-        u = np.empty(n)
-        vt = np.empty(n)
+        """(u, v~) of the self-dual method; (x, s, y), lam of the primal-only
+        method; (x, z, y), (lam, v) of the dual-only method."""
+        nE, ns, m, _ = self._dims[i]
+        if self.settings.method == SELF_DUAL:
+            u, vt = np.empty(self.state_len(i)), np.empty(self.state_len(i))
+        else:
+            u = np.empty(nE + ns + m)
+            vt = np.empty(ns if self.settings.method == PRIMAL else 2 * ns)
         _check(load().cdcs_get_state(self.h, i, _ptr(u, C.c_double), _ptr(vt, C.c_double)))
         return u, vt
 
@@ -289,6 +299,14 @@ class Solver:
         _check(load().cdcs_adjoint(self.h, C.c_void_p(dX.data_ptr()), C.c_void_p(dc.data_ptr()),
                                    C.c_void_p(db.data_ptr()), 1, int(max_iter), float(tol), C.byref(it)))
         return it.value
+
+    def adjoint_info(self):
+        """Per instance of the last adjoint: (final relative residual, reason),
+        reason 0 = within tol, 1 = stalled, 2 = iteration limit."""
+        r = np.empty(self.count)
+        why = np.empty(self.count, np.int32)
+        _check(load().cdcs_get_adjoint_info(self.h, _ptr(r, C.c_double), _ptr(why, C.c_int32)))
+        return r, why
 
     def phase_times(self):
         cap = 32

@@ -71,13 +71,15 @@ enum Phase {
   PH_R0 = 0, PH_SPMV_A, PH_TRSV, PH_SPMV_AT, PH_SCALAR1, PH_UPDATE_E, PH_UPDATE_R,
   PH_CONE16, PH_CONE32, PH_CONE64, PH_CONE96, PH_LG_GATHER, PH_LG_TRD_SYMV, PH_LG_TRD_UPDATE, PH_LG_TRD_TRAIL,
   PH_LG_TRD_TAIL, PH_LG_EIG_PREP, PH_LG_EIG_BISECT, PH_LG_EIG_SINGLE, PH_LG_EIG_CLUSTER, PH_LG_BT_TFACTOR,
-  PH_LG_BT_APPLY, PH_LG_RECON, PH_LG_PARTIALS, PH_SCALAR2, kNumPhases
+  PH_LG_BT_APPLY, PH_LG_RECON, PH_LG_PARTIALS, PH_SCALAR2, PH_SPLIT_R, PH_SPLIT_G, PH_SPLIT_X, PH_SPLIT_W,
+  PH_SPLIT_UPDATE, PH_SPLIT_SCALAR, kNumPhases
 };
 const char* kPhaseNames[kNumPhases] = {
     "r0_scatter", "spmv_A", "trsv", "spmv_At", "scalar1", "update_x", "update_y",
     "cone_jacobi16", "cone_jacobi32", "cone_jacobi64", "cone_jacobi96", "large_gather", "trd_symv",
     "trd_update", "trd_trail", "trd_tail", "eig_prep", "eig_bisect", "eig_single", "eig_cluster", "bt_tfactor",
-    "bt_apply", "large_recon", "large_partials", "scalar2"};
+    "bt_apply", "large_recon", "large_partials", "scalar2", "split_scatter", "split_rhs", "split_x",
+    "split_gather", "split_update", "split_scalar"};
 // phase of each large-clique step (the tridiagonalisation is timed per launch kind)
 const int kLargeStepPhase[kLargeSteps] = {PH_LG_GATHER, -1, -1, -1, PH_LG_RECON, PH_LG_PARTIALS};
 
@@ -104,6 +106,11 @@ struct cdcs_handle {
   // cone work lists by kernel variant
   int32_t* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int32_t ntasks[5] = {0, 0, 0, 0, 0};
+  // the adjoint's Jacobi lists (every clique of up to 64 vertices by size,
+  // independent of settings.jacobi_max) and the largest clique order
+  int32_t* adj_tasks[3] = {nullptr, nullptr, nullptr};
+  int32_t adj_ntasks[3] = {0, 0, 0};
+  int32_t max_clique = 0;
   // Jacobi buckets: clique orders (host), tile variant, whether autotuned
   std::vector<int32_t> bucket_sizes[4];
   int32_t jvar[4] = {0, 0, 0, 0};
@@ -133,6 +140,13 @@ struct cdcs_handle {
   int64_t* gm_seg = nullptr;   // 10 * B
   int32_t* gm_inst = nullptr;  // nf
   double setup_s = 0.0;
+  // primal-only / dual-only ADMM (settings.method 1 or 2)
+  SplitArgs sa{};
+  // outcome of the last cdcs_adjoint per instance: final relative residual
+  // ||g - (I - T'^T) mu|| / ||g|| and why GMRES stopped (0 tolerance met,
+  // 1 stalled, 2 iteration limit)
+  std::vector<double> adj_resid;
+  std::vector<int32_t> adj_reason;
 };
 
 namespace {
@@ -165,12 +179,15 @@ int dev_zeros(cdcs_handle* h, T** p, size_t count) {
   return 0;
 }
 
-int bucket_of(int K) {
+// Jacobi bucket of a clique of order K (0: <= 16, 1: <= 32, 2: <= 64), or 4
+// (the tridiagonal path) above jmax, the largest order the Jacobi kernels
+// take (settings.jacobi_max)
+int bucket_of(int K, int jmax = kJacobiMax) {
+  if (K > jmax) return 4;
   if (K <= 16) return 0;
   if (K <= 32) return 1;
   if (K <= 64) return 2;
-  if (K <= kJacobiMax) return 3;
-  return 4;
+  return 3;
 }
 
 // record a phase launch between two events when timing is on
@@ -248,7 +265,54 @@ void harvest_timers(cdcs_handle* h) {
   h->ev_used.clear();
 }
 
+// one iteration of the primal-only (method 1) or dual-only (method 2) ADMM:
+// scatter, right-hand side, the m x m solve (the same triangular-solve
+// kernel, its solution written to y), x, projection argument, the clique
+// projections (the conic-step kernels' stand-alone entry; buckets in
+// sequence, the large cliques' chain beside them on the second stream),
+// multiplier update, residuals
+int launch_split_iteration(cdcs_handle* h, int32_t stop) {
+  const DevPlan& d = h->d;
+  const SplitArgs& a = h->sa;
+  const int primal = h->set.method == 1;
+  hipStream_t st = h->stream;
+  DevPlan dy = d;
+  dy.w = d.y;
+  { PhaseTimer t(h, PH_SPLIT_R); launch_split_r(d, a, primal, st); }
+  { PhaseTimer t(h, PH_SPLIT_G); launch_split_g(d, a, primal, st); }
+  { PhaseTimer t(h, PH_TRSV); launch_trsv(dy, st); }
+  { PhaseTimer t(h, PH_SPLIT_X); launch_split_x(d, a, primal, st); }
+  { PhaseTimer t(h, PH_SPLIT_W); launch_split_w(d, a, primal, st); }
+  const bool fork = h->ntasks[4] != 0;
+  hipStream_t lst = st;
+  if (fork) {
+    HIPCHK(hipEventRecord(h->ev_fork, st));
+    lst = h->aux;
+    HIPCHK(hipStreamWaitEvent(lst, h->ev_fork, 0));
+    PhaseTimer t(h, PH_LG_GATHER, lst);
+    launch_psd_project_large(d.clq_size, d.clq_slot, h->tasks[4], d.big_size, h->large_sizes.data(), h->ntasks[4],
+                             h->kmax_large, a.w, a.p, d.big_work, d.big_off, lst);
+  }
+  const int kmaxs[4] = {16, 32, 64, 96};
+  for (int bk = 0; bk < 4; ++bk)
+    if (h->ntasks[bk]) {
+      PhaseTimer t(h, PH_CONE16 + bk);
+      launch_psd_project(d.clq_size, d.clq_slot, h->tasks[bk], h->ntasks[bk], kmaxs[bk], a.w, a.p, st, h->jvar[bk],
+                         h->set.eig_fp32);
+    }
+  if (fork) {
+    HIPCHK(hipEventRecord(h->ev_join, lst));
+    HIPCHK(hipStreamWaitEvent(st, h->ev_join, 0));
+  }
+  { PhaseTimer t(h, PH_SPLIT_UPDATE); launch_split_update(d, a, primal, st); }
+  { PhaseTimer t(h, PH_SPLIT_SCALAR); launch_split_scalar(d, a, h->set.eps_tol, h->set.max_iter, stop, st); }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return 0;
+}
+
 int launch_iteration(cdcs_handle* h, int32_t stop) {
+  if (h->set.method != 0) return launch_split_iteration(h, stop);
   const DevPlan& d = h->d;
   hipStream_t st = h->stream;
   { PhaseTimer t(h, PH_R0); launch_r0(d, st); }
@@ -490,7 +554,8 @@ int pack_and_upload(cdcs_handle* h) {
     const int64_t eo = h->ent_off[i], so = h->slot_off[i];
     for (int64_t e = 0; e < I[i].nE; ++e) {
       c[eo + e] = I[i].c[e];
-      pinv[eo + e] = 1.0 / (1.0 + 0.5 * I[i].D[e]);
+      // self-dual: P^{-1} = 1 / (1 + D/2); primal/dual-only methods: D^{-1}
+      pinv[eo + e] = h->set.method ? 1.0 / (double)I[i].D[e] : 1.0 / (1.0 + 0.5 * I[i].D[e]);
       halfD[eo + e] = 0.5 * I[i].D[e];
       ztx[eo + e] = I[i].zt_x[e];
       atzy[eo + e] = I[i].atzy[e];
@@ -689,17 +754,29 @@ int pack_and_upload(cdcs_handle* h) {
   // cliques and cone work lists (bucketed by size, largest first within a bucket)
   std::vector<int32_t> csize(P), cinst(P);
   std::vector<int64_t> cslot(P);
-  std::vector<std::vector<int32_t>> bk(5);
+  std::vector<std::vector<int32_t>> bk(5), abk(3);
+  const int jmax = h->set.jacobi_max ? h->set.jacobi_max : kJacobiMax;
+  h->max_clique = 0;
   for (int32_t i = 0; i < B; ++i)
     for (int32_t k = 0; k < I[i].p; ++k) {
       const int32_t g = h->clq_off[i] + k;
       csize[g] = I[i].csize[k];
       cinst[g] = i;
       cslot[g] = h->slot_off[i] + I[i].slot_off[k];
-      bk[bucket_of(csize[g])].push_back(g);
+      bk[bucket_of(csize[g], jmax)].push_back(g);
+      // the adjoint's eigen-cache runs Jacobi on every clique of up to 64
+      // vertices, whichever path the forward iteration routes it to
+      if (csize[g] <= kJacobiMax) abk[bucket_of(csize[g])].push_back(g);
+      h->max_clique = std::max(h->max_clique, csize[g]);
     }
   for (auto& v : bk)
     std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b2) { return csize[a] > csize[b2]; });
+  for (auto& v : abk)
+    std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b2) { return csize[a] > csize[b2]; });
+  for (int bkt = 0; bkt < 3; ++bkt) {
+    h->adj_ntasks[bkt] = (int32_t)abk[bkt].size();
+    if ((rc = dev_upload(h, &h->adj_tasks[bkt], abk[bkt]))) return rc;
+  }
   if ((rc = dev_upload(h, (int32_t**)&d.clq_size, csize)) || (rc = dev_upload(h, (int32_t**)&d.clq_inst, cinst)) ||
       (rc = dev_upload(h, (int64_t**)&d.clq_slot, cslot)))
     return rc;
@@ -748,8 +825,10 @@ int pack_and_upload(cdcs_handle* h) {
   std::vector<double> sc((size_t)B * kNsc, 0.0);
   for (int32_t i = 0; i < B; ++i) {
     double* s = &sc[(size_t)i * kNsc];
+    // (the primal/dual-only methods keep tau = 1, kappa = 0: objectives are
+    // c^T x and b^T y as they stand)
     s[SC_TAU] = 1.0;
-    s[SC_KAPPA] = 1.0;
+    s[SC_KAPPA] = h->set.method ? 0.0 : 1.0;
     s[SC_DEN] = I[i].den;
     s[SC_CTZX] = I[i].ctzx;
     s[SC_BTZY] = I[i].btzy;
@@ -757,6 +836,23 @@ int pack_and_upload(cdcs_handle* h) {
     s[SC_NC] = I[i].nc;
   }
   if ((rc = dev_upload(h, &d.sc, sc)) || (rc = dev_zeros(h, &d.st, (size_t)B * kNst))) return rc;
+  if (h->set.method) {
+    // slot blocks (never straddling an instance), projection buffers, partials
+    std::vector<int4> sblk;
+    std::vector<int32_t> sblk_off(B + 1, 0);
+    for (int32_t i = 0; i < B; ++i) {
+      for (int64_t q = h->slot_off[i]; q < h->slot_off[i + 1]; q += kSlotChunk)
+        sblk.push_back(make_int4(i, (int)q, (int)std::min<int64_t>(q + kSlotChunk, h->slot_off[i + 1]), 0));
+      sblk_off[i + 1] = (int32_t)sblk.size();
+    }
+    SplitArgs& a = h->sa;
+    a.rho = h->set.rho;
+    a.n_sblk = (int32_t)sblk.size();
+    if ((rc = dev_upload(h, (int4**)&a.sblk, sblk)) || (rc = dev_upload(h, (int32_t**)&a.sblk_off, sblk_off)) ||
+        (rc = dev_zeros(h, &a.w, NS)) || (rc = dev_zeros(h, &a.p, NS)) ||
+        (rc = dev_zeros(h, &a.part_s, (size_t)std::max<int32_t>(a.n_sblk, 1) * kSplitParts)))
+      return rc;
+  }
   return 0;
 }
 
@@ -866,6 +962,9 @@ void cdcs_default_settings(cdcs_settings* s) {
   s->autotune = 0;
   s->alpha = 1.0;
   s->eig_warm = 0;
+  s->method = CDCS_METHOD_SELF_DUAL;
+  s->rho = 1.0;
+  s->jacobi_max = 0;
 }
 
 int cdcs_abi_version(void) { return CDCS_ABI_VERSION; }
@@ -912,6 +1011,14 @@ int cdcs_setup_batch(int32_t count, const cdcs_problem* prob, const cdcs_setting
   if (!(set.alpha > 0.0 && set.alpha < 2.0))
     return set_error(CDCS_E_ARG, "settings: alpha must lie in (0, 2)");
   if (set.eig_warm != 0 && set.eig_warm != 1) return set_error(CDCS_E_ARG, "settings: eig_warm must be 0 or 1");
+  if (set.method < CDCS_METHOD_SELF_DUAL || set.method > CDCS_METHOD_DUAL)
+    return set_error(CDCS_E_ARG, "settings: method must be 0 (self-dual), 1 (primal) or 2 (dual)");
+  if (set.method != CDCS_METHOD_SELF_DUAL && (!(set.rho > 0.0) || !std::isfinite(set.rho)))
+    return set_error(CDCS_E_ARG, "settings: rho must be positive");
+  if (set.jacobi_max != 0 && set.jacobi_max != 16 && set.jacobi_max != 32 && set.jacobi_max != 64)
+    return set_error(CDCS_E_ARG, "settings: jacobi_max must be 0 (= 64), 16, 32 or 64");
+  if (set.method != CDCS_METHOD_SELF_DUAL && (set.alpha != 1.0 || set.eig_warm != 0))
+    return set_error(CDCS_E_ARG, "settings: alpha and eig_warm apply to the self-dual method only");
   const auto t0 = std::chrono::steady_clock::now();
   cdcs_handle* h = new cdcs_handle();
   h->stream = (hipStream_t)stream;
@@ -943,7 +1050,7 @@ int cdcs_setup_batch(int32_t count, const cdcs_problem* prob, const cdcs_setting
   std::vector<std::thread> pool;
   for (int t = 0; t < nthr; ++t)
     pool.emplace_back([&, t]() {
-      for (int i = t; i < count; i += nthr) rcs[i] = build_instance(prob[i], h->inst[i], errs[i]);
+      for (int i = t; i < count; i += nthr) rcs[i] = build_instance(prob[i], h->inst[i], errs[i], set.method);
     });
   for (auto& th : pool) th.join();
   for (int i = 0; i < count; ++i)
@@ -1085,6 +1192,20 @@ int cdcs_get_state(const cdcs_handle* h, int32_t inst, double* u, double* vt) {
   int rc = fetch_state(h, inst, S);
   if (rc) return rc;
   const Instance& I = h->inst[inst];
+  if (h->set.method != CDCS_METHOD_SELF_DUAL) {
+    // primal/dual-only methods: u = (x, s or z, y), vt = lam (primal) or (lam, v) (dual)
+    if (u) {
+      double* p = u;
+      std::memcpy(p, S.x.data(), I.nE * sizeof(double)); p += I.nE;
+      std::memcpy(p, S.s.data(), I.ns * sizeof(double)); p += I.ns;
+      std::memcpy(p, S.y.data(), I.m * sizeof(double));
+    }
+    if (vt) {
+      std::memcpy(vt, S.z.data(), I.ns * sizeof(double));
+      if (h->set.method == CDCS_METHOD_DUAL) std::memcpy(vt + I.ns, S.v.data(), I.ns * sizeof(double));
+    }
+    return 0;
+  }
   if (u) {
     double* p = u;
     std::memcpy(p, S.x.data(), I.nE * sizeof(double)); p += I.nE;
@@ -1107,6 +1228,23 @@ int cdcs_get_state(const cdcs_handle* h, int32_t inst, double* u, double* vt) {
 int cdcs_set_state(cdcs_handle* h, int32_t inst, const double* u, const double* vt) {
   if (!valid_inst(h, inst) || !u || !vt) return set_error(CDCS_E_ARG, "bad handle, instance or state");
   const Instance& I = h->inst[inst];
+  if (h->set.method != CDCS_METHOD_SELF_DUAL) {
+    const int64_t eo = h->ent_off[inst], so = h->slot_off[inst];
+    const int32_t ro = h->row_off[inst];
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpy(h->d.x + eo, u, I.nE * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d.s + so, u + I.nE, I.ns * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d.y + ro, u + I.nE + I.ns, I.m * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->d.z + so, vt, I.ns * sizeof(double), hipMemcpyHostToDevice));
+    if (h->set.method == CDCS_METHOD_DUAL)
+      HIPCHK(hipMemcpy(h->d.v + so, vt + I.ns, I.ns * sizeof(double), hipMemcpyHostToDevice));
+    int32_t st[kNst];
+    HIPCHK(hipMemcpy(st, h->d.st + (size_t)inst * kNst, sizeof(st), hipMemcpyDeviceToHost));
+    st[ST_STATUS] = CDCS_RUNNING;
+    st[ST_FROZEN] = 0;
+    HIPCHK(hipMemcpy(h->d.st + (size_t)inst * kNst, st, sizeof(st), hipMemcpyHostToDevice));
+    return 0;
+  }
   // h, r, w are identically zero along the iteration (step Step3); a state
   // with non-zero h, r or w is not one the method produces
   const double* hv = vt;
@@ -1153,8 +1291,11 @@ int cdcs_get_solution(const cdcs_handle* h, int32_t inst, double* X, double* y, 
   std::vector<double> xo(I.nE), yo(I.m), zo(I.nE, 0.0);
   for (int64_t e = 0; e < I.nE; ++e) xo[e] = S.x[e] / S.tau;
   for (int32_t r = 0; r < I.m; ++r) yo[r] = S.y[r] / S.tau;
-  // Z = sum_k E_k^T Z_k E_k (Theorem 2) = H^T z / tau in svec coordinates
-  for (int64_t s = 0; s < I.ns; ++s) zo[I.slot2ent[s]] += S.z[s];
+  // Z = sum_k E_k^T Z_k E_k (Theorem 2) = H^T z / tau in svec coordinates;
+  // the clique blocks Z_k are z (self-dual), the multiplier (primal-only
+  // method) or the projected block (dual-only method)
+  const std::vector<double>& zk = h->set.method == CDCS_METHOD_DUAL ? S.s : S.z;
+  for (int64_t s = 0; s < I.ns; ++s) zo[I.slot2ent[s]] += zk[s];
   for (int64_t e = 0; e < I.nE; ++e) zo[e] /= S.tau;
   if ((rc = put_out(h, X, xo, on_device)) || (rc = put_out(h, y, yo, on_device)) || (rc = put_out(h, Z, zo, on_device)))
     return rc;
@@ -1163,6 +1304,8 @@ int cdcs_get_solution(const cdcs_handle* h, int32_t inst, double* X, double* y, 
 
 int cdcs_get_certificate(const cdcs_handle* h, int32_t inst, double* y_cert, double* X_cert, int32_t on_device) {
   if (!valid_inst(h, inst)) return set_error(CDCS_E_ARG, "bad handle or instance");
+  if (h->set.method != CDCS_METHOD_SELF_DUAL)
+    return set_error(CDCS_E_STATE, "the primal-only and dual-only methods give no infeasibility certificates");
   HostState S;
   int rc = fetch_state(h, inst, S);
   if (rc) return rc;
@@ -1291,7 +1434,9 @@ int adjoint_prepare(cdcs_handle* h) {
 int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32_t on_device, int32_t max_iter,
                  double tol, int32_t* iters) {
   if (!h || !dX || max_iter < 1 || !(tol > 0.0)) return set_error(CDCS_E_ARG, "bad adjoint arguments");
-  if (h->ntasks[3] || h->ntasks[4]) return set_error(CDCS_E_ARG, "the adjoint supports cliques of up to 64 vertices");
+  if (h->set.method != CDCS_METHOD_SELF_DUAL)
+    return set_error(CDCS_E_ARG, "the adjoint differentiates the self-dual method's fixed point only");
+  if (h->max_clique > kJacobiMax) return set_error(CDCS_E_ARG, "the adjoint supports cliques of up to 64 vertices");
   const int32_t B = h->B;
   const int64_t NE = h->ent_off[B];
   const int32_t M = h->row_off[B];
@@ -1328,9 +1473,9 @@ int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32
   HIPCHK(hipMemcpy(a.as, as.data(), as.size() * sizeof(double), hipMemcpyHostToDevice));
   // eigenpairs of the clique blocks at the solution
   const int kmaxs[3] = {16, 32, 64};
-  for (int bk = 0; bk < 3; ++bk) launch_adj_eig(a, h->tasks[bk], h->ntasks[bk], kmaxs[bk], h->stream);
-  const int32_t* tl[3] = {h->tasks[0], h->tasks[1], h->tasks[2]};
-  const int32_t nt[3] = {h->ntasks[0], h->ntasks[1], h->ntasks[2]};
+  for (int bk = 0; bk < 3; ++bk) launch_adj_eig(a, h->adj_tasks[bk], h->adj_ntasks[bk], kmaxs[bk], h->stream);
+  const int32_t* tl[3] = {h->adj_tasks[0], h->adj_tasks[1], h->adj_tasks[2]};
+  const int32_t nt[3] = {h->adj_ntasks[0], h->adj_ntasks[1], h->adj_ntasks[2]};
   hipStream_t st = h->stream;
   const int64_t nf = h->nf;
   const int64_t NS = h->slot_off[B];
@@ -1466,6 +1611,20 @@ int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(CDCS_E_DEVICE, std::string("adjoint launch: ") + hipGetErrorString(e));
   }
+  // the final true residual of every instance (one more application)
+  {
+    double* V0 = h->gm_V;
+    if ((rc = apply_op(h->gm_mu, h->gm_w))) return rc;
+    launch_flat_sub(V0, h->gm_g, h->gm_w, nf, st);
+    if ((rc = seg_dots(V0, V0, 1, nrm))) return rc;
+    h->adj_resid.assign(B, 0.0);
+    h->adj_reason.assign(B, 0);
+    for (int32_t i = 0; i < B; ++i) {
+      const double rel = gnorm[i] > 0.0 ? std::sqrt(nrm[i]) / gnorm[i] : 0.0;
+      h->adj_resid[i] = rel;
+      h->adj_reason[i] = rel <= tol ? 0 : (done[i] ? 1 : 2);
+    }
+  }
   // nu = (I - Q)^{-1} mu and the data gradients
   adj_point(h, h->gm_mu);
   launch_adj_iteration(a, tl, nt, 1, 0, h->stream);
@@ -1475,6 +1634,16 @@ int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32
   if (iters) *iters = it;
   if (dC) HIPCHK(hipMemcpy(dC, a.dc, NE * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
   if (db) HIPCHK(hipMemcpy(db, a.db, M * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  return 0;
+}
+
+int cdcs_get_adjoint_info(const cdcs_handle* h, double* resid, int32_t* reason) {
+  if (!h) return set_error(CDCS_E_ARG, "null handle");
+  if (h->adj_resid.empty()) return set_error(CDCS_E_STATE, "no cdcs_adjoint call on this handle yet");
+  for (int32_t i = 0; i < h->B; ++i) {
+    if (resid) resid[i] = h->adj_resid[i];
+    if (reason) reason[i] = h->adj_reason[i];
+  }
   return 0;
 }
 

@@ -189,6 +189,20 @@ __device__ __forceinline__ double slot_vnew(const DevPlan& d, double s, double z
   return d.relax ? v + d.alpha * (uv - v) : uv;
 }
 
+// primal-only / dual-only ADMM (kernels_split.hip): arguments beyond the
+// shared plan
+struct SplitArgs {
+  double rho;             // penalty of the consensus constraint
+  double* w;              // slot space: projection argument
+  double* p;              // slot space: projection result
+  double* part_s;         // n_sblk * kSplitParts partial sums
+  const int4* sblk;       // slot blocks {inst, begin, end, 0}
+  int32_t n_sblk;
+  const int32_t* sblk_off;  // B+1 (slot-block ranges)
+};
+constexpr int kSplitParts = 8;
+constexpr int kSlotChunk = 4096;     // slots per slot block
+
 // launchers (defined in the .hip files)
 void launch_r0(const DevPlan& d, hipStream_t st);
 void launch_spmv_a(const DevPlan& d, hipStream_t st);
@@ -198,6 +212,13 @@ void launch_scalar1(const DevPlan& d, hipStream_t st);
 void launch_update_e(const DevPlan& d, hipStream_t st);
 void launch_update_r(const DevPlan& d, hipStream_t st);
 void launch_scalar2(const DevPlan& d, double eps_tol, int32_t max_iter, int32_t stop, hipStream_t st);
+void launch_split_r(const DevPlan& d, const SplitArgs& a, int primal, hipStream_t st);
+void launch_split_g(const DevPlan& d, const SplitArgs& a, int primal, hipStream_t st);
+void launch_split_x(const DevPlan& d, const SplitArgs& a, int primal, hipStream_t st);
+void launch_split_w(const DevPlan& d, const SplitArgs& a, int primal, hipStream_t st);
+void launch_split_update(const DevPlan& d, const SplitArgs& a, int primal, hipStream_t st);
+void launch_split_scalar(const DevPlan& d, const SplitArgs& a, double eps_tol, int32_t max_iter, int32_t stop,
+                         hipStream_t st);
 // cone step: tasks are clique ids.  Jacobi tile shape per bucket: variant 0
 // = the default threads per clique, 1 = the other candidate (twice as many for
 // 16-vertex cliques, half as many otherwise); fp32 = 1 runs the

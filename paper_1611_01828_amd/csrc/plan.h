@@ -60,11 +60,17 @@ struct Instance {
 };
 
 // Build one instance (validation, E', H, A, factor, Sherman-Morrison data).
-// Returns 0 or a negative CDCS_E_* code with err filled.
-int build_instance(const cdcs_problem& P, Instance& out, Error& err);
+// method 0 = the self-dual embedding (factor of I + A P^{-1} A^T); 1, 2 =
+// the primal-only / dual-only ADMM (factor of A D^{-1} A^T, no
+// Sherman-Morrison data).  Returns 0 or a negative CDCS_E_* code with err
+// filled.
+int build_instance(const cdcs_problem& P, Instance& out, Error& err, int32_t method = 0);
 
 // Dense Cholesky / sparse factor helpers (exposed for tests of the host code)
+// K = shift I + A diag(pinv) A^T (shift 1: the self-dual method; 0: the
+// primal-only / dual-only methods)
 int factor_K(int32_t m, const std::vector<int32_t>& aptr, const std::vector<int32_t>& acol,
-             const std::vector<double>& aval, const std::vector<double>& pinv, Factor& f, Error& err);
+             const std::vector<double>& aval, const std::vector<double>& pinv, Factor& f, Error& err,
+             double shift = 1.0);
 
 }  // namespace cdcs

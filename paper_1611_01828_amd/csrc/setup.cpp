@@ -98,7 +98,7 @@ void Factor::solve(std::vector<double>& g) const {
 
 int factor_K(int32_t m, const std::vector<int32_t>& aptr, const std::vector<int32_t>& acol,
              const std::vector<double>& aval, const std::vector<double>& pinv, Factor& f,
-             Error& err) {
+             Error& err, double shift) {
   f = Factor();
   f.m = m;
   const int64_t nE = (int64_t)pinv.size();
@@ -118,10 +118,10 @@ int factor_K(int32_t m, const std::vector<int32_t>& aptr, const std::vector<int3
         cval[at] = aval[q];
       }
   }
-  // K = I + A P^{-1} A^T, lower triangle
+  // K = shift I + A P^{-1} A^T, lower triangle
   if (m > 8192) return fail(err, CDCS_E_ARG, "m > 8192 constraints is not supported");
   std::vector<double> K((size_t)m * m, 0.0);   // column-major, lower used
-  for (int32_t i = 0; i < m; ++i) K[(size_t)i * m + i] = 1.0;
+  for (int32_t i = 0; i < m; ++i) K[(size_t)i * m + i] = shift;
   for (int64_t e = 0; e < nE; ++e) {
     const double w = pinv[e];
     for (int64_t a = cptr[e]; a < cptr[e + 1]; ++a) {
@@ -140,7 +140,7 @@ int factor_K(int32_t m, const std::vector<int32_t>& aptr, const std::vector<int3
     for (int32_t j = 0; j < m; ++j) {
       double d = L[(size_t)j * m + j];
       for (int32_t k = 0; k < j; ++k) d -= L[(size_t)k * m + j] * L[(size_t)k * m + j];
-      if (!(d > 0.0)) return fail(err, CDCS_E_FACTOR, "Cholesky of I + A P^-1 A^T broke down");
+      if (!(d > 0.0)) return fail(err, CDCS_E_FACTOR, "Cholesky of the m x m matrix broke down (constraints linearly dependent on the pattern?)");
       const double ljj = std::sqrt(d);
       L[(size_t)j * m + j] = ljj;
       for (int32_t i = j + 1; i < m; ++i) {
@@ -218,7 +218,7 @@ int factor_K(int32_t m, const std::vector<int32_t>& aptr, const std::vector<int3
       work[j] -= ljk * ljk;
       for (size_t t = q + 1; t < rows.size(); ++t) work[rows[t]] -= vals[t] * ljk;
     }
-    if (!(work[j] > 0.0)) return fail(err, CDCS_E_FACTOR, "sparse Cholesky of I + A P^-1 A^T broke down");
+    if (!(work[j] > 0.0)) return fail(err, CDCS_E_FACTOR, "sparse Cholesky of the m x m matrix broke down (constraints linearly dependent on the pattern?)");
     const double ljj = std::sqrt(work[j]);
     f.diag[j] = ljj;
     work[j] = 0.0;
@@ -285,7 +285,7 @@ int factor_K(int32_t m, const std::vector<int32_t>& aptr, const std::vector<int3
   return 0;
 }
 
-int build_instance(const cdcs_problem& P, Instance& I, Error& err) {
+int build_instance(const cdcs_problem& P, Instance& I, Error& err, int32_t method) {
   const int32_t n = P.n, m = P.m, p = P.p;
   if (n < 1 || m < 1 || p < 1) return fail(err, CDCS_E_ARG, "need n >= 1, m >= 1, p >= 1");
   if (!P.b || !P.clique_ptr || !P.clique_vtx) return fail(err, CDCS_E_ARG, "null b or clique arrays");
@@ -417,10 +417,29 @@ int build_instance(const cdcs_problem& P, Instance& I, Error& err) {
   I.b.assign(P.b, P.b + m);
   for (double v : I.b)
     if (!finite(v)) return fail(err, CDCS_E_NONFINITE, "non-finite value in b");
+  if (method != 0) {
+    // primal-only / dual-only ADMM: step 1 of both reduces to the m x m
+    // matrix A D^{-1} A^T (no Sherman-Morrison data)
+    std::vector<double> dinv(I.nE);
+    for (int64_t e = 0; e < I.nE; ++e) dinv[e] = 1.0 / (double)I.D[e];
+    int rc = factor_K(m, I.aptr, I.acol, I.aval, dinv, I.fac, err, 0.0);
+    if (rc) return rc;
+    I.zt_x.assign(I.nE, 0.0);
+    I.atzy.assign(I.nE, 0.0);
+    I.zt_y.assign(m, 0.0);
+    double nb = 0.0, nc = 0.0;
+    for (int64_t e = 0; e < I.nE; ++e) nc += I.c[e] * I.c[e];
+    for (int32_t i = 0; i < m; ++i) nb += I.b[i] * I.b[i];
+    I.den = 1.0;
+    I.ctzx = I.btzy = 0.0;
+    I.nb = std::sqrt(nb);
+    I.nc = std::sqrt(nc);
+    return 0;
+  }
   // ---- factor of the inner matrix (eqs. ThirdBlkElm, FactorizationMatrix) ----
   std::vector<double> pinv(I.nE);
   for (int64_t e = 0; e < I.nE; ++e) pinv[e] = 1.0 / (1.0 + 0.5 * I.D[e]);
-  int rc = factor_K(m, I.aptr, I.acol, I.aval, pinv, I.fac, err);
+  int rc = factor_K(m, I.aptr, I.acol, I.aval, pinv, I.fac, err, 1.0);
   if (rc) return rc;
   // ---- Sherman-Morrison data (eq. MatrixInverseResult) ----
   // zeta = (c, 0, -b, 0); M^{-1} zeta through the same eliminations:

@@ -11,6 +11,8 @@ dL/dC_ij = sqrt(2) dL/dc_e when C_ij = C_ji is one parameter).
 """
 from __future__ import annotations
 
+import warnings
+
 import numpy as np
 import torch
 
@@ -86,5 +88,13 @@ class _SolveFn(torch.autograd.Function):
             dc = torch.as_tensor(dcn)
             db = torch.as_tensor(dbn)
         ctx.adjoint_iterations = it
+        resid, why = ctx.solver.adjoint_info()
         ctx.solver.close()
+        off = [i for i in range(len(resid)) if why[i] != 0]
+        if off:
+            what = {1: "stalled", 2: "hit the iteration limit"}
+            warnings.warn("SDPLayer.backward: the adjoint system of instances "
+                          + ", ".join(f"{i} ({what[int(why[i])]}, residual {resid[i]:.1e})" for i in off)
+                          + f" is not solved to adjoint_tol = {layer.adjoint_tol:.0e}; their gradients are only "
+                          "as accurate as the forward solve", RuntimeWarning)
         return dc, db, None

@@ -29,17 +29,18 @@ def test_library_exports_every_declared_symbol():
     for name in _declared():
         assert hasattr(lib, name), name
     assert set(_declared()) == set(cdcs.EXPORTS)
-    assert lib.cdcs_abi_version() == 4
+    assert lib.cdcs_abi_version() == 5 == cdcs.ABI_VERSION
 
 
 def test_default_settings_match_the_paper():
     s = cdcs.default_settings()
     assert s.eps_tol == 1e-4 and s.max_iter == 2000 and s.check_every == 1
     assert s.eig_fp32 == 0 and s.autotune == 0 and s.alpha == 1.0 and s.eig_warm == 0
+    assert s.method == cdcs.SELF_DUAL and s.rho == 1.0 and s.jacobi_max == 0
 
 
 def test_struct_layouts():
     # cdcs_problem: 2 ints, (int64 + 3 ptrs), (int64 + 4 ptrs), ptr, int, 3 ptrs
     assert ctypes.sizeof(cdcs.Problem) == 8 + 32 + 40 + 8 + 8 + 24
-    assert ctypes.sizeof(cdcs.Settings) == 48
+    assert ctypes.sizeof(cdcs.Settings) == 64
     assert ctypes.sizeof(cdcs.Info) == 8 + 9 * 8

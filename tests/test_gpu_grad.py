@@ -90,3 +90,34 @@ def test_torch_layer_gradient_matches_finite_differences(lib):
         an = float(gc @ dc + gb @ db)
         _log(f"  fd {fd:.10f} autograd {an:.10f}")
         assert abs(fd - an) <= 1e-4 * (abs(an) + np.linalg.norm(gc) + np.linalg.norm(gb))
+
+
+def test_adjoint_reports_its_outcome(lib):
+    """cdcs_get_adjoint_info: the final relative residual of every instance and
+    why GMRES stopped; a tiny iteration limit is reported as such, and
+    SDPLayer turns it into a warning."""
+    import warnings
+
+    import torch
+    from paper_1611_01828_amd.layer import SDPLayer
+    _log("adjoint outcome reporting")
+    insts = [configs.small_block_arrow(50 + i, n=14, block=4, arrow=2, m=5) for i in range(2)]
+    ws = [np.random.default_rng(i).standard_normal(hsde.build_problem(x).nE) for i, x in enumerate(insts)]
+    s, _, _, _ = _gpu_grad(lib, insts, ws)
+    r, why = s.adjoint_info()
+    assert np.all(np.isfinite(r)) and set(why.tolist()) <= {0, 1}
+    assert all((why[i] == 0) == (r[i] <= 1e-11) for i in range(2))
+    s.adjoint(np.concatenate(ws), max_iter=3, tol=1e-14)
+    r3, why3 = s.adjoint_info()
+    assert list(why3) == [2, 2] and np.all(r3 > 1e-14)
+    s.close()
+    layer = SDPLayer(insts, eps_tol=1e-9, adjoint_tol=1e-14, adjoint_max_iter=3)
+    c0 = np.concatenate([layer.svec_of(i, x.C) for i, x in enumerate(insts)])
+    b0 = np.concatenate([x.b for x in insts])
+    c = torch.tensor(c0, dtype=torch.float64, device="cuda", requires_grad=True)
+    b = torch.tensor(b0, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = layer(c, b).sum()
+    with warnings.catch_warnings(record=True) as rec:
+        warnings.simplefilter("always")
+        L.backward()
+    assert any("iteration limit" in str(x.message) for x in rec)
