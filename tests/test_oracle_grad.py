@@ -65,3 +65,63 @@ def test_adjoint_iteration_reaches_the_dense_adjoint():
     db = tau * nu[off[2]:off[3]] - nu[off[4]] * u[off[2]:off[3]]
     assert np.linalg.norm(dc - gc) <= 1e-7 * np.linalg.norm(gc)
     assert np.linalg.norm(db - gb) <= 1e-7 * max(np.linalg.norm(gb), 1e-12)
+
+
+# ----------------------------------------------------------------------------
+# the Daleckii-Krein derivative of the PSD projection on its own
+# ----------------------------------------------------------------------------
+
+def _sym(rng, K):
+    G = rng.standard_normal((K, K))
+    return (G + G.T) / 2
+
+
+@pytest.mark.parametrize("K", [2, 3, 5, 8, 13, 20])
+def test_dproj_block_matches_central_differences_of_the_projection(K):
+    """dproj_block(Y, dY) against (Pi(Y + h dY) - Pi(Y - h dY)) / 2h, with Pi
+    the projection by eigendecomposition.  Random Y has no eigenvalue near 0
+    (where Pi is not differentiable): the truncation error is O(h^2) and the
+    rounding error O(eps / h)."""
+    rng = np.random.default_rng(100 + K)
+    for _ in range(5):
+        Y = _sym(rng, K)
+        lam = np.linalg.eigvalsh(Y)
+        assert np.min(np.abs(lam)) > 1e-3
+        dY = _sym(rng, K)
+        h = 1e-5
+        fd = (hsde.proj_psd(Y + h * dY) - hsde.proj_psd(Y - h * dY)) / (2 * h)
+        an = grad.dproj_block(Y, dY)
+        assert np.linalg.norm(an - fd) <= 1e-8 * np.linalg.norm(fd), np.linalg.norm(an - fd)
+
+
+def test_dproj_block_special_cases():
+    """Positive definite Y: the projection is the identity near Y, so DPi = I.
+    Negative definite: DPi = 0.  A 2x2 diagonal Y = diag(a, -c): the
+    off-diagonal entry of dY is scaled by a / (a + c) (the divided difference
+    of max(., 0) between a and -c), the diagonal keeps only the (1,1) entry."""
+    rng = np.random.default_rng(7)
+    G = rng.standard_normal((6, 6))
+    P = G @ G.T + 0.1 * np.eye(6)
+    dY = _sym(rng, 6)
+    assert np.allclose(grad.dproj_block(P, dY), dY, rtol=0, atol=1e-13)
+    assert np.allclose(grad.dproj_block(-P, dY), 0.0, rtol=0, atol=1e-13)
+    a, c = 3.0, 1.0
+    Y = np.diag([a, -c])
+    dY = np.array([[0.7, 0.4], [0.4, -0.2]])
+    want = np.array([[0.7, 0.4 * a / (a + c)], [0.4 * a / (a + c), 0.0]])
+    assert np.allclose(grad.dproj_block(Y, dY), want, rtol=0, atol=1e-15)
+
+
+def test_dproj_block_is_self_adjoint_and_a_contraction():
+    """DPi at Y is symmetric in the trace inner product with eigenvalues in
+    [0, 1] (the projection is firmly nonexpansive)."""
+    rng = np.random.default_rng(8)
+    K = 7
+    Y = _sym(rng, K)
+    A, B = _sym(rng, K), _sym(rng, K)
+    lhs = np.sum(grad.dproj_block(Y, A) * B)
+    rhs = np.sum(A * grad.dproj_block(Y, B))
+    assert abs(lhs - rhs) <= 1e-13 * max(1.0, abs(lhs))
+    nA = np.sum(A * A)
+    q = np.sum(A * grad.dproj_block(Y, A))
+    assert -1e-13 <= q <= nA * (1 + 1e-13)
