@@ -42,6 +42,14 @@ PEAK_HBM_GBS = 8000.0
 JACOBI_MAX = 64              # cliques up to this order: Jacobi in LDS; larger: the tridiagonal path
 
 
+# settings every solver of the run gets (command-line options)
+SOLVER_DEFAULTS = {}
+
+
+def make_solver(cdcs, instances, **settings):
+    return cdcs.Solver(instances, **{**SOLVER_DEFAULTS, **settings})
+
+
 def trd_tail_start(K, tail=136, nb=32):
     """First column of a clique's tridiagonalisation done in LDS by the tail kernel."""
     return ((K - tail + nb - 1) // nb) * nb if K > tail else 0
@@ -173,7 +181,7 @@ def measure_peaks(torch):
 def timed_solve(cdcs, torch, inst, label, **settings):
     """Wall time of a fresh cdcs_solve (graph replay, status read every 10 iterations)."""
     import threading
-    fresh = cdcs.Solver(inst, check_every=10, use_graph=1, **settings)
+    fresh = make_solver(cdcs, inst, check_every=10, use_graph=1, **settings)
     torch.cuda.synchronize()
     box = {}
     t0 = time.perf_counter()
@@ -208,7 +216,13 @@ def main():
     ap.add_argument("--alpha", type=float, default=1.8,
                     help="relaxation of the second solve (1 = skip it; the value is always alpha = 1)")
     ap.add_argument("--workload", choices=["maxcut", "batch", "grad", "grid"], default="maxcut")
+    ap.add_argument("--jacobi-max", type=int, default=0, choices=[0, 16, 32, 64],
+                    help="largest clique order the Jacobi kernels take (settings.jacobi_max; 0 = 64)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="leave out the compact batched and differentiated figures of the default line")
     args = ap.parse_args()
+    if args.jacobi_max:
+        SOLVER_DEFAULTS["jacobi_max"] = args.jacobi_max
     whole = args.workload in ("maxcut", "grid")
     if args.steps is None:
         args.steps = 2000 if whole else 20
@@ -243,7 +257,7 @@ def main():
     # timed region: the iteration replayed from a captured HIP graph
     t0 = time.perf_counter()
     ew = args.eig_warm
-    solver = cdcs.Solver(inst, use_graph=1, eig_warm=ew)
+    solver = make_solver(cdcs, inst, use_graph=1, eig_warm=ew)
     setup_s = time.perf_counter() - t0
     dims = solver.dims()
     print(f"[bench] setup {setup_s:.2f}s dims(nE, ns, m, p)={dims}", file=sys.stderr, flush=True)
@@ -267,7 +281,7 @@ def main():
     # per-kernel times: the first min(K, 200) of the same iterations launched
     # one by one with a HIP event pair around every launch on its stream
     ev_steps = min(args.steps, 200)
-    timed = cdcs.Solver(inst, timing=1, eig_warm=ew)
+    timed = make_solver(cdcs, inst, timing=1, eig_warm=ew)
     timed.iterate(args.warmup)
     timed.reset_phase_times()
     torch.cuda.synchronize()
@@ -313,7 +327,7 @@ def main():
         if args.alpha != 1.0:
             # the over-relaxed form of the same ADMM: its cost per iteration
             # (graph replay, as the value) and its time to the tolerance
-            rs = cdcs.Solver(inst, use_graph=1, alpha=args.alpha, eig_warm=ew)
+            rs = make_solver(cdcs, inst, use_graph=1, alpha=args.alpha, eig_warm=ew)
             rs.iterate(args.warmup)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -352,6 +366,11 @@ def main():
                "one_thread": {"value": round(args.cpu_iters / cdt1, 5), "cores": 1, "seconds": round(cdt1, 2)}}
         print(f"[bench] cpu oracle: {cpu}", file=sys.stderr, flush=True)
 
+    extra = {}
+    if not grid and not args.no_extra:
+        extra["batch"] = batch_summary(cdcs, configs, torch)
+        extra["grad"] = grad_summary(cdcs, configs, torch)
+
     out = {
         "metric": METRIC if not grid else "ADMM iters/s + time-to-1e-4 residual (max-cut grid companion)",
         "value": round(its, 3),
@@ -370,7 +389,8 @@ def main():
                                ("max-cut relaxation, G(n=2000, M=6000) random graph, C=-L, A_i=e_i e_i^T, b=1, "
                                 "min-degree chordal extension"),
                    "n": inst.n, "m": inst.m, "cliques": len(sizes), "max_clique": max(sizes),
-                   "nE": dims[0], "ns": dims[1], "eps_tol": 1e-4, "eig_warm": ew},
+                   "nE": dims[0], "ns": dims[1], "eps_tol": 1e-4, "eig_warm": ew,
+                   "jacobi_max": args.jacobi_max or 64},
         "roofline": roof,
         "measured_peaks": peaks,
         "cpu_baseline": cpu,
@@ -379,8 +399,102 @@ def main():
         "phases_ms_per_step": {k: round(v[0] / ev_steps, 4) for k, v in phases.items() if v[1]},
         "event_timed_ms_per_step": round(1e3 * dt_ev / ev_steps, 4),
         "event_timed_steps": ev_steps,
+        **extra,
     }
     print(json.dumps(out))
+
+
+def _status_counts(cdcs, infos):
+    st = {}
+    for x in infos:
+        k = cdcs.STATUS_NAMES[x["status"]]
+        st[k] = st.get(k, 0) + 1
+    return st
+
+
+def batch_summary(cdcs, configs, torch, steps=200, warmup=3):
+    """Compact figures of the 256-SDP batched workload for the default line:
+    instance-iterations/s of one batched handle (graph replay) against the
+    plain path (one handle per instance, a sample of 16), and the time until
+    every instance has stopped at eps_tol = 1e-4, in FP64 and with FP32
+    Jacobi eigensolves."""
+    insts = configs.block_arrow_batch256()
+
+    def rate(solver, count):
+        solver.iterate(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.iterate(steps)
+        torch.cuda.synchronize()
+        return count * steps / (time.perf_counter() - t0)
+
+    out = {"workload": "256 block-arrow SDPs, n ~ U{50..400}, block ~ U{4..32}, arrow ~ U{2..8}, m = n/2",
+           "unit": "instance-iter/s", "steps": steps}
+    for label, settings in (("fp64", {}), ("fp32_eig", {"eig_fp32": 1})):
+        s = make_solver(cdcs, insts, use_graph=1, **settings)
+        r = rate(s, len(insts))
+        s.close()
+        f = make_solver(cdcs, insts, check_every=10, use_graph=1, **settings)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = f.solve()
+        tsolve = time.perf_counter() - t0
+        f.close()
+        out[label] = {"value": round(r, 1), "ms_per_batch_iteration": round(1e3 * len(insts) / r, 4),
+                      "time_to_1e-4": {"seconds": round(tsolve, 3), "max_iterations": max(x["iter"] for x in infos),
+                                       "status_counts": _status_counts(cdcs, infos)}}
+        print(f"[bench] batch {label}: {r:.0f} instance-iterations/s, all stopped in {tsolve:.2f}s", file=sys.stderr,
+              flush=True)
+    plain_t, sample = 0.0, insts[::16]
+    for inst in sample:
+        p = make_solver(cdcs, inst, use_graph=1)
+        plain_t += steps / rate(p, 1)           # seconds for this instance's steps
+        p.close()
+    plain = len(sample) * steps / plain_t
+    out["plain_value"] = round(plain, 1)
+    out["speedup_vs_plain"] = round(out["fp64"]["value"] / plain, 2)
+    print(f"[bench] batch plain per instance: {plain:.0f} instance-iterations/s", file=sys.stderr, flush=True)
+    return out
+
+
+def grad_loss_weights(cdcs, insts):
+    """svec(W) over each instance's E' (W is drawn on the lower pattern entries)."""
+    import numpy as np
+    s = make_solver(cdcs, insts[:1])
+    rows, cols = s.entries(0)
+    s.close()
+    out = []
+    for inst in insts:
+        wr, wc, wv = inst.meta["W"]
+        key = {(int(r), int(c)): e for e, (r, c) in enumerate(zip(rows, cols))}
+        v = np.zeros(len(rows))
+        for r, c, x in zip(wr, wc, wv):
+            v[key[(int(r), int(c))]] = x * (1.0 if r == c else np.sqrt(2.0))
+        out.append(v)
+    return np.concatenate(out)
+
+
+def grad_summary(cdcs, configs, torch):
+    """Compact figures of the differentiated 64-SDP batch for the default line:
+    forward solve (eps_tol = 1e-4) + implicit gradient per second against the
+    forward solve alone, and the adjoint's operator applications."""
+    insts = configs.block_arrow_grad64()
+    dX = grad_loss_weights(cdcs, insts)      # every instance has the same pattern
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f = make_solver(cdcs, insts, check_every=10, use_graph=1)
+    infos = f.solve()
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dc, db, it = f.adjoint(dX, max_iter=20000, tol=1e-10)
+    tb = time.perf_counter() - t0
+    f.close()
+    out = {"workload": "64 block-arrow SDPs, n=200, block 16, arrow 4, m=100; loss <W, X*>",
+           "unit": "batches/s", "value": round(1.0 / (tf + tb), 4), "forward_only": round(1.0 / tf, 4),
+           "forward_s": round(tf, 3), "backward_s": round(tb, 3), "adjoint_applications": it,
+           "forward_iterations_max": max(x["iter"] for x in infos), "status_counts": _status_counts(cdcs, infos)}
+    print(f"[bench] grad: forward {tf:.3f}s backward {tb:.3f}s ({it} applications)", file=sys.stderr, flush=True)
+    return out
 
 
 def bench_batch(args, cdcs, configs):
@@ -396,7 +510,7 @@ def bench_batch(args, cdcs, configs):
 
     def run(label, **settings):
         t0 = time.perf_counter()
-        s = cdcs.Solver(insts, use_graph=1, **settings)
+        s = make_solver(cdcs, insts, use_graph=1, **settings)
         setup = time.perf_counter() - t0
         s.iterate(args.warmup)
         torch.cuda.synchronize()
@@ -406,7 +520,7 @@ def bench_batch(args, cdcs, configs):
         dt = time.perf_counter() - t0
         tuning = s.tuning()
         s.close()
-        f = cdcs.Solver(insts, check_every=10, use_graph=1, **settings)
+        f = make_solver(cdcs, insts, check_every=10, use_graph=1, **settings)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         infos = f.solve()
@@ -456,7 +570,7 @@ def bench_batch(args, cdcs, configs):
     sample = insts[::16]
     plain_t = 0.0
     for inst in sample:
-        p = cdcs.Solver(inst, use_graph=1)
+        p = make_solver(cdcs, inst, use_graph=1)
         p.iterate(args.warmup)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -468,7 +582,7 @@ def bench_batch(args, cdcs, configs):
     print(f"[bench] plain per instance: {plain:.0f} instance-iterations/s", file=sys.stderr, flush=True)
     # the streaming phases of the affine step against the HBM roofline
     # (per-launch durations from HIP events on the launch stream)
-    tm = cdcs.Solver(insts, timing=1)
+    tm = make_solver(cdcs, insts, timing=1)
     tm.iterate(args.warmup)
     tm.reset_phase_times()
     tm.iterate(args.steps)
@@ -508,7 +622,7 @@ def bench_grad(args, cdcs, configs):
     insts = configs.block_arrow_grad64()
     W = np.concatenate([i.meta["W"][2] for i in insts])
     # W is drawn on the lower pattern entries; map to svec over each instance's E'
-    s = cdcs.Solver(insts, check_every=10)
+    s = make_solver(cdcs, insts, check_every=10)
     dX = []
     for i, inst in enumerate(insts):
         rows, cols = s.entries(i)
@@ -524,7 +638,7 @@ def bench_grad(args, cdcs, configs):
     def run(**settings):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        f = cdcs.Solver(insts, check_every=10, use_graph=1, **settings)
+        f = make_solver(cdcs, insts, check_every=10, use_graph=1, **settings)
         infos = f.solve()
         tf = time.perf_counter() - t0
         t0 = time.perf_counter()
