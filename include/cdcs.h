@@ -18,7 +18,9 @@
  *    list strictly increasing (the natural order of Section 2.1) and of at
  *    most 1024 vertices (CDCS_E_CLIQUES otherwise).  Every vertex must lie in
  *    some clique and every data entry inside some C_k x C_k (the chordal
- *    pattern E').  At most 8192 constraints per instance (CDCS_E_ARG).  The optional clique_parent array
+ *    pattern E').  The m x m matrix of step 1 is factorised densely when it
+ *    is at least 20 % full and m <= 2048 (or m <= 64), sparsely otherwise
+ *    (any m).  The optional clique_parent array
  *    (p entries, -1 = root) is checked for the running-intersection
  *    property.  Chordal extension and clique-tree construction are done by
  *    the caller on the host.

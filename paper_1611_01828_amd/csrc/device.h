@@ -121,6 +121,7 @@ struct DevPlan {
   const int32_t* f_blev_off;
   const int32_t* f_blev_ptr;
   const int32_t* f_blev_rows;
+  double* trsv_z;             // M: the sparse solve's vector for orders above its LDS capacity
   // work lists
   const int4* eblk;           // {inst, begin, end, 0}
   int32_t n_eblk;
@@ -202,6 +203,33 @@ struct SplitArgs {
 };
 constexpr int kSplitParts = 8;
 constexpr int kSlotChunk = 4096;     // slots per slot block
+
+// Restarted-GMRES bookkeeping of one instance per thread, on the device, so
+// that a cycle runs without a host round trip.  Per instance i: the
+// (R+1) x R Hessenberg matrix (column-major), the Givens rotations, the
+// rotated right-hand side gamma, jlim (-1 while the instance still takes
+// columns, else the number of columns its update uses), done, and a ring of
+// the last kGmWindow restart residuals for the stall test.
+struct GmState {
+  double* H;      // B (R+1) R
+  double* cs;     // B R
+  double* sn;     // B R
+  double* gam;    // B (R+1)
+  double* hist;   // B kGmWindow
+  double* gnorm;  // B
+  int32_t* jlim;  // B
+  int32_t* done;  // B
+  int32_t* nhist; // B
+  int32_t* alldone;  // 1
+};
+constexpr int kGmWindow = 5;
+constexpr double kGmStall = 0.9;
+void launch_gm_begin(const GmState& g, const double* nrm, double* scale, int B, int R, double tol, hipStream_t st);
+void launch_gm_step(const GmState& g, const double* d1, const double* d2, const double* nrm, double* scale, int B,
+                    int R, int j, double tol, hipStream_t st);
+void launch_gm_solve(const GmState& g, double* coef, int B, int R, int jdone, hipStream_t st);
+void launch_gm_final(const GmState& g, const double* nrm, double* resid, int32_t* reason, int B, double tol,
+                     hipStream_t st);
 
 // launchers (defined in the .hip files)
 void launch_r0(const DevPlan& d, hipStream_t st);

@@ -398,6 +398,106 @@ __global__ __launch_bounds__(256) void k_flat_sub(double* out, const double* a, 
   if (e < NF) out[e] = a[e] - b[e];
 }
 
+
+// start of a cycle: beta = ||g - A mu|| (nrm holds its square); an instance
+// stops when beta <= tol ||g|| or when beta fell by less than 10 % over the
+// last kGmWindow restarts
+__global__ void k_gm_begin(GmState g, const double* nrm, double* scale, int B, int R, double tol) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const double beta = sqrt(nrm[i]);
+  int done = g.done[i];
+  if (!done) {
+    const int nh = g.nhist[i];
+    if (beta <= tol * fmax(g.gnorm[i], 1e-300) ||
+        (nh >= kGmWindow && beta > kGmStall * g.hist[(size_t)i * kGmWindow + nh % kGmWindow]))
+      done = 1;
+    g.hist[(size_t)i * kGmWindow + nh % kGmWindow] = beta;
+    g.nhist[i] = nh + 1;
+    g.done[i] = done;
+  }
+  g.gam[(size_t)i * (R + 1)] = beta;
+  scale[i] = beta > 0.0 ? 1.0 / beta : 0.0;
+  g.jlim[i] = done ? 0 : -1;
+  if (!done) g.alldone[0] = 0;   // (set to 1 by the host before the launch)
+}
+
+// Krylov step j: Hessenberg column from the two Gram-Schmidt passes (d1, d2:
+// (j+1) x B) and the new norm, previous rotations, a new one, gamma, the
+// instance's stopping column, and the scale of the next basis vector
+__global__ void k_gm_step(GmState g, const double* d1, const double* d2, const double* nrm, double* scale, int B,
+                          int R, int j, double tol) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  double* Hc = g.H + ((size_t)i * (R + 1)) * R + (size_t)j * (R + 1);
+  for (int k = 0; k <= j; ++k) Hc[k] = d1[(size_t)k * B + i] + d2[(size_t)k * B + i];
+  const double hn = sqrt(nrm[i]);
+  Hc[j + 1] = hn;
+  scale[i] = hn > 1e-300 ? 1.0 / hn : 0.0;
+  double* c_ = g.cs + (size_t)i * R;
+  double* s_ = g.sn + (size_t)i * R;
+  for (int k = 0; k < j; ++k) {
+    const double h0 = Hc[k], h1 = Hc[k + 1];
+    Hc[k] = c_[k] * h0 + s_[k] * h1;
+    Hc[k + 1] = -s_[k] * h0 + c_[k] * h1;
+  }
+  const double h0 = Hc[j], h1 = Hc[j + 1];
+  const double r = hypot(h0, h1);
+  c_[j] = r > 0.0 ? h0 / r : 1.0;
+  s_[j] = r > 0.0 ? h1 / r : 0.0;
+  Hc[j] = r;
+  Hc[j + 1] = 0.0;
+  double* gi = g.gam + (size_t)i * (R + 1);
+  gi[j + 1] = -s_[j] * gi[j];
+  gi[j] = c_[j] * gi[j];
+  if (g.jlim[i] < 0 && fabs(gi[j + 1]) <= tol * fmax(g.gnorm[i], 1e-300)) g.jlim[i] = j + 1;
+}
+
+// end of a cycle of jdone steps: y from H y = gamma over the instance's
+// columns (back substitution), coef[k B + i] = y_k (zero past them)
+__global__ void k_gm_solve(GmState g, double* coef, int B, int R, int jdone) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const int ji = g.jlim[i] < 0 ? jdone : g.jlim[i];
+  const double* Hm = g.H + ((size_t)i * (R + 1)) * R;
+  const double* gi = g.gam + (size_t)i * (R + 1);
+  double y[32];
+  for (int k = ji - 1; k >= 0; --k) {
+    double t = gi[k];
+    for (int l = k + 1; l < ji; ++l) t -= Hm[(size_t)l * (R + 1) + k] * y[l];
+    const double dkk = Hm[(size_t)k * (R + 1) + k];
+    y[k] = dkk != 0.0 ? t / dkk : 0.0;
+  }
+  for (int k = 0; k < jdone; ++k) coef[(size_t)k * B + i] = k < ji ? y[k] : 0.0;
+}
+
+// final relative residual and reason per instance (0 within tol, 1 stalled,
+// 2 iteration limit)
+__global__ void k_gm_final(GmState g, const double* nrm, double* resid, int32_t* reason, int B, double tol) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const double gn = g.gnorm[i];
+  const double rel = gn > 0.0 ? sqrt(nrm[i]) / gn : 0.0;
+  resid[i] = rel;
+  reason[i] = rel <= tol ? 0 : (g.done[i] ? 1 : 2);
+}
+
+void launch_gm_begin(const GmState& g, const double* nrm, double* scale, int B, int R, double tol,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_gm_begin, dim3((B + 63) / 64), dim3(64), 0, st, g, nrm, scale, B, R, tol);
+}
+void launch_gm_step(const GmState& g, const double* d1, const double* d2, const double* nrm, double* scale, int B,
+                    int R, int j, double tol, hipStream_t st) {
+  hipLaunchKernelGGL(k_gm_step, dim3((B + 63) / 64), dim3(64), 0, st, g, d1, d2, nrm, scale, B, R, j, tol);
+}
+void launch_gm_solve(const GmState& g, double* coef, int B, int R, int jdone, hipStream_t st) {
+  hipLaunchKernelGGL(k_gm_solve, dim3((B + 63) / 64), dim3(64), 0, st, g, coef, B, R, jdone);
+}
+void launch_gm_final(const GmState& g, const double* nrm, double* resid, int32_t* reason, int B, double tol,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_gm_final, dim3((B + 63) / 64), dim3(64), 0, st, g, nrm, resid, reason, B, tol);
+}
+
 void launch_seg_dots(const double* w, const double* Vb, int64_t NF, int nk, const int64_t* seg, double* out,
                      int B, hipStream_t st) {
   hipLaunchKernelGGL(k_seg_dots, dim3(B, nk), dim3(256), 0, st, w, Vb, NF, seg, out, B);
@@ -410,6 +510,13 @@ void launch_flat_axpy_multi(double* w, const double* Vb, int64_t NF, int nk, con
 void launch_flat_scale(double* out, const double* w, const double* sc, const int32_t* inst_of, int64_t NF,
                        hipStream_t st) {
   hipLaunchKernelGGL(k_flat_scale, dim3((NF + 255) / 256), dim3(256), 0, st, out, w, sc, inst_of, NF);
+}
+__global__ __launch_bounds__(256) void k_flat_sqrt(double* out, const double* a, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) out[e] = sqrt(a[e]);
+}
+void launch_flat_sqrt(double* out, const double* a, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_flat_sqrt, dim3((n + 255) / 256), dim3(256), 0, st, out, a, n);
 }
 void launch_flat_sub(double* out, const double* a, const double* b, int64_t NF, hipStream_t st) {
   hipLaunchKernelGGL(k_flat_sub, dim3((NF + 255) / 256), dim3(256), 0, st, out, a, b, NF);

@@ -211,12 +211,15 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(DevPlan d) {
     if (tid == 0) d.sc[inst * kNsc + SC_BW] = bw;
     return;
   }
-  // sparse, permuted: z = g[perm]
+  // sparse, permuted: z = g[perm], in LDS up to kTrsvLds rows, above in
+  // the instance's slice of the global vector trsv_z (the barriers between
+  // levels order its writes and reads within the workgroup)
+  double* z = (m <= kTrsvLds) ? zl : d.trsv_z + r0;
   const int32_t* perm = d.f_perm + r0;
   const double* dg = d.f_diag + r0;
   const int32_t* lptr = d.f_lptr + r0 + inst;
   const int32_t* uptr = d.f_uptr + r0 + inst;
-  for (int i = tid; i < m; i += kTrsvThreads) zl[i] = d.g[r0 + perm[i]];
+  for (int i = tid; i < m; i += kTrsvThreads) z[i] = d.g[r0 + perm[i]];
   __syncthreads();
   {
     const int l0 = d.f_flev_off[inst], l1 = d.f_flev_off[inst + 1];
@@ -224,9 +227,9 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(DevPlan d) {
       const int a = d.f_flev_ptr[l], bnd = d.f_flev_ptr[l + 1];
       for (int t = a + tid; t < bnd; t += kTrsvThreads) {
         const int i = d.f_flev_rows[t];
-        double sacc = zl[i];
-        for (int q = lptr[i]; q < lptr[i + 1]; ++q) sacc -= d.f_lval[q] * zl[d.f_lcol[q]];
-        zl[i] = sacc / dg[i];
+        double sacc = z[i];
+        for (int q = lptr[i]; q < lptr[i + 1]; ++q) sacc -= d.f_lval[q] * z[d.f_lcol[q]];
+        z[i] = sacc / dg[i];
       }
       __syncthreads();
     }
@@ -237,9 +240,9 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(DevPlan d) {
       const int a = d.f_blev_ptr[l], bnd = d.f_blev_ptr[l + 1];
       for (int t = a + tid; t < bnd; t += kTrsvThreads) {
         const int i = d.f_blev_rows[t];
-        double sacc = zl[i];
-        for (int q = uptr[i]; q < uptr[i + 1]; ++q) sacc -= d.f_uval[q] * zl[d.f_ucol[q]];
-        zl[i] = sacc / dg[i];
+        double sacc = z[i];
+        for (int q = uptr[i]; q < uptr[i + 1]; ++q) sacc -= d.f_uval[q] * z[d.f_ucol[q]];
+        z[i] = sacc / dg[i];
       }
       __syncthreads();
     }
@@ -247,8 +250,8 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(DevPlan d) {
   double bw = 0.0;
   for (int i = tid; i < m; i += kTrsvThreads) {
     const int r = r0 + perm[i];
-    d.w[r] = zl[i];
-    bw += d.b[r] * zl[i];
+    d.w[r] = z[i];
+    bw += d.b[r] * z[i];
   }
   bw = block_sum<kTrsvThreads>(bw, red);
   if (tid == 0) d.sc[inst * kNsc + SC_BW] = bw;

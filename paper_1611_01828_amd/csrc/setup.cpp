@@ -118,24 +118,73 @@ int factor_K(int32_t m, const std::vector<int32_t>& aptr, const std::vector<int3
         cval[at] = aval[q];
       }
   }
-  // K = shift I + A P^{-1} A^T, lower triangle
-  if (m > 8192) return fail(err, CDCS_E_ARG, "m > 8192 constraints is not supported");
-  std::vector<double> K((size_t)m * m, 0.0);   // column-major, lower used
-  for (int32_t i = 0; i < m; ++i) K[(size_t)i * m + i] = shift;
-  for (int64_t e = 0; e < nE; ++e) {
-    const double w = pinv[e];
-    for (int64_t a = cptr[e]; a < cptr[e + 1]; ++a) {
-      const int32_t i = crow[a];
-      const double ai = cval[a] * w;
-      for (int64_t bq = cptr[e]; bq <= a; ++bq) K[(size_t)crow[bq] * m + i] += ai * cval[bq];
+  // K = shift I + A P^{-1} A^T, lower triangle, as columns: kcp[j] ..
+  // kcp[j+1] holds the rows i >= j (ascending) and values of column j.  Up to
+  // kDenseAssembly rows K is summed in a dense m x m array (fast); above, as
+  // one term a_ie w_e a_je per pair of constraints touching entry e, sorted
+  // and summed per (column, row) key, so that a sparse K of any order needs
+  // memory in proportion to those pairs only.
+  constexpr int32_t kDenseAssembly = 8192;
+  std::vector<int64_t> kcp(m + 1, 0);
+  std::vector<int32_t> krow;
+  std::vector<double> kval;
+  if (m <= kDenseAssembly) {
+    std::vector<double> K((size_t)m * m, 0.0);   // column-major, lower used
+    for (int32_t i = 0; i < m; ++i) K[(size_t)i * m + i] = shift;
+    for (int64_t e = 0; e < nE; ++e) {
+      const double w = pinv[e];
+      for (int64_t a = cptr[e]; a < cptr[e + 1]; ++a) {
+        const int32_t i = crow[a];
+        const double ai = cval[a] * w;
+        for (int64_t bq = cptr[e]; bq <= a; ++bq) K[(size_t)crow[bq] * m + i] += ai * cval[bq];
+      }
+    }
+    for (int32_t j = 0; j < m; ++j)
+      for (int32_t i = j; i < m; ++i)
+        if (K[(size_t)j * m + i] != 0.0) {
+          krow.push_back(i);
+          kval.push_back(K[(size_t)j * m + i]);
+          kcp[j + 1]++;
+        }
+  } else {
+    struct Term {
+      int64_t key;   // j m + i
+      double v;
+    };
+    std::vector<Term> terms;
+    int64_t nt = m;
+    for (int64_t e = 0; e < nE; ++e) nt += (cptr[e + 1] - cptr[e]) * (cptr[e + 1] - cptr[e] + 1) / 2;
+    terms.reserve((size_t)nt);
+    for (int32_t i = 0; i < m; ++i) terms.push_back({(int64_t)i * m + i, shift});
+    for (int64_t e = 0; e < nE; ++e) {
+      const double w = pinv[e];
+      for (int64_t a = cptr[e]; a < cptr[e + 1]; ++a) {
+        const int32_t i = crow[a];
+        const double ai = cval[a] * w;
+        for (int64_t bq = cptr[e]; bq <= a; ++bq) terms.push_back({(int64_t)crow[bq] * m + i, ai * cval[bq]});
+      }
+    }
+    std::stable_sort(terms.begin(), terms.end(), [](const Term& x, const Term& y) { return x.key < y.key; });
+    for (size_t t = 0; t < terms.size();) {
+      size_t u = t;
+      double v = 0.0;
+      while (u < terms.size() && terms[u].key == terms[t].key) v += terms[u++].v;
+      if (v != 0.0) {
+        krow.push_back((int32_t)(terms[t].key % m));
+        kval.push_back(v);
+        kcp[terms[t].key / m + 1]++;
+      }
+      t = u;
     }
   }
-  int64_t nnz = 0;
-  for (int32_t j = 0; j < m; ++j)
-    for (int32_t i = j; i < m; ++i) nnz += (K[(size_t)j * m + i] != 0.0);
+  for (int32_t j = 0; j < m; ++j) kcp[j + 1] += kcp[j];
+  const int64_t nnz = kcp[m];
   const double density = (double)nnz / (0.5 * (double)m * (m + 1));
   if (m <= 64 || (density > 0.2 && m <= 2048)) {
     f.dense = true;
+    std::vector<double> K((size_t)m * m, 0.0);   // column-major, lower used
+    for (int32_t j = 0; j < m; ++j)
+      for (int64_t q = kcp[j]; q < kcp[j + 1]; ++q) K[(size_t)j * m + krow[q]] = kval[q];
     std::vector<double>& L = K;
     for (int32_t j = 0; j < m; ++j) {
       double d = L[(size_t)j * m + j];
@@ -178,10 +227,10 @@ int factor_K(int32_t m, const std::vector<int32_t>& aptr, const std::vector<int3
   f.dense = false;
   std::vector<std::set<int32_t>> adj(m);
   for (int32_t j = 0; j < m; ++j)
-    for (int32_t i = j + 1; i < m; ++i)
-      if (K[(size_t)j * m + i] != 0.0) {
-        adj[i].insert(j);
-        adj[j].insert(i);
+    for (int64_t q = kcp[j]; q < kcp[j + 1]; ++q)
+      if (krow[q] != j) {
+        adj[krow[q]].insert(j);
+        adj[j].insert(krow[q]);
       }
   std::vector<int32_t> order;
   std::vector<std::vector<int32_t>> higher;
@@ -203,7 +252,9 @@ int factor_K(int32_t m, const std::vector<int32_t>& aptr, const std::vector<int3
   auto Kp = [&](int32_t i, int32_t j) {            // i >= j in permuted labels
     int32_t a = order[i], b = order[j];
     if (a < b) std::swap(a, b);
-    return K[(size_t)b * m + a];
+    const auto lo = krow.begin() + kcp[b], hi = krow.begin() + kcp[b + 1];
+    const auto it = std::lower_bound(lo, hi, a);
+    return (it != hi && *it == a) ? kval[it - krow.begin()] : 0.0;
   };
   f.diag.assign(m, 0.0);
   for (int32_t j = 0; j < m; ++j) {

@@ -303,3 +303,15 @@ def test_setup_rejects_bad_inputs(lib, torch_cuda):
     with pytest.raises(lib.CDCSError) as e:
         lib.Solver(bad)
     assert e.value.code == -4
+
+
+@pytest.mark.timeout(600)
+def test_iterates_sparse_factor_beyond_lds(lib, torch_cuda):
+    """Max-cut on the periodic 100 x 100 grid: m = 10000 constraints, above the
+    8192 rows the sparse triangular solve keeps in LDS (its vector then lives
+    in global memory) and above the order up to which K is summed densely on
+    the host (K is assembled from its nonzero terms)."""
+    _log("iterates: max-cut on the 100 x 100 periodic grid (m = 10000)")
+    inst = configs.grid_maxcut(2, rows=100, cols=100)
+    w = _iterate_parity(lib, inst, 5)
+    _log(f"  worst rel {w:.2e}")
