@@ -24,6 +24,8 @@ Secondary measurements (their own JSON line, not the headline):
   --workload grid    the max-cut relaxation on a periodic 40 x 50 grid
                      (n = 2000, 1499 cliques of 5..147 vertices), measured
                      like the headline
+  --workload uneven  the uneven-clique SDP (n = 5000, cliques of 4..96
+                     vertices, m = 2000), measured like the headline
 """
 from __future__ import annotations
 
@@ -215,7 +217,10 @@ def main():
                     help="warm-start the Jacobi eigen-decompositions (settings.eig_warm)")
     ap.add_argument("--alpha", type=float, default=1.8,
                     help="relaxation of the second solve (1 = skip it; the value is always alpha = 1)")
-    ap.add_argument("--workload", choices=["maxcut", "batch", "grad", "grid"], default="maxcut")
+    ap.add_argument("--workload", choices=["maxcut", "batch", "grad", "grid", "uneven"], default="maxcut")
+    ap.add_argument("--method", choices=["self_dual", "primal", "dual"], default="self_dual",
+                    help="secondary lines only: the primal-only or dual-only ADMM (settings.method) in place of "
+                         "the self-dual method (the headline line always measures the self-dual method)")
     ap.add_argument("--jacobi-max", type=int, default=0, choices=[0, 16, 32, 64],
                     help="largest clique order the Jacobi kernels take (settings.jacobi_max; 0 = 64)")
     ap.add_argument("--no-extra", action="store_true",
@@ -223,7 +228,15 @@ def main():
     args = ap.parse_args()
     if args.jacobi_max:
         SOLVER_DEFAULTS["jacobi_max"] = args.jacobi_max
-    whole = args.workload in ("maxcut", "grid")
+    split = args.method != "self_dual"
+    if split:
+        if args.workload not in ("grid", "uneven") and not (args.workload == "maxcut" and args.no_extra):
+            print("--method primal|dual measures a secondary line: use --workload grid|uneven, or maxcut with "
+                  "--no-extra", file=sys.stderr)
+            sys.exit(2)
+        SOLVER_DEFAULTS["method"] = {"primal": 1, "dual": 2}[args.method]
+        args.alpha = 1.0        # the relaxed form belongs to the self-dual method
+    whole = args.workload in ("maxcut", "grid", "uneven")
     if args.steps is None:
         args.steps = 2000 if whole else 20
     if args.warmup is None:
@@ -246,9 +259,14 @@ def main():
     if args.workload == "grad":
         return bench_grad(args, cdcs, configs)
 
-    grid = args.workload == "grid"
+    grid = args.workload in ("grid", "uneven")   # secondary single-SDP workloads (no extra objects)
     t0 = time.perf_counter()
-    inst = configs.grid_maxcut(1) if grid else configs.maxcut_random_2000()
+    if args.workload == "grid":
+        inst = configs.grid_maxcut(1)
+    elif args.workload == "uneven":
+        inst = configs.uneven_cliques_5000()
+    else:
+        inst = configs.maxcut_random_2000()
     gen_s = time.perf_counter() - t0
     sizes = [len(c) for c in inst.cliques]
     print(f"[bench] workload: {inst.name}, p={len(sizes)}, max clique {max(sizes)}, "
@@ -341,23 +359,32 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        from oracle import hsde
+        from oracle import hsde, split as osplit
         prob = hsde.build_problem(inst)
-        cache = hsde.AffineCache(prob)
         csz = hsde.clique_sizes(prob)
-        u, vt = hsde.initial_point(prob)
+        if split:
+            scache = osplit.SplitCache(prob)
+
+            def sample():
+                st = osplit.initial_state(prob)
+                for _ in range(args.cpu_iters):
+                    st, _ = osplit.iterate(prob, scache, st, args.method, csz)
+        else:
+            cache = hsde.AffineCache(prob)
+
+            def sample():
+                u, vt = hsde.initial_point(prob)
+                for _ in range(args.cpu_iters):
+                    u, vt = hsde.iterate(prob, cache, u, vt, csz)
         t0 = time.perf_counter()
-        for _ in range(args.cpu_iters):
-            u, vt = hsde.iterate(prob, cache, u, vt, csz)
+        sample()
         cdt = time.perf_counter() - t0
         cores = len(os.sched_getaffinity(0))
         # the same sample with the BLAS/LAPACK pools limited to one thread
         from threadpoolctl import threadpool_limits
-        u, vt = hsde.initial_point(prob)
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
-            for _ in range(args.cpu_iters):
-                u, vt = hsde.iterate(prob, cache, u, vt, csz)
+            sample()
             cdt1 = time.perf_counter() - t0
         cpu = {"value": round(args.cpu_iters / cdt, 5), "unit": "iter/s", "cores": cores, "kind": "oracle",
                "sample": f"{args.cpu_iters} ADMM iterations of the same workload from the initial point "
@@ -372,7 +399,8 @@ def main():
         extra["grad"] = grad_summary(cdcs, configs, torch)
 
     out = {
-        "metric": METRIC if not grid else "ADMM iters/s + time-to-1e-4 residual (max-cut grid companion)",
+        "metric": METRIC if not (grid or split) else
+                  f"ADMM iters/s + time-to-1e-4 residual ({args.workload} workload, {args.method} method)",
         "value": round(its, 3),
         "unit": "iter/s",
         "n_gpus": 1,
@@ -385,12 +413,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": ("max-cut relaxation, periodic 40x50 grid (n=2000), C=-L, A_i=e_i e_i^T, b=1, "
-                                "min-degree chordal extension") if grid else
+                                "min-degree chordal extension") if args.workload == "grid" else
+                               ("uneven-clique SDP: clique-tree growth, n=5000, cliques of 4-96 vertices, m=2000 "
+                                "constraints of 8 entries, strictly feasible") if args.workload == "uneven" else
                                ("max-cut relaxation, G(n=2000, M=6000) random graph, C=-L, A_i=e_i e_i^T, b=1, "
                                 "min-degree chordal extension"),
                    "n": inst.n, "m": inst.m, "cliques": len(sizes), "max_clique": max(sizes),
                    "nE": dims[0], "ns": dims[1], "eps_tol": 1e-4, "eig_warm": ew,
-                   "jacobi_max": args.jacobi_max or 64},
+                   "jacobi_max": args.jacobi_max or 64, "method": args.method},
         "roofline": roof,
         "measured_peaks": peaks,
         "cpu_baseline": cpu,
@@ -454,6 +484,26 @@ def batch_summary(cdcs, configs, torch, steps=200, warmup=3):
     out["plain_value"] = round(plain, 1)
     out["speedup_vs_plain"] = round(out["fp64"]["value"] / plain, 2)
     print(f"[bench] batch plain per instance: {plain:.0f} instance-iterations/s", file=sys.stderr, flush=True)
+    # the gather/scatter/solve phases of the affine step against the HBM
+    # roofline: algorithmic bytes (affine_work) over the average launch
+    # duration from HIP events on the launch stream, 20 iterations
+    tm = make_solver(cdcs, insts, timing=1)
+    tm.iterate(warmup)
+    tm.reset_phase_times()
+    tm.iterate(20)
+    torch.cuda.synchronize()
+    phases = tm.phase_times()
+    dims = [tm.dims(i) for i in range(len(insts))]
+    tm.close()
+    aff = {}
+    for name, nbytes in affine_work(insts, dims).items():
+        ms, n = phases.get(name, (0.0, 0))
+        if n:
+            gbs = nbytes / (ms / n * 1e-3) / 1e9
+            aff[name] = {"achieved": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": nbytes,
+                         "avg_launch_ms": round(ms / n, 5)}
+    out["roofline_affine"] = {"bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s", "kernels": aff}
+    print(f"[bench] batch affine phases: {aff}", file=sys.stderr, flush=True)
     return out
 
 
