@@ -223,11 +223,16 @@ def main():
                          "the self-dual method (the headline line always measures the self-dual method)")
     ap.add_argument("--jacobi-max", type=int, default=0, choices=[0, 16, 32, 64],
                     help="largest clique order the Jacobi kernels take (settings.jacobi_max; 0 = 64)")
+    ap.add_argument("--band-min", type=int, default=0,
+                    help="smallest clique order of the two-stage tridiagonalisation (settings.band_min; 0 = 137, "
+                         "above 1024 = the one-stage reduction for every clique)")
     ap.add_argument("--no-extra", action="store_true",
                     help="leave out the compact batched and differentiated figures of the default line")
     args = ap.parse_args()
     if args.jacobi_max:
         SOLVER_DEFAULTS["jacobi_max"] = args.jacobi_max
+    if args.band_min:
+        SOLVER_DEFAULTS["band_min"] = args.band_min
     split = args.method != "self_dual"
     if split:
         if args.workload not in ("grid", "uneven") and not (args.workload == "maxcut" and args.no_extra):
@@ -420,7 +425,7 @@ def main():
                                 "min-degree chordal extension"),
                    "n": inst.n, "m": inst.m, "cliques": len(sizes), "max_clique": max(sizes),
                    "nE": dims[0], "ns": dims[1], "eps_tol": 1e-4, "eig_warm": ew,
-                   "jacobi_max": args.jacobi_max or 64, "method": args.method},
+                   "jacobi_max": args.jacobi_max or 64, "band_min": args.band_min or 137, "method": args.method},
         "roofline": roof,
         "measured_peaks": peaks,
         "cpu_baseline": cpu,

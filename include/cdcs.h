@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define CDCS_ABI_VERSION 5
+#define CDCS_ABI_VERSION 6
 
 /* outcomes (cdcs_info.status) */
 enum {
@@ -158,6 +158,13 @@ typedef struct {
                           vertices, then bisection, inverse iteration and back-transformation).
                           The projection is the same (it is unique); only the route and its cost
                           change.  eig_fp32 and eig_warm apply to the Jacobi cliques only. */
+  int32_t band_min;    /* smallest clique order whose eigendecomposition starts with the two-stage
+                          reduction (dense to a band of 8 sub-diagonals by panel QR, then band
+                          to tridiagonal by bulge chasing in LDS); smaller cliques above the
+                          Jacobi sizes take the one-stage blocked reduction (its last 136
+                          columns in LDS).  0 = 137 (every clique the LDS reduction cannot
+                          hold whole); values above 1024 keep the one-stage reduction for all;
+                          otherwise at least 137 (CDCS_E_ARG).  Same projection, other cost. */
 } cdcs_settings;
 
 typedef struct {
@@ -171,7 +178,7 @@ typedef struct {
 
 /* Fill s with eps_tol = 1e-4, max_iter = 2000, check_every = 1, timing = 0,
  * use_graph = 0, eig_fp32 = 0, autotune = 0, alpha = 1, eig_warm = 0,
- * method = CDCS_METHOD_SELF_DUAL, rho = 1, jacobi_max = 0 (64). */
+ * method = CDCS_METHOD_SELF_DUAL, rho = 1, jacobi_max = 0 (64), band_min = 0 (137). */
 void cdcs_default_settings(cdcs_settings* s);
 
 /* Build the cached data of step 1 (the m x m factor of the matrix of eq.
@@ -241,8 +248,9 @@ int cdcs_set_state(cdcs_handle* h, int32_t inst, const double* u, const double* 
  * follows eps_tol of the solve, not tol); all stop after max_iter operator
  * applications.  *iters (may be NULL) receives the number of applications.
  * on_device = 1: dX, dC, db are device pointers.  Every instance must be
- * SOLVED (CDCS_E_STATE) and have cliques of at most 64 vertices
- * (CDCS_E_ARG). */
+ * SOLVED (CDCS_E_STATE) and have cliques of at most 96 vertices
+ * (CDCS_E_ARG): the eigen-cache of the projection's derivative is a Jacobi
+ * decomposition held in LDS. */
 int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32_t on_device,
                  int32_t max_iter, double tol, int32_t* iters);
 

@@ -104,7 +104,15 @@ def adjoint_gradient_dense(res, w):
     Tp = np.eye(N) + R @ (2 * DP - np.eye(N)) - DP
     _, gu = loss_and_du(prob, res.u, w)
     g = DP @ gu
-    mu = np.linalg.lstsq((np.eye(N) - Tp).T, g, rcond=None)[0]
+    Aadj = (np.eye(N) - Tp).T
+    try:
+        mu = np.linalg.lstsq(Aadj, g, rcond=None)[0]
+    except np.linalg.LinAlgError:
+        # the divide-and-conquer SVD of gelsd does not converge on some of
+        # these matrices: the same minimum-norm least-squares solution from
+        # the QR-iteration SVD (gelss)
+        import scipy.linalg as sla
+        mu = sla.lstsq(Aadj, g, lapack_driver="gelss")[0]
     nu = R.T @ mu
     tau = u[off[4]]
     x = u[off[0]:off[1]]

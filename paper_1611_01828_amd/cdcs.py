@@ -38,7 +38,8 @@ class Settings(C.Structure):
     _fields_ = [("eps_tol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("timing", C.c_int32), ("use_graph", C.c_int32), ("eig_fp32", C.c_int32),
                 ("autotune", C.c_int32), ("alpha", C.c_double), ("eig_warm", C.c_int32),
-                ("method", C.c_int32), ("rho", C.c_double), ("jacobi_max", C.c_int32)]
+                ("method", C.c_int32), ("rho", C.c_double), ("jacobi_max", C.c_int32),
+                ("band_min", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -51,7 +52,7 @@ class Info(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-ABI_VERSION = 5   # the layout of the structures above
+ABI_VERSION = 6   # the layout of the structures above
 
 SELF_DUAL, PRIMAL, DUAL = 0, 1, 2   # settings.method
 
@@ -309,12 +310,12 @@ class Solver:
         return r, why
 
     def phase_times(self):
-        cap = 32
+        cap = 64
         names = (C.c_char_p * cap)()
         ms = (C.c_double * cap)()
         n = (C.c_int64 * cap)()
         k = _check(load().cdcs_get_phase_times(self.h, names, ms, n, cap))
-        return {names[i].decode(): (ms[i], n[i]) for i in range(k)}
+        return {names[i].decode(): (ms[i], n[i]) for i in range(min(k, cap))}
 
     def reset_phase_times(self):
         _check(load().cdcs_reset_phase_times(self.h))

@@ -19,6 +19,10 @@
 
 using namespace cdcs;
 
+// largest clique order the adjoint differentiates (Jacobi eigen-cache and
+// Daleckii-Krein product in LDS)
+constexpr int kAdjMax = 96;
+
 
 namespace cdcs {
 enum As { AS_QT = 0, AS_GT, AS_DEN2, AS_DIFF2, AS_NORM2, AS_BY, AS_EA, kNas = 8 };
@@ -74,14 +78,14 @@ enum Phase {
   PH_CONE16, PH_CONE32, PH_CONE64, PH_CONE96, PH_LG_GATHER, PH_LG_TRD_SYMV, PH_LG_TRD_UPDATE, PH_LG_TRD_TRAIL,
   PH_LG_TRD_TAIL, PH_LG_EIG_PREP, PH_LG_EIG_BISECT, PH_LG_EIG_SINGLE, PH_LG_EIG_CLUSTER, PH_LG_BT_TFACTOR,
   PH_LG_BT_APPLY, PH_LG_RECON, PH_LG_PARTIALS, PH_SCALAR2, PH_SPLIT_R, PH_SPLIT_G, PH_SPLIT_X, PH_SPLIT_W,
-  PH_SPLIT_UPDATE, PH_SPLIT_SCALAR, kNumPhases
+  PH_SPLIT_UPDATE, PH_SPLIT_SCALAR, PH_LG_BAND_PANEL, PH_LG_BAND_TRAIL, PH_LG_BAND_CHASE, PH_LG_BAND_Q2, kNumPhases
 };
 const char* kPhaseNames[kNumPhases] = {
     "r0_scatter", "spmv_A", "trsv", "spmv_At", "scalar1", "update_x", "update_y",
     "cone_jacobi16", "cone_jacobi32", "cone_jacobi64", "cone_jacobi96", "large_gather", "trd_symv",
     "trd_update", "trd_trail", "trd_tail", "eig_prep", "eig_bisect", "eig_single", "eig_cluster", "bt_tfactor",
     "bt_apply", "large_recon", "large_partials", "scalar2", "split_scatter", "split_rhs", "split_x",
-    "split_gather", "split_update", "split_scalar"};
+    "split_gather", "split_update", "split_scalar", "band_panel", "band_trail", "band_chase", "band_q2"};
 // phase of each large-clique step (the tridiagonalisation is timed per launch kind)
 const int kLargeStepPhase[kLargeSteps] = {PH_LG_GATHER, -1, -1, -1, PH_LG_RECON, PH_LG_PARTIALS};
 
@@ -108,10 +112,11 @@ struct cdcs_handle {
   // cone work lists by kernel variant
   int32_t* tasks[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int32_t ntasks[5] = {0, 0, 0, 0, 0};
-  // the adjoint's Jacobi lists (every clique of up to 64 vertices by size,
-  // independent of settings.jacobi_max) and the largest clique order
-  int32_t* adj_tasks[3] = {nullptr, nullptr, nullptr};
-  int32_t adj_ntasks[3] = {0, 0, 0};
+  // the adjoint's Jacobi lists (every clique of up to kAdjMax vertices by
+  // size: <= 16, 32, 64, 96; independent of settings.jacobi_max) and the
+  // largest clique order
+  int32_t* adj_tasks[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t adj_ntasks[4] = {0, 0, 0, 0};
   int32_t max_clique = 0;
   // Jacobi buckets: clique orders (host), tile variant, whether autotuned
   std::vector<int32_t> bucket_sizes[4];
@@ -198,6 +203,9 @@ int bucket_of(int K, int jmax = kJacobiMax) {
   return 3;
 }
 
+// smallest clique order that takes the two-stage tridiagonalisation
+int band_min_of(const cdcs_settings& s) { return s.band_min ? s.band_min : kBandMinDefault; }
+
 // record a phase launch between two events when timing is on
 // event pair from the pool (not yet recorded)
 size_t timer_alloc(cdcs_handle* h) {
@@ -258,7 +266,7 @@ struct TrdTimer {
   }
   static void end(void* c, int kind) {
     auto* t = static_cast<TrdTimer*>(c);
-    timer_commit(t->h, t->slot, PH_LG_TRD_SYMV + kind);
+    timer_commit(t->h, t->slot, kind < 10 ? PH_LG_TRD_SYMV + kind : PH_LG_BAND_PANEL + kind - 10);
   }
 };
 
@@ -299,7 +307,7 @@ int launch_split_iteration(cdcs_handle* h, int32_t stop) {
     HIPCHK(hipStreamWaitEvent(lst, h->ev_fork, 0));
     PhaseTimer t(h, PH_LG_GATHER, lst);
     launch_psd_project_large(d.clq_size, d.clq_slot, h->tasks[4], d.big_size, h->large_sizes.data(), h->ntasks[4],
-                             h->kmax_large, a.w, a.p, d.big_work, d.big_off, lst);
+                             h->kmax_large, a.w, a.p, d.big_work, d.big_off, lst, band_min_of(h->set));
   }
   const int kmaxs[4] = {16, 32, 64, 96};
   for (int bk = 0; bk < 4; ++bk)
@@ -356,6 +364,7 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
     for (int step = 0; step < kLargeSteps; ++step) {
       PhaseTimer t(h, kLargeStepPhase[step], lst);
       launch_cone_large_step(d, h->tasks[4], h->ntasks[4], h->kmax_large, h->large_sizes.data(), step, lst,
+                             band_min_of(h->set),
                              h->set.timing ? &hook : nullptr);
     }
   }
@@ -763,7 +772,7 @@ int pack_and_upload(cdcs_handle* h) {
   // cliques and cone work lists (bucketed by size, largest first within a bucket)
   std::vector<int32_t> csize(P), cinst(P);
   std::vector<int64_t> cslot(P);
-  std::vector<std::vector<int32_t>> bk(5), abk(3);
+  std::vector<std::vector<int32_t>> bk(5), abk(4);
   const int jmax = h->set.jacobi_max ? h->set.jacobi_max : kJacobiMax;
   h->max_clique = 0;
   for (int32_t i = 0; i < B; ++i)
@@ -773,16 +782,16 @@ int pack_and_upload(cdcs_handle* h) {
       cinst[g] = i;
       cslot[g] = h->slot_off[i] + I[i].slot_off[k];
       bk[bucket_of(csize[g], jmax)].push_back(g);
-      // the adjoint's eigen-cache runs Jacobi on every clique of up to 64
-      // vertices, whichever path the forward iteration routes it to
-      if (csize[g] <= kJacobiMax) abk[bucket_of(csize[g])].push_back(g);
+      // the adjoint's eigen-cache runs Jacobi on every clique of up to
+      // kAdjMax vertices, whichever path the forward iteration routes it to
+      if (csize[g] <= kAdjMax) abk[bucket_of(csize[g], kAdjMax)].push_back(g);
       h->max_clique = std::max(h->max_clique, csize[g]);
     }
   for (auto& v : bk)
     std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b2) { return csize[a] > csize[b2]; });
   for (auto& v : abk)
     std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b2) { return csize[a] > csize[b2]; });
-  for (int bkt = 0; bkt < 3; ++bkt) {
+  for (int bkt = 0; bkt < 4; ++bkt) {
     h->adj_ntasks[bkt] = (int32_t)abk[bkt].size();
     if ((rc = dev_upload(h, &h->adj_tasks[bkt], abk[bkt]))) return rc;
   }
@@ -974,6 +983,7 @@ void cdcs_default_settings(cdcs_settings* s) {
   s->method = CDCS_METHOD_SELF_DUAL;
   s->rho = 1.0;
   s->jacobi_max = 0;
+  s->band_min = 0;
 }
 
 int cdcs_abi_version(void) { return CDCS_ABI_VERSION; }
@@ -1026,6 +1036,8 @@ int cdcs_setup_batch(int32_t count, const cdcs_problem* prob, const cdcs_setting
     return set_error(CDCS_E_ARG, "settings: rho must be positive");
   if (set.jacobi_max != 0 && set.jacobi_max != 16 && set.jacobi_max != 32 && set.jacobi_max != 64)
     return set_error(CDCS_E_ARG, "settings: jacobi_max must be 0 (= 64), 16, 32 or 64");
+  if (set.band_min != 0 && set.band_min < kBandMinDefault)
+    return set_error(CDCS_E_ARG, "settings: band_min must be 0 or at least 137");
   if (set.method != CDCS_METHOD_SELF_DUAL && (set.alpha != 1.0 || set.eig_warm != 0))
     return set_error(CDCS_E_ARG, "settings: alpha and eig_warm apply to the self-dual method only");
   const auto t0 = std::chrono::steady_clock::now();
@@ -1458,7 +1470,7 @@ int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32
   if (!h || !dX || max_iter < 1 || !(tol > 0.0)) return set_error(CDCS_E_ARG, "bad adjoint arguments");
   if (h->set.method != CDCS_METHOD_SELF_DUAL)
     return set_error(CDCS_E_ARG, "the adjoint differentiates the self-dual method's fixed point only");
-  if (h->max_clique > kJacobiMax) return set_error(CDCS_E_ARG, "the adjoint supports cliques of up to 64 vertices");
+  if (h->max_clique > kAdjMax) return set_error(CDCS_E_ARG, "the adjoint supports cliques of up to 96 vertices");
   const int32_t B = h->B;
   const int64_t NE = h->ent_off[B];
   const int32_t M = h->row_off[B];
@@ -1494,10 +1506,10 @@ int cdcs_adjoint(cdcs_handle* h, const double* dX, double* dC, double* db, int32
   HIPCHK(hipMemcpy(const_cast<double*>(a.gx), gx.data(), NE * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(a.as, as.data(), as.size() * sizeof(double), hipMemcpyHostToDevice));
   // eigenpairs of the clique blocks at the solution
-  const int kmaxs[3] = {16, 32, 64};
-  for (int bk = 0; bk < 3; ++bk) launch_adj_eig(a, h->adj_tasks[bk], h->adj_ntasks[bk], kmaxs[bk], h->stream);
-  const int32_t* tl[3] = {h->adj_tasks[0], h->adj_tasks[1], h->adj_tasks[2]};
-  const int32_t nt[3] = {h->adj_ntasks[0], h->adj_ntasks[1], h->adj_ntasks[2]};
+  const int kmaxs[4] = {16, 32, 64, 96};
+  for (int bk = 0; bk < 4; ++bk) launch_adj_eig(a, h->adj_tasks[bk], h->adj_ntasks[bk], kmaxs[bk], h->stream);
+  const int32_t* tl[4] = {h->adj_tasks[0], h->adj_tasks[1], h->adj_tasks[2], h->adj_tasks[3]};
+  const int32_t nt[4] = {h->adj_ntasks[0], h->adj_ntasks[1], h->adj_ntasks[2], h->adj_ntasks[3]};
   hipStream_t st = h->stream;
   const int64_t nf = h->nf;
   const int64_t NS = h->slot_off[B];

@@ -143,10 +143,13 @@ struct DevPlan {
 
 // doubles of workspace one large-clique task needs (matrix, eigenvectors,
 // LU / panel scratch, tridiagonal data, tile partials)
+// reflectors of the band-to-tridiagonal stage: kBandRefl doubles (tau and
+// v_1..v_7) per step, (K + 6) / 8 steps per sweep, K - 2 sweeps
+inline int64_t band_refl_size(int K) { return K > 2 ? (int64_t)(K - 2) * ((K + 6) / 8) * 8 : 0; }
 inline int64_t large_work_size(int K) {
   const int64_t T = (K + 31) / 32;
   const int64_t ld = (K + 7) & ~7;
-  return 5LL * ld * ld + 5LL * ld + 16 + T * (T + 1) + 64;
+  return 5LL * ld * ld + 5LL * ld + 16 + T * (T + 1) + 64 + band_refl_size(K);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -258,17 +261,24 @@ void launch_cone_jacobi(const DevPlan& d, const int32_t* tasks, int32_t ntask, i
 constexpr int kLargeSteps = 6;
 // timing of the large-clique launches (kind 0 symv, 1 update, 2 trailing
 // update, 3 tail in LDS, 4 eigen prep, 5 bisection, 6 isolated vectors,
-// 7 clustered vectors, 8 WY factors, 9 back-transformation): begin() hands
-// out an event pair that the launch itself records (the kernel's own start
-// and end), end() files it
+// 7 clustered vectors, 8 WY factors, 9 back-transformation, 10 band panel
+// QR, 11 band trailing update, 12 bulge chasing, 13 bulge-chasing
+// back-transformation): begin() hands out an event
+// pair that the launch itself records (the kernel's own start and end),
+// end() files it
 struct LaunchHook {
   void (*begin)(void* ctx, int kind, hipEvent_t* start, hipEvent_t* stop);
   void (*end)(void* ctx, int kind);
   void* ctx;
 };
+// Cliques of at least band_min vertices take the two-stage reduction (dense
+// to band, band to tridiagonal); the others the one-stage blocked reduction
+// and the LDS tail.
+constexpr int kBandMinDefault = 137;
 // host_sizes: the tasks' clique orders on the host, sorted descending
 void launch_cone_large_step(const DevPlan& d, const int32_t* tasks, int32_t ntask, int32_t kmax,
-                            const int32_t* host_sizes, int step, hipStream_t st, const LaunchHook* hook = nullptr);
+                            const int32_t* host_sizes, int step, hipStream_t st, int band_min,
+                            const LaunchHook* hook = nullptr);
 // stand-alone projection of packed blocks
 void launch_psd_project(const int32_t* sizes, const int64_t* offs, const int32_t* tasks, int32_t ntask,
                         int kmax, const double* in, double* out, hipStream_t st, int variant = 0, int fp32 = 0);
@@ -276,6 +286,7 @@ void launch_psd_project(const int32_t* sizes, const int64_t* offs, const int32_t
 // host_sizes (host) hold those orders
 void launch_psd_project_large(const int32_t* sizes, const int64_t* offs, const int32_t* tasks,
                               const int32_t* task_sizes, const int32_t* host_sizes, int32_t ntask, int32_t kmax,
-                              const double* in, double* out, double* work, const int64_t* work_off, hipStream_t st);
+                              const double* in, double* out, double* work, const int64_t* work_off, hipStream_t st,
+                              int band_min = kBandMinDefault);
 
 }  // namespace cdcs

@@ -242,20 +242,24 @@ __global__ __launch_bounds__(kThreads) void k_adj_ur(AdjPlan ap, int final_pass)
 // 9. s and v blocks of mu: q_s, q_v from H q_x, then DPi on the clique block
 template <int KMAX, int NT>
 __global__ __launch_bounds__(NT) void k_adj_cone(AdjPlan ap, const int32_t* tasks) {
+  // V and one K x K work matrix in LDS (two arrays: 147 KB at KMAX = 96);
+  // each product's entries are formed in registers (NO per thread) and
+  // written over the work matrix after a barrier
+  constexpr int NO = (KMAX * KMAX + NT - 1) / NT;
   __shared__ double Vs[KMAX * KMAX];
   __shared__ double M[KMAX * KMAX];
-  __shared__ double T[KMAX * KMAX];
   __shared__ double lam[KMAX];
   __shared__ double red[NT / 64 + 1];
   const DevPlan& d = ap.d;
   const int k = tasks[blockIdx.x];
   const int K = d.clq_size[k];
+  const int KK = K * K;
   const int64_t s0 = d.clq_slot[k];
   const double* eg = ap.eig + ap.eig_off[k];
   const int tid = threadIdx.x;
   const int nslot = K * (K + 1) / 2;
-  for (int idx = tid; idx < K * K; idx += NT) Vs[idx] = eg[idx];
-  for (int l = tid; l < K; l += NT) lam[l] = eg[K * K + l];
+  for (int idx = tid; idx < KK; idx += NT) Vs[idx] = eg[idx];
+  for (int l = tid; l < K; l += NT) lam[l] = eg[KK + l];
   // D = smat(2 q_s - mu_s) into M (full symmetric)
   for (int t = tid; t < nslot; t += NT) {
     int a, bq;
@@ -269,48 +273,75 @@ __global__ __launch_bounds__(NT) void k_adj_cone(AdjPlan ap, const int32_t* task
     M[bq * K + a] = dv;
   }
   __syncthreads();
-  // T = D V ; M = V^T T
-  for (int idx = tid; idx < K * K; idx += NT) {
-    const int i = idx / K, l = idx - (idx / K) * K;
+  double r[NO];
+  // T = D V
+#pragma unroll
+  for (int u = 0; u < NO; ++u) {
+    const int idx = tid + u * NT;
     double acc = 0.0;
-    for (int j = 0; j < K; ++j) acc += M[i * K + j] * Vs[j * K + l];
-    T[idx] = acc;
+    if (idx < KK) {
+      const int i = idx / K, l = idx - (idx / K) * K;
+      for (int j = 0; j < K; ++j) acc += M[i * K + j] * Vs[j * K + l];
+    }
+    r[u] = acc;
   }
   __syncthreads();
-  for (int idx = tid; idx < K * K; idx += NT) {
-    const int p = idx / K, l = idx - (idx / K) * K;
+#pragma unroll
+  for (int u = 0; u < NO; ++u)
+    if (tid + u * NT < KK) M[tid + u * NT] = r[u];
+  __syncthreads();
+  // B o (V^T T), B the divided differences of max(lambda, 0)
+#pragma unroll
+  for (int u = 0; u < NO; ++u) {
+    const int idx = tid + u * NT;
     double acc = 0.0;
-    for (int i = 0; i < K; ++i) acc += Vs[i * K + p] * T[i * K + l];
-    // divided differences of max(lambda, 0)
-    const double lp = lam[p], ll = lam[l];
-    double bw;
-    if (lp > 0.0 && ll > 0.0) bw = 1.0;
-    else if (lp <= 0.0 && ll <= 0.0) bw = 0.0;
-    else bw = (fmax(lp, 0.0) - fmax(ll, 0.0)) / (lp - ll);
-    M[idx] = bw * acc;
+    if (idx < KK) {
+      const int p = idx / K, l = idx - (idx / K) * K;
+      for (int i = 0; i < K; ++i) acc += Vs[i * K + p] * M[i * K + l];
+      const double lp = lam[p], ll = lam[l];
+      double bw;
+      if (lp > 0.0 && ll > 0.0) bw = 1.0;
+      else if (lp <= 0.0 && ll <= 0.0) bw = 0.0;
+      else bw = (fmax(lp, 0.0) - fmax(ll, 0.0)) / (lp - ll);
+      acc *= bw;
+    }
+    r[u] = acc;
   }
   __syncthreads();
-  // T = M V^T ; result = V T
-  for (int idx = tid; idx < K * K; idx += NT) {
-    const int p = idx / K, j = idx - (idx / K) * K;
+#pragma unroll
+  for (int u = 0; u < NO; ++u)
+    if (tid + u * NT < KK) M[tid + u * NT] = r[u];
+  __syncthreads();
+  // T = (B o ...) V^T
+#pragma unroll
+  for (int u = 0; u < NO; ++u) {
+    const int idx = tid + u * NT;
     double acc = 0.0;
-    for (int l = 0; l < K; ++l) acc += M[p * K + l] * Vs[j * K + l];
-    T[idx] = acc;
+    if (idx < KK) {
+      const int p = idx / K, j = idx - (idx / K) * K;
+      for (int l = 0; l < K; ++l) acc += M[p * K + l] * Vs[j * K + l];
+    }
+    r[u] = acc;
   }
   __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NO; ++u)
+    if (tid + u * NT < KK) M[tid + u * NT] = r[u];
+  __syncthreads();
+  // result = V T on the packed slots, and the adjoint update of mu_s, mu_v
   double df = 0.0, nm = 0.0;
   for (int t = tid; t < nslot; t += NT) {
     int a, bq;
     unpack_index(t, K, a, bq);
-    double r = 0.0;
-    for (int p = 0; p < K; ++p) r += Vs[a * K + p] * T[p * K + bq];
-    if (a != bq) r *= kSqrt2;
+    double rr = 0.0;
+    for (int p = 0; p < K; ++p) rr += Vs[a * K + p] * M[p * K + bq];
+    if (a != bq) rr *= kSqrt2;
     const int64_t sl = s0 + t;
     const double hq = ap.qx[d.slot2ent[sl]];
     const double ms = ap.mu_s[sl], mv = ap.mu_v[sl];
     const double qs = 0.5 * (ms + mv + hq);
     const double qv = 0.5 * (mv - ms + hq);
-    const double ns = ms - qs + r;
+    const double ns = ms - qs + rr;
     ap.mu_s[sl] = ns;
     ap.mu_v[sl] = qv;
     df += (ns - ms) * (ns - ms) + (qv - mv) * (qv - mv);
@@ -530,10 +561,11 @@ void launch_adj_eig(const AdjPlan& ap, const int32_t* tasks, int32_t ntask, int 
   if (ntask <= 0) return;
   if (kmax <= 16) hipLaunchKernelGGL((k_adj_eig<16, 64>), dim3(ntask), dim3(64), 0, st, ap, tasks);
   else if (kmax <= 32) hipLaunchKernelGGL((k_adj_eig<32, 128>), dim3(ntask), dim3(128), 0, st, ap, tasks);
-  else hipLaunchKernelGGL((k_adj_eig<64, 256>), dim3(ntask), dim3(256), 0, st, ap, tasks);
+  else if (kmax <= 64) hipLaunchKernelGGL((k_adj_eig<64, 256>), dim3(ntask), dim3(256), 0, st, ap, tasks);
+  else hipLaunchKernelGGL((k_adj_eig<96, 512>), dim3(ntask), dim3(512), 0, st, ap, tasks);
 }
 
-// tasks[0..2]: clique lists for K <= 16, <= 32, <= 64
+// tasks[0..3]: clique lists for K <= 16, <= 32, <= 64, <= 96
 void launch_adj_iteration(const AdjPlan& ap, const int32_t* const* tasks, const int32_t* ntasks,
                           int final_pass, int use_g, hipStream_t st) {
   const DevPlan& d = ap.d;
@@ -548,6 +580,7 @@ void launch_adj_iteration(const AdjPlan& ap, const int32_t* const* tasks, const 
   if (ntasks[0]) hipLaunchKernelGGL((k_adj_cone<16, 64>), dim3(ntasks[0]), dim3(64), 0, st, ap, tasks[0]);
   if (ntasks[1]) hipLaunchKernelGGL((k_adj_cone<32, 128>), dim3(ntasks[1]), dim3(128), 0, st, ap, tasks[1]);
   if (ntasks[2]) hipLaunchKernelGGL((k_adj_cone<64, 256>), dim3(ntasks[2]), dim3(256), 0, st, ap, tasks[2]);
+  if (ntasks[3]) hipLaunchKernelGGL((k_adj_cone<96, 512>), dim3(ntasks[3]), dim3(512), 0, st, ap, tasks[3]);
   hipLaunchKernelGGL(k_adj_s2, dim3(d.B), dim3(64), 0, st, ap, use_g);
 }
 

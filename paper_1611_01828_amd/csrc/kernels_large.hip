@@ -30,6 +30,12 @@ namespace {
 constexpr int kLT = 1024;        // threads of the per-task kernels
 constexpr int kTT = 512;         // threads of the tridiagonalisation kernel
 constexpr int kNB = 32;          // panel width of the tridiagonalisation
+constexpr int kBand = 8;         // bandwidth of the two-stage reduction's first stage
+constexpr int kBandRefl = 8;     // doubles per stored bulge-chasing reflector: tau, v_1..v_7
+constexpr int kQ2Sweeps = 8;     // sweeps of reflectors staged per LDS chunk of the back-transformation
+// bulge-chasing steps per sweep (the first sweep's count; the stride of the
+// reflector array)
+__host__ __device__ __forceinline__ int band_nk(int K) { return (K + 6) / kBand; }
 constexpr int kTile = 32;        // reconstruction tile
 constexpr double kEps = 2.220446049250313e-16;
 constexpr double kSqrt2 = 1.4142135623730951;
@@ -52,6 +58,7 @@ struct Ws {
   double* zs;    // ld    scale of each eigenvector column of Z (1 / its norm)
   double* meta;  // 16    [0] r, [1] 1 = positive side, [2] first, [3] pivmin, [4] ||T||
   double* tiles; // 2 * ntiles partial sums
+  double* refl;  // band_refl_size(K): reflectors of the band-to-tridiagonal stage
 };
 
 __device__ __forceinline__ int lead_dim(int K) { return (K + 7) & ~7; }
@@ -70,6 +77,8 @@ __device__ __forceinline__ Ws ws_of(double* base, int K) {
   w.zs = w.lam + ld;
   w.meta = w.zs + ld;
   w.tiles = w.meta + 16;
+  const int T = (K + 31) / 32;
+  w.refl = w.tiles + T * (T + 1) + 64;
   return w;
 }
 
@@ -96,6 +105,7 @@ struct LargeArgs {
   double* work;
   const int64_t* woff;        // per task
   const int32_t* tsize;       // per task: order K of its block
+  int band_min;               // tasks of at least this order take the two-stage reduction
 };
 
 template <bool ADMM>
@@ -264,7 +274,7 @@ __global__ __launch_bounds__(256, 4) void k_trd_symv(LargeArgs a, int p, int i, 
   __shared__ double part[4];
   const int K = a.tsize[blockIdx.x];
   int j, nb;
-  if (!trd_col(K, p, i, j, nb)) return;
+  if (K >= a.band_min || !trd_col(K, p, i, j, nb)) return;
   const int ld = lead_dim(K);
   const int ncol = K - j - 1, nall = ncol + 2 * i;
   const int cb = blockIdx.y % ncy, rb = blockIdx.y / ncy;
@@ -388,7 +398,7 @@ __global__ __launch_bounds__(256) void k_trd_update(LargeArgs a, int p, int i) {
   __shared__ double py[4][kUpdRows], pv[4][kUpdRows];
   const int K = a.tsize[blockIdx.x];
   int j, nb;
-  if (!trd_col(K, p, i, j, nb)) return;
+  if (K >= a.band_min || !trd_col(K, p, i, j, nb)) return;
   const int ld = lead_dim(K);
   if (blockIdx.y * kUpdRows >= ld) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
@@ -509,7 +519,7 @@ __global__ __launch_bounds__(kTT) void k_trd_trail(LargeArgs a, int p) {
   double(*pc_w)[64] = reinterpret_cast<double(*)[64]>(stage + 2 * kNB * 128 + kNB * 64);
   const int K = a.tsize[blockIdx.x];
   const int j0 = p * kNB;
-  if (j0 >= trd_tail_start(K)) return;
+  if (K >= a.band_min || j0 >= trd_tail_start(K)) return;
   const int nb = kNB;
   const int jn = j0 + nb, n2 = K - jn;
   const int ntr = (n2 + 127) / 128, ntc = (n2 + 63) / 64;
@@ -597,6 +607,7 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
   __shared__ double vb[kTail], wb[kTail], ph[kTailG][kTail];
   __shared__ double red[4];
   const int K = a.tsize[blockIdx.x];
+  if (K >= a.band_min) return;   // tridiagonal after the two-stage reduction
   const int j0 = trd_tail_start(K), n = K - j0;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const int ld = lead_dim(K);
@@ -706,6 +717,689 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
     w.e[K - 1] = 0.0;
     w.tau[K - 2] = 0.0;
     w.tau[K - 1] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2'. Two-stage tridiagonalisation for cliques of at least band_min vertices
+//    (successive band reduction: Bischof, Lang & Sun; the bulge chasing of
+//    Schwarz's and Lang's band-to-tridiagonal algorithms):
+//    stage 1 reduces Y to a band of width kBand.  Panel p (columns
+//    j0 = 8p .. j0 + 7) takes the Householder QR of A(j0+8:K, j0:j0+8), then
+//    the two-sided update A22 <- Q^T A22 Q of the trailing matrix with
+//    Q = I - V T V^T: X = A22 V T, Y = X - 1/2 V T^T V^T X, A22 -= V Y^T +
+//    Y V^T.  Column c keeps the band on rows c..c+8 and its reflector below
+//    (1 on row c + 8, implicit), tau[c].  Stage 2 reduces the band to
+//    tridiagonal form in LDS: sweep s annihilates column s below the
+//    subdiagonal with a reflector on rows s+1..s+8, which fills a block
+//    kBand rows further down; each further step annihilates the first column
+//    of that bulge with a reflector on its rows and moves the fill another
+//    kBand rows down.  The trailing matrix is read once per panel of kBand
+//    columns (the one-stage reduction reads it once per column).
+//    Launches per panel: k_band_panel (one workgroup per task: Y of the
+//    previous panel, the panel's columns brought up to date, its QR, T and
+//    U = V T) and k_band_trail (many workgroups: the previous panel's
+//    trailing update fused with A22 U of this panel); then k_band_chase.
+// ---------------------------------------------------------------------------
+constexpr int kBandT = 256;                 // threads of the panel kernel (one wave per SIMD)
+constexpr int kBandRows = 1024 / kBandT;    // rows per thread of the panel kernel
+constexpr int kBandTile = 128;              // rows and columns of a trailing-update tile
+constexpr int kBandXT = (1024 + kBandTile - 1) / kBandTile;   // column tiles
+constexpr int kChaseWaves = 8;              // waves of the bulge chasing (8 sweeps each)
+constexpr int kChaseLd = 1032;              // LDS stride of a stored diagonal: K + 7 columns, zero past K
+constexpr int kChaseSpin = 1 << 22;         // bound on a wave's wait for the previous sweep
+
+// panels of a task: panel p is reduced while its QR block has two rows or more
+__host__ __device__ __forceinline__ int band_panels(int K) { return (K - 9 + kBand - 1) / kBand; }
+
+// (pointers computed from the parity rather than picked from an array, which
+// would put the structure in scratch memory)
+struct BandBufs {
+  double* S;
+  int ld;
+  // ld x kBand, row-major: explicit reflectors of the panels of parity par
+  __device__ double* V(int par) const { return S + (size_t)par * kBand * ld; }
+  __device__ double* U() const { return S + (size_t)2 * kBand * ld; }   // V T of the current panel
+  __device__ double* Y() const { return S + (size_t)3 * kBand * ld; }   // Y of the previous panel
+  // kBand x kBand (row-major) per parity
+  __device__ double* T(int par) const { return S + (size_t)4 * kBand * ld + par * kBand * kBand; }
+  // per column tile, ld x kBand: partial sums of A22 U of the current panel
+  __device__ double* X() const { return S + (size_t)4 * kBand * ld + 2 * kBand * kBand; }
+};
+
+__device__ __forceinline__ BandBufs band_bufs(const Ws& w, int ld) { return BandBufs{w.S, ld}; }
+
+// per-lane values m[0..31] summed over the wave by recursive halving (32
+// exchanges): lane L returns the total of value L & 31
+template <int H>
+__device__ __forceinline__ void halve_step(double (&m)[32], int lane) {
+  const bool up = (lane & H) != 0;
+#pragma unroll
+  for (int q = 0; q < H; ++q) {
+    const double send = up ? m[q] : m[q + H];
+    const double keep = up ? m[q + H] : m[q];
+    m[q] = keep + __shfl_xor(send, H, 64);
+  }
+}
+__device__ __forceinline__ double wave_reduce_scatter32(double (&m)[32], int lane) {
+  halve_step<16>(m, lane);
+  halve_step<8>(m, lane);
+  halve_step<4>(m, lane);
+  halve_step<2>(m, lane);
+  halve_step<1>(m, lane);
+  return m[0] + __shfl_xor(m[0], 32, 64);
+}
+
+// (A^T B)(i, j) = sum over the block's rows of A(r, i) B(r, j) for the
+// kBandRows x kBand row slices A, B of every thread, into out[64] (LDS,
+// row-major); big: LDS scratch of kBandT doubles
+__device__ __forceinline__ void band_gram(const double (&A)[kBandRows][kBand], const double (&B)[kBandRows][kBand],
+                                          double (*big)[64], double* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int hf = 0; hf < 2; ++hf) {
+    double m[32];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int jx = 0; jx < kBand; ++jx) {
+        double t = 0.0;
+#pragma unroll
+        for (int u = 0; u < kBandRows; ++u) t += A[u][4 * hf + i] * B[u][jx];
+        m[i * kBand + jx] = t;
+      }
+    const double v = wave_reduce_scatter32(m, lane);
+    if (lane < 32) big[wid][32 * hf + lane] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBandT / 64; ++q) t += big[q][threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+}
+
+// x of another lane through a DPP exchange (CTRL: the DPP control word)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+// sum over the wave: DPP exchanges inside each row of 16 lanes (xor 1,
+// xor 2, half-row mirror, row mirror), then the four row sums read from
+// lanes 0, 16, 32 and 48 (every lane gets the total)
+__device__ __forceinline__ double wave_sum_dpp(double x) {
+  x += dpp_f64<0xB1>(x);
+  x += dpp_f64<0x4E>(x);
+  x += dpp_f64<0x141>(x);
+  x += dpp_f64<0x140>(x);
+  return (readlane_f64(x, 0) + readlane_f64(x, 16)) + (readlane_f64(x, 32) + readlane_f64(x, 48));
+}
+
+// block sums of NV values over kBandT threads (buf: one of two alternating
+// buffers, so that consecutive sums need one barrier each)
+template <int NV>
+__device__ __forceinline__ void band_block_sum(double (&v)[NV], double (*buf)[kBand]) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum_dpp(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) buf[wid][k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBandT / 64; ++q) t += buf[q][k];
+    v[k] = t;
+  }
+}
+
+template <bool ADMM>
+__global__ __launch_bounds__(kBandT) void k_band_panel(LargeArgs a, int p) {
+  static_assert(kBand == 8 && kBandT * kBandRows == 1024 && kBandT > 8 + kBand, "panel layout");
+  __shared__ double red[2][kBandT / 64][kBand];
+  __shared__ double big[kBandT / 64][64];
+  __shared__ double sm[64], st[64], cv[kBand][kBand], cy[kBand][kBand];
+  __shared__ double piv[2][kBand], taus[kBand];
+  const int K = a.tsize[blockIdx.x];
+  if (K < a.band_min) return;
+  const int np = band_panels(K);
+  if (p > np) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int ld = lead_dim(K);
+  const BandBufs bb = band_bufs(w, ld);
+  double* W = w.W;
+  const int tid = threadIdx.x;
+  const int j0 = p * kBand, r0 = j0 + kBand;
+  const int nc = min(kBand, K - j0);
+  int nred = 0;
+  // the panel's columns on rows j0 + tid + kBandT u, in registers (clamped
+  // loads); loaded after the work on panel p - 1's Y, which does not need them
+  double P[kBandRows][kBand];
+  auto load_panel = [&]() {
+#pragma unroll
+    for (int u = 0; u < kBandRows; ++u)
+#pragma unroll
+      for (int l = 0; l < kBand; ++l)
+        P[u][l] = W[(size_t)(j0 + min(l, nc - 1)) * ld + min(j0 + tid + kBandT * u, K - 1)];
+  };
+  if (p == 0) load_panel();
+  if (p > 0) {
+    // (a) Y of panel p - 1 on rows [j0, K): X = A22 U (the column-tile
+    //     partials of k_band_trail summed), M = V^T X, Y = X - 1/2 V (T^T M)
+    const double* Vq = bb.V((p + 1) & 1);
+    const double* Tq = bb.T((p + 1) & 1);
+    // (the partials of two column tiles loaded at a time, each batch issued
+    // together)
+    const int nct = (K - j0 + kBandTile - 1) / kBandTile;
+    double X[kBandRows][kBand], Vr[kBandRows][kBand];
+#pragma unroll
+    for (int u = 0; u < kBandRows; ++u) {
+      const int r = j0 + tid + kBandT * u;
+      const bool ok = r < K;
+      const int rc = min(r, K - 1);
+#pragma unroll
+      for (int l = 0; l < kBand; ++l) {
+        Vr[u][l] = ok ? Vq[(size_t)rc * kBand + l] : 0.0;
+        X[u][l] = 0.0;
+      }
+      for (int h = 0; h < nct; h += 2) {
+        double xp[2][kBand];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int l = 0; l < kBand; ++l) xp[ct][l] = bb.X()[((size_t)min(h + ct, nct - 1) * ld + rc) * kBand + l];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int l = 0; l < kBand; ++l) X[u][l] += (ok && h + ct < nct) ? xp[ct][l] : 0.0;
+      }
+    }
+    band_gram(Vr, X, big, sm);   // M = V^T X
+    __syncthreads();
+    if (tid < 64) {
+      const int i = tid >> 3, jx = tid & 7;   // (T^T M)(i, jx)
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < kBand; ++k) t += Tq[k * kBand + i] * sm[k * kBand + jx];
+      st[tid] = t;
+    }
+    __syncthreads();
+    // (the empty asm statements keep the compiler from loading all of an
+    // 8 x 8 LDS matrix into registers at once)
+#pragma unroll
+    for (int l = 0; l < kBand; ++l) {
+      double sl[kBand];
+#pragma unroll
+      for (int i = 0; i < kBand; ++i) sl[i] = st[i * kBand + l];
+#pragma unroll
+      for (int u = 0; u < kBandRows; ++u) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < kBand; ++i) t += Vr[u][i] * sl[i];
+        X[u][l] -= 0.5 * t;   // now Y
+      }
+      asm volatile("" ::: "memory");
+    }
+#pragma unroll
+    for (int u = 0; u < kBandRows; ++u) {
+      const int r = j0 + tid + kBandT * u;
+      if (r < K)
+#pragma unroll
+        for (int l = 0; l < kBand; ++l) bb.Y()[(size_t)r * kBand + l] = X[u][l];
+    }
+    // (b) the panel's columns (rows [j0, K)) brought up to date with panel
+    //     p - 1: A(:, c) -= V Y(c, :)^T + Y V(c, :)^T
+    load_panel();
+    if (tid < kBand)
+#pragma unroll
+      for (int l = 0; l < kBand; ++l) {
+        cv[tid][l] = Vr[0][l];
+        cy[tid][l] = X[0][l];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kBand; ++c) {
+      double yc[kBand], vc[kBand];
+#pragma unroll
+      for (int l = 0; l < kBand; ++l) {
+        yc[l] = cy[c][l];
+        vc[l] = cv[c][l];
+      }
+#pragma unroll
+      for (int u = 0; u < kBandRows; ++u) {
+        double t = 0.0;
+#pragma unroll
+        for (int l = 0; l < kBand; ++l) t += Vr[u][l] * yc[l] + X[u][l] * vc[l];
+        P[u][c] -= t;
+      }
+      asm volatile("" ::: "memory");
+    }
+  }
+  if (p == np) {
+    // the last columns (at most 9 rows): band entries, no reflector
+#pragma unroll
+    for (int u = 0; u < kBandRows; ++u) {
+      const int r = j0 + tid + kBandT * u;
+      if (r < K)
+#pragma unroll
+        for (int l = 0; l < kBand; ++l)
+          if (l < nc) W[(size_t)(j0 + l) * ld + r] = P[u][l];
+    }
+    if (tid < K - j0) w.tau[j0 + tid] = 0.0;
+    return;
+  }
+  // (c) Householder QR of rows [r0, K) of the panel (rows [j0, r0) are its
+  //     diagonal block, kept as they are); P(r, l) below the pivot then
+  //     holds the Householder vector, R above.  One block sum per column:
+  //     ss = sum_{t > rl} P(t, l)^2 and g_m = sum_{t > rl} P(t, l) P(t, m)
+  //     (m > l), the pivot row broadcast beside it; v = (1, P(t, l) scale)
+  //     then gives v^T P(:, m) = P(rl, m) + scale g_m.
+#pragma unroll
+  for (int l = 0; l < kBand; ++l) {
+    const int rl = r0 + l;   // pivot row: thread kBand + l, u = 0
+    if (rl >= K) {
+      if (tid == 0) taus[l] = 0.0;
+      continue;
+    }
+    double sg[kBand];
+#pragma unroll
+    for (int mm = 0; mm < kBand; ++mm) sg[mm] = 0.0;
+#pragma unroll
+    for (int u = 0; u < kBandRows; ++u) {
+      const int r = j0 + tid + kBandT * u;
+      const double x = (r > rl && r < K) ? P[u][l] : 0.0;
+#pragma unroll
+      for (int mm = l; mm < kBand; ++mm) sg[mm] += x * P[u][mm];
+    }
+    double* pv = piv[l & 1];
+    if (tid == kBand + l)
+#pragma unroll
+      for (int mm = 0; mm < kBand; ++mm) pv[mm] = P[0][mm];
+    band_block_sum<kBand>(sg, red[nred++ & 1]);
+    const double alpha = pv[l];
+    double beta, tu, scale;
+    if (sg[l] == 0.0) {
+      beta = alpha;
+      tu = 0.0;
+      scale = 0.0;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + sg[l]), alpha);
+      tu = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    double wv[kBand];
+#pragma unroll
+    for (int mm = l + 1; mm < kBand; ++mm) wv[mm] = pv[mm] + scale * sg[mm];
+#pragma unroll
+    for (int u = 0; u < kBandRows; ++u) {
+      const int r = j0 + tid + kBandT * u;
+      const double vl = (r == rl) ? 1.0 : ((r > rl && r < K) ? P[u][l] * scale : 0.0);
+#pragma unroll
+      for (int mm = l + 1; mm < kBand; ++mm) P[u][mm] -= tu * vl * wv[mm];
+      P[u][l] = (r == rl) ? beta : ((r > rl) ? vl : P[u][l]);
+    }
+    if (tid == 0) taus[l] = tu;
+  }
+  // (d) write back the diagonal block, R and the Householder vectors; the
+  //     explicit V (1 on the pivot, zero above); tau
+  double V[kBandRows][kBand];
+#pragma unroll
+  for (int u = 0; u < kBandRows; ++u) {
+    const int r = j0 + tid + kBandT * u;
+#pragma unroll
+    for (int l = 0; l < kBand; ++l) {
+      V[u][l] = (r == r0 + l) ? 1.0 : ((r > r0 + l && r < K) ? P[u][l] : 0.0);
+      if (r < K) W[(size_t)(j0 + l) * ld + r] = P[u][l];
+    }
+    if (r >= r0 && r < K)
+#pragma unroll
+      for (int l = 0; l < kBand; ++l) bb.V(p & 1)[(size_t)r * kBand + l] = V[u][l];
+  }
+  // (e) T (forward, columnwise: T(k, i) = -tau_i sum_{k <= m < i} T(k, m)
+  //     (V^T V)(m, i)) and U = V T
+  __syncthreads();   // taus
+  band_gram(V, V, big, sm);   // V^T V
+  if (tid < kBand) w.tau[j0 + tid] = taus[tid];
+  __syncthreads();
+  if (tid < kBand) {
+    const int k = tid;
+    double tr[kBand];
+#pragma unroll
+    for (int i = 0; i < kBand; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < kBand; ++mm)
+        if (mm >= k && mm < i) t += tr[mm] * sm[mm * kBand + i];
+      tr[i] = (i < k) ? 0.0 : ((i == k) ? taus[i] : -taus[i] * t);
+    }
+#pragma unroll
+    for (int i = 0; i < kBand; ++i) {
+      st[k * kBand + i] = tr[i];
+      bb.T(p & 1)[k * kBand + i] = tr[i];
+    }
+  }
+  __syncthreads();
+  double Ur[kBandRows][kBand];
+#pragma unroll
+  for (int l = 0; l < kBand; ++l) {
+    double sl[kBand];
+#pragma unroll
+    for (int k = 0; k < kBand; ++k) sl[k] = st[k * kBand + l];
+#pragma unroll
+    for (int u = 0; u < kBandRows; ++u) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < kBand; ++k) t += V[u][k] * sl[k];
+      Ur[u][l] = t;
+    }
+    asm volatile("" ::: "memory");
+  }
+#pragma unroll
+  for (int u = 0; u < kBandRows; ++u) {
+    const int r = j0 + tid + kBandT * u;
+    if (r >= r0 && r < K)
+#pragma unroll
+      for (int l = 0; l < kBand; ++l) bb.U()[(size_t)r * kBand + l] = Ur[u][l];
+  }
+}
+
+// A22 -= V Y^T + Y V^T of panel p - 1 (p > 0) and the partial sums of
+// X = A22 U of panel p (p < np) on a 128 x 128 tile of the trailing matrix
+// [8p + 8, K)^2 (both triangles).  Thread (row, quarter) takes 32 columns:
+// all its loads are issued before any store (stores count against the same
+// vector-memory counter as loads, so a load behind a store waits for it).
+// X partials: one ld x kBand array per column tile.
+constexpr int kTrailT = 512;
+constexpr int kTrailQ = kTrailT / kBandTile;          // column groups
+constexpr int kTrailC = kBandTile / kTrailQ;          // columns per thread
+template <bool ADMM>
+__global__ __launch_bounds__(kTrailT) void k_band_trail(LargeArgs a, int p) {
+  __shared__ double cs[kBandTile][3 * kBand];   // V, Y, U of the tile's columns
+  __shared__ double xh[kTrailQ - 1][kBandTile][kBand];
+  const int K = a.tsize[blockIdx.x];
+  if (K < a.band_min) return;
+  const int np = band_panels(K);
+  if (p > np) return;
+  const int R0 = p * kBand + kBand, n = K - R0;
+  if (n <= 0) return;
+  const int nt = (n + kBandTile - 1) / kBandTile;
+  if ((int)blockIdx.y >= nt * nt) return;
+  const int tr = blockIdx.y % nt, tc = blockIdx.y / nt;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int ld = lead_dim(K);
+  const BandBufs bb = band_bufs(w, ld);
+  double* W = w.W;
+  const bool upd = p > 0, sym = p < np;
+  const int vpar = (p + 1) & 1;   // V of panel p - 1
+  const int tid = threadIdx.x;
+  const int cb0 = R0 + tc * kBandTile;
+  const int rl = tid & (kBandTile - 1), qt = tid / kBandTile;
+  const int r = R0 + tr * kBandTile + rl;
+  const int rc = min(r, K - 1);
+  const int cs0 = qt * kTrailC;                       // first tile column of this thread
+  // the thread's 32 entries (clamped addresses), issued first
+  double x[kTrailC];
+#pragma unroll
+  for (int j = 0; j < kTrailC; ++j) x[j] = W[(size_t)min(cb0 + cs0 + j, K - 1) * ld + rc];
+  // column operands (offset arithmetic: V, U, Y are kBand ld-row arrays at
+  // slots vpar, 2 and 3 of the workspace)
+  for (int idx = tid; idx < kBandTile * 3 * kBand; idx += kTrailT) {
+    const int cc = idx / (3 * kBand), f = idx - cc * (3 * kBand), c = min(cb0 + cc, K - 1);
+    const int sel = (f < kBand) ? vpar : ((f < 2 * kBand) ? 3 : 2);
+    const bool on = (f < 2 * kBand) ? upd : sym;
+    cs[cc][f] = on ? bb.S[(size_t)sel * kBand * ld + (size_t)c * kBand + (f & (kBand - 1))] : 0.0;
+  }
+  double vr[kBand], yr[kBand], acc[kBand];
+#pragma unroll
+  for (int l = 0; l < kBand; ++l) {
+    vr[l] = upd ? bb.V(vpar)[(size_t)rc * kBand + l] : 0.0;
+    yr[l] = upd ? bb.Y()[(size_t)rc * kBand + l] : 0.0;
+    acc[l] = 0.0;
+  }
+  __syncthreads();
+  const int ncc = min(kTrailC, K - (cb0 + cs0));       // valid columns (may be <= 0)
+  // (the empty asm statements keep the compiler from loading every
+  // column's LDS operands into registers at once)
+  if (upd) {
+#pragma unroll
+    for (int j = 0; j < kTrailC; ++j) {
+      double t = x[j];
+#pragma unroll
+      for (int l = 0; l < kBand; ++l) t -= vr[l] * cs[cs0 + j][kBand + l] + yr[l] * cs[cs0 + j][l];
+      x[j] = t;
+      asm volatile("" ::: "memory");
+    }
+    if (r < K)
+#pragma unroll
+      for (int j = 0; j < kTrailC; ++j)
+        if (j < ncc) W[(size_t)(cb0 + cs0 + j) * ld + r] = x[j];
+  }
+  if (sym) {
+#pragma unroll
+    for (int j = 0; j < kTrailC; ++j) {
+      const double t = (j < ncc) ? x[j] : 0.0;
+      double u8[kBand];
+#pragma unroll
+      for (int l = 0; l < kBand; ++l) u8[l] = cs[cs0 + j][2 * kBand + l];
+#pragma unroll
+      for (int l = 0; l < kBand; ++l) acc[l] += t * u8[l];
+      asm volatile("" ::: "memory");
+    }
+    if (qt > 0)
+#pragma unroll
+      for (int l = 0; l < kBand; ++l) xh[qt - 1][rl][l] = acc[l];
+    __syncthreads();
+    if (qt == 0 && r < K)
+#pragma unroll
+      for (int l = 0; l < kBand; ++l) {
+        double t = acc[l];
+#pragma unroll
+        for (int g = 0; g < kTrailQ - 1; ++g) t += xh[g][rl][l];
+        bb.X()[((size_t)tc * ld + r) * kBand + l] = t;
+      }
+  }
+}
+
+// Stage 2: the band (diagonals 0..kBand of W) to tridiagonal form in LDS,
+// one workgroup per task.  Stored diagonals: L[d][j] = B(j + d, j),
+// d < 2 kBand (a bulge reaches 2 kBand - 1 below the diagonal); entries
+// past the matrix are zero and stay zero (a step's rows and columns past K
+// hold zeros in and out), so the steps need no bounds tests.  Step k of
+// sweep s reads and writes C = B(r:r+8, r-8:r) and D = B(r:r+8, r:r+8),
+// r = s + 1 + 8k: it must follow step k + 1 of sweep s - 1 (whose C
+// overlaps D) and is disjoint from step k + 2 of sweep s - 1, so sweep s
+// runs two steps behind sweep s - 1.
+// An 8-lane group runs one sweep, lane i holding row i of the step's 8 x 8
+// blocks (sums over a block's rows are 3 DPP exchanges, sums along a row
+// stay in the lane).  A wave runs 8 consecutive sweeps in lockstep, group g
+// 2 steps behind group g - 1 (wave step t is step t - 2 g of sweep base +
+// g), which is the order the dependence needs; the first group waits on the
+// previous wave's last sweep through an LDS progress flag
+// (sweep * 256 + steps done, + 255 when the sweep ends).
+constexpr int kChaseG = 8;                   // sweeps per wave
+
+// sum over the lane's aligned group of 8 (every lane gets it)
+__device__ __forceinline__ double sum8(double x) {
+  x += dpp_f64<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  x += dpp_f64<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  x += dpp_f64<0x141>(x);   // row_half_mirror: lane j <-> 7 - j of the group
+  return x;
+}
+// out[j] = x of lane j of the lane's group of 8
+__device__ __forceinline__ void gather8(double x, double (&out)[kBand], bool upper) {
+  const double y0 = dpp_f64<0x00>(x), y1 = dpp_f64<0x55>(x), y2 = dpp_f64<0xAA>(x), y3 = dpp_f64<0xFF>(x);
+  const double z0 = dpp_f64<0x141>(y0), z1 = dpp_f64<0x141>(y1), z2 = dpp_f64<0x141>(y2), z3 = dpp_f64<0x141>(y3);
+  out[0] = upper ? z0 : y0;
+  out[1] = upper ? z1 : y1;
+  out[2] = upper ? z2 : y2;
+  out[3] = upper ? z3 : y3;
+  out[4] = upper ? y0 : z0;
+  out[5] = upper ? y1 : z1;
+  out[6] = upper ? y2 : z2;
+  out[7] = upper ? y3 : z3;
+}
+
+template <bool ADMM>
+__global__ __launch_bounds__(64 * kChaseWaves) void k_band_chase(LargeArgs a) {
+  static_assert(kBand == 8 && kChaseG == 8, "one 8-lane group per sweep, 8 x 8 blocks");
+  __shared__ double L[2 * kBand * kChaseLd];
+  __shared__ int prog[kChaseWaves];
+  const int K = a.tsize[blockIdx.x];
+  if (K < a.band_min) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int ld = lead_dim(K);
+  const double* W = w.W;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int idx = tid; idx < 2 * kBand * kChaseLd; idx += 64 * kChaseWaves) {
+    const int j = idx / (2 * kBand), d = idx - j * (2 * kBand);
+    double x = 0.0;
+    if (d <= kBand && j + d < K) x = W[(size_t)j * ld + j + d];
+    L[d * kChaseLd + j] = x;
+  }
+  if (tid < kChaseWaves) prog[tid] = -1;
+  __syncthreads();
+  const int g = lane >> 3, i = lane & 7;
+  const bool upper = (i & 4) != 0;
+  const int NK = band_nk(K);
+  const int pw = (wv + kChaseWaves - 1) % kChaseWaves;
+  // Progress flags order LDS data only: a wave publishes after its LDS
+  // accesses have completed (s_waitcnt lgkmcnt(0), not waiting for its
+  // global stores of reflectors, which only later kernels read), and a
+  // waiting wave reads the flag with a volatile load before its data loads
+  // (LDS requests are served in order).
+  volatile int* vprog = prog;
+  bool fail = false;
+  auto house = [](double alpha, double ss, double& beta, double& tu, double& scale) {
+    if (ss == 0.0) {
+      beta = alpha;
+      tu = 0.0;
+      scale = 0.0;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+      tu = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+  };
+  for (int base = wv * kChaseG; base < K - 2; base += kChaseWaves * kChaseG) {
+    const int s = base + g;
+    const int nst = (s < K - 2) ? (K - 1 - s + kBand - 1) / kBand : 0;   // steps of sweep s
+    const int nst0 = (K - 1 - base + kBand - 1) / kBand;
+    const int T = 2 * (kChaseG - 1) + nst0;                             // wave steps (group 0 is longest)
+    double pv[kBand], ptu = 0.0;
+#pragma unroll
+    for (int q = 0; q < kBand; ++q) pv[q] = 0.0;
+    for (int t = 0; t < T; ++t) {
+      // group 0 (sweep base) may run step t once sweep base - 1 (the
+      // previous wave's last group) has completed step t + 1
+      if (base > 0 && !fail && t < nst0) {
+        const int need = (base - 1) * 256 + min(t + 2, 255);
+        int it = 0;
+        while (vprog[pw] < need) {
+          if (++it > kChaseSpin) {
+            fail = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        asm volatile("" ::: "memory");
+      }
+      const int k = t - 2 * g;
+      if (k >= 0 && k < nst) {
+        // rows r.. of the block the step annihilates and reduces; column
+        // block pr0.. of the previous reflector (step 0: column s itself)
+        const int pr0 = (k == 0) ? s : s + 1 + kBand * (k - 1);
+        const int r = s + 1 + kBand * k;
+        // C = B(r:r+8, pr0:pr0+8) (step 0: column s only), row i;
+        // D = B(r:r+8, r:r+8), row i
+        double c[kBand], dr[kBand];
+#pragma unroll
+        for (int jj = 0; jj < kBand; ++jj) {
+          const int dj = (k > 0) ? jj : 0;   // step 0 reads column s only
+          const double cv = L[(r + i - pr0 - dj) * kChaseLd + pr0 + dj];
+          c[jj] = (k > 0 || jj == 0) ? cv : 0.0;
+          const int hi = max(i, jj), lo = min(i, jj);
+          dr[jj] = L[(hi - lo) * kChaseLd + r + lo];
+        }
+        if (k > 0) {
+          // C <- C H_prev (the fill the previous reflector makes)
+          double t1 = 0.0;
+#pragma unroll
+          for (int jj = 0; jj < kBand; ++jj) t1 += c[jj] * pv[jj];
+#pragma unroll
+          for (int jj = 0; jj < kBand; ++jj) c[jj] -= ptu * t1 * pv[jj];
+        }
+        // the reflector of C's first column: H C(:, 0) = beta e_1
+        const double x = c[0];
+        const double ss = sum8((i >= 1) ? x * x : 0.0);
+        double beta, tu, scale;
+        double alpha;   // x of lane 0 of the group
+        {
+          const double y0 = dpp_f64<0x00>(x), z0 = dpp_f64<0x141>(y0);
+          alpha = upper ? z0 : y0;
+        }
+        house(alpha, ss, beta, tu, scale);
+        const double vi = (i == 0) ? 1.0 : x * scale;
+        double v[kBand];
+        gather8(vi, v, upper);
+        // C <- H C (the first column exactly beta e_1)
+#pragma unroll
+        for (int jj = 1; jj < kBand; ++jj) {
+          const double u = sum8(vi * c[jj]);
+          c[jj] -= tu * vi * u;
+        }
+        c[0] = (i == 0) ? beta : 0.0;
+        if (k > 0) {
+#pragma unroll
+          for (int jj = 0; jj < kBand; ++jj) L[(r + i - pr0 - jj) * kChaseLd + pr0 + jj] = c[jj];
+        } else {
+          L[(r + i - pr0) * kChaseLd + pr0] = c[0];
+        }
+        w.refl[((size_t)s * NK + k) * kBandRefl + i] = (i == 0) ? tu : vi;
+        // D <- H D H: p = tau D v, w = p - tau/2 (p^T v) v, D -= v w^T + w v^T
+        double p = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < kBand; ++jj) p += dr[jj] * v[jj];
+        p *= tu;
+        const double pvs = sum8(p * vi);
+        const double wi = p - 0.5 * tu * pvs * vi;
+        double wa[kBand];
+        gather8(wi, wa, upper);
+#pragma unroll
+        for (int jj = 0; jj < kBand; ++jj) dr[jj] -= vi * wa[jj] + wi * v[jj];
+#pragma unroll
+        for (int jj = 0; jj < kBand; ++jj)
+          if (jj <= i) L[(i - jj) * kChaseLd + r + jj] = dr[jj];
+#pragma unroll
+        for (int q = 0; q < kBand; ++q) pv[q] = v[q];
+        ptu = tu;
+      }
+      // publish the progress of the last group's sweep
+      const int sl = base + kChaseG - 1, kl = t - 2 * (kChaseG - 1) + 1;
+      const int nstl = (K - 1 - sl + kBand - 1) / kBand;
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS accesses done
+      asm volatile("" ::: "memory");
+      if (lane == 0) vprog[wv] = sl * 256 + ((kl >= nstl) ? 255 : max(kl, 0));
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    asm volatile("" ::: "memory");
+    if (lane == 0) vprog[wv] = (base + kChaseG - 1) * 256 + 255;
+  }
+  __syncthreads();
+  if (fail && lane == 0) w.meta[5] = 1.0;
+  for (int j = tid; j < K; j += 64 * kChaseWaves) {
+    w.d[j] = L[j];
+    w.e[j] = (j < K - 1) ? L[kChaseLd + j] : 0.0;
   }
 }
 
@@ -1150,15 +1844,112 @@ __global__ __launch_bounds__(64) void k_eig_cluster(LargeArgs a) {
 //    T(0:i, i) = -tau_i T(0:i, 0:i) V_p(:, 0:i)^T v_i), and
 //    Q Z = B_0 (B_1 (... B_{P-1} Z)).
 // ---------------------------------------------------------------------------
+// Z <- Q2 Z for the tasks of the two-stage reduction, Q2 the product of the
+// bulge-chasing reflectors in the order they were made: sweeps from the last
+// to the first (a sweep's reflectors act on disjoint rows s + 1 + kBand k
+// onwards and commute).  One wave per kQ2C eigenvectors, held in LDS row by
+// row; lane (k, c) applies reflector k (+ 8 per pass) of the sweep to
+// eigenvector c.  The next sweep's reflectors are loaded into registers
+// while the current sweep runs, then stored to the other LDS buffer (one
+// wave: LDS accesses are served in order, no barrier).
+constexpr int kQ2C = 8;
+constexpr int kQ2Pass = 4;   // reflector passes whose loads are issued together
+template <bool ADMM>
+__global__ __launch_bounds__(64) void k_band_q2(LargeArgs a) {
+  // rows of the eigenvectors, (kmax + kBand) x kQ2C doubles sized at launch
+  // (rows past K stay zero), so that two or three workgroups share a CU
+  extern __shared__ double Zr[];
+  __shared__ double R[2][128 * kBandRefl];
+  int K;
+  int64_t base;
+  if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
+  if (K < a.band_min) return;
+  Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
+  const int r = (int)w.meta[0];
+  const int c0 = blockIdx.y * kQ2C;
+  if (c0 >= r) return;
+  const int nc = min(kQ2C, r - c0);
+  const int lane = threadIdx.x, c = lane & (kQ2C - 1), kk = lane >> 3;
+  const int NK = band_nk(K);
+  for (int idx = lane; idx < kQ2C * (K + kBand); idx += 64) {
+    const int row = idx / kQ2C, cl = idx - row * kQ2C;
+    Zr[idx] = (cl < nc && row < K) ? w.Z[(size_t)(c0 + cl) * K + row] : 0.0;
+  }
+  constexpr int kPre = 128 * kBandRefl / 64;   // reflector doubles per lane per sweep
+  auto nsteps = [&](int s) { return (K - 1 - s + kBand - 1) / kBand; };
+  auto load_sweep = [&](int s, double (&x)[kPre]) {
+    const double* src = w.refl + (size_t)s * NK * kBandRefl;
+    const int n = nsteps(s) * kBandRefl;
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) x[q] = src[min(lane + 64 * q, n - 1)];
+  };
+  double x[kPre];
+  int buf = 0;
+  load_sweep(K - 3, x);
+#pragma unroll
+  for (int q = 0; q < kPre; ++q) R[0][lane + 64 * q] = x[q];
+  for (int s = K - 3; s >= 0; --s) {
+    if (s > 0) load_sweep(s - 1, x);
+    const double* rs_ = R[buf];
+    const int ns = nsteps(s);
+    // passes of 8 reflectors (lane (k, c): reflector kk + 8 j), kQ2Pass at
+    // a time: all their loads first (the passes touch disjoint rows), then
+    // the updates.  Reflector entries past the matrix are stored as zero.
+    for (int j0 = 0; kBand * j0 < ns; j0 += kQ2Pass) {
+      double z[kQ2Pass][kBand], v[kQ2Pass][kBand];
+      int rsq[kQ2Pass];
+#pragma unroll
+      for (int jq = 0; jq < kQ2Pass; ++jq) {
+        const int k = kk + kBand * (j0 + jq);
+        const bool on = k < ns;
+        rsq[jq] = on ? s + 1 + kBand * k : K;   // K: a zero row block
+        const double* rf = rs_ + min(k, NK - 1) * kBandRefl;
+#pragma unroll
+        for (int i = 0; i < kBand; ++i) {
+          z[jq][i] = Zr[(rsq[jq] + i) * kQ2C + c];
+          v[jq][i] = on ? ((i == 0) ? 1.0 : rf[i]) : 0.0;
+        }
+        rsq[jq] = on ? rsq[jq] : -1;
+        const double tu = on ? rf[0] : 0.0;   // the record's slot 0 holds tau (v_0 = 1)
+        double dot = 0.0;
+#pragma unroll
+        for (int i = 0; i < kBand; ++i) dot += v[jq][i] * z[jq][i];
+        dot *= tu;
+#pragma unroll
+        for (int i = 0; i < kBand; ++i) z[jq][i] -= dot * v[jq][i];
+      }
+#pragma unroll
+      for (int jq = 0; jq < kQ2Pass; ++jq)
+        if (rsq[jq] >= 0)
+#pragma unroll
+          for (int i = 0; i < kBand; ++i) Zr[(rsq[jq] + i) * kQ2C + c] = z[jq][i];
+    }
+    if (s > 0) {
+#pragma unroll
+      for (int q = 0; q < kPre; ++q) R[buf ^ 1][lane + 64 * q] = x[q];
+      buf ^= 1;
+    }
+  }
+  for (int idx = lane; idx < nc * K; idx += 64) {
+    const int cl = idx / K, row = idx - cl * K;
+    w.Z[(size_t)(c0 + cl) * K + row] = Zr[row * kQ2C + cl];
+  }
+}
+
 constexpr int kBtNC = 8;     // eigenvectors per apply workgroup, resident in LDS
 constexpr int kBtCR = 256;   // rows of a staged V panel chunk
 
-// element (row, a) of V_p: v_{j0+a} has 1 on row j0+a+1 and the stored
-// Householder vector below it
-__device__ __forceinline__ double bt_v(const double* W, int ld, int K, int j0, int nbp, int a, int row) {
-  if (a >= nbp || row >= K || row <= j0 + a) return 0.0;
-  return (row == j0 + a + 1) ? 1.0 : W[(size_t)(j0 + a) * ld + row];
+// element (row, a) of V_p: the reflector of column c = j0 + a has 1 on row
+// c + sh and the stored Householder vector below it (sh = 1 after the
+// one-stage reduction, kBand after the dense-to-band stage, whose column c
+// keeps the band on rows c..c+kBand)
+__device__ __forceinline__ double bt_v(const double* W, int ld, int K, int j0, int nbp, int a, int row, int sh) {
+  if (a >= nbp || row >= K || row < j0 + a + sh) return 0.0;
+  return (row == j0 + a + sh) ? 1.0 : W[(size_t)(j0 + a) * ld + row];
 }
+
+// reflector columns of a task: 0 .. bt_ncols - 1
+__device__ __forceinline__ int bt_ncols(int K, int sh) { return K - 1 - sh; }
 
 __device__ __forceinline__ double* bt_tbuf(const Ws& w) { return w.S; }   // 32 x 32 per panel
 
@@ -1169,7 +1960,7 @@ __device__ __forceinline__ double* bt_tbuf(const Ws& w) { return w.S; }   // 32 
 // move a load under its lane condition: the thread's loads are in flight
 // together instead of one round trip each.  The value is selected after.
 __device__ __forceinline__ void bt_stage(double (*Vc)[33], const double* W, int ld, int K, int j0, int nbp,
-                                         int row0, int tid) {
+                                         int row0, int tid, int sh) {
   constexpr int NQ = kBtCR * 32 / 1024;
   double x[NQ];
 #pragma unroll
@@ -1182,8 +1973,8 @@ __device__ __forceinline__ void bt_stage(double (*Vc)[33], const double* W, int 
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int idx = tid + 1024 * q, as = idx / kBtCR, rl = idx - as * kBtCR, row = row0 + rl;
-    const bool zero = as >= nbp || row >= K || row <= j0 + as;
-    Vc[rl][as] = zero ? 0.0 : ((row == j0 + as + 1) ? 1.0 : x[q]);
+    const bool zero = as >= nbp || row >= K || row < j0 + as + sh;
+    Vc[rl][as] = zero ? 0.0 : ((row == j0 + as + sh) ? 1.0 : x[q]);
   }
 }
 
@@ -1195,18 +1986,20 @@ __global__ __launch_bounds__(1024) void k_bt_tfactor(LargeArgs a) {
   int K;
   int64_t base;
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
-  const int P = (K - 2 + kNB - 1) / kNB;
+  const int sh = (K >= a.band_min) ? kBand : 1;
+  const int ncols = bt_ncols(K, sh);
+  const int P = (ncols + kNB - 1) / kNB;
   const int p = blockIdx.y;
   if (p >= P) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   if ((int)w.meta[0] == 0) return;
   const int ld = lead_dim(K);
-  const int j0 = p * kNB, nbp = min(kNB, K - 2 - j0);
+  const int j0 = p * kNB, nbp = min(kNB, ncols - j0);
   const int tid = threadIdx.x, ta = tid >> 5, tb = tid & 31;
   // Gram matrix V_p^T V_p over 32-row chunks staged in LDS
   double g = 0.0;
-  for (int row0 = j0 + 1; row0 < K; row0 += 32) {
-    Vc[tb][ta] = bt_v(w.W, ld, K, j0, nbp, ta, row0 + tb);   // Vc[row][col]
+  for (int row0 = j0 + sh; row0 < K; row0 += 32) {
+    Vc[tb][ta] = bt_v(w.W, ld, K, j0, nbp, ta, row0 + tb, sh);   // Vc[row][col]
     __syncthreads();
 #pragma unroll 8
     for (int rr = 0; rr < 32; ++rr) g += Vc[rr][ta] * Vc[rr][tb];
@@ -1244,7 +2037,9 @@ __global__ __launch_bounds__(1024) void k_bt_apply(LargeArgs a) {
   if (c0 >= r) return;
   const int nc = min(kBtNC, r - c0);
   const int ld = lead_dim(K);
-  const int P = (K - 2 + kNB - 1) / kNB;
+  const int sh = (K >= a.band_min) ? kBand : 1;   // Q2 already applied by k_band_q2
+  const int ncols = bt_ncols(K, sh);
+  const int P = (ncols + kNB - 1) / kNB;
   const int tid = threadIdx.x;
   for (int idx = tid; idx < kBtNC * K; idx += 1024) {
     const int cl = idx / K, row = idx - cl * K;
@@ -1253,12 +2048,12 @@ __global__ __launch_bounds__(1024) void k_bt_apply(LargeArgs a) {
   const int a1 = tid & 31, cl1 = (tid >> 5) & 7, h1 = tid >> 8;   // pass 1: S(a, cl), row phase h
   const int rl3 = tid & 127, cl3 = tid >> 7;                        // pass 2: Z(row, cl)
   for (int p = P - 1; p >= 0; --p) {
-    const int j0 = p * kNB, nbp = min(kNB, K - 2 - j0);
+    const int j0 = p * kNB, nbp = min(kNB, ncols - j0);
     Ts[tid >> 5][tid & 31] = bt_tbuf(w)[(size_t)p * kNB * kNB + tid];
     // pass 1: S = V_p^T Z
     double sp = 0.0;
-    for (int row0 = j0 + 1; row0 < K; row0 += kBtCR) {
-      bt_stage(Vc, w.W, ld, K, j0, nbp, row0, tid);
+    for (int row0 = j0 + sh; row0 < K; row0 += kBtCR) {
+      bt_stage(Vc, w.W, ld, K, j0, nbp, row0, tid, sh);
       __syncthreads();
       const int nr = min(kBtCR, K - row0);
       for (int rr = h1; rr < nr; rr += 4) sp += Vc[rr][a1] * Zs[cl1][row0 + rr];
@@ -1275,8 +2070,8 @@ __global__ __launch_bounds__(1024) void k_bt_apply(LargeArgs a) {
     }
     __syncthreads();
     // pass 2: Z -= V_p S
-    for (int row0 = j0 + 1; row0 < K; row0 += kBtCR) {
-      bt_stage(Vc, w.W, ld, K, j0, nbp, row0, tid);
+    for (int row0 = j0 + sh; row0 < K; row0 += kBtCR) {
+      bt_stage(Vc, w.W, ld, K, j0, nbp, row0, tid, sh);
       __syncthreads();
 #pragma unroll
       for (int hh = 0; hh < kBtCR / 128; ++hh) {
@@ -1420,40 +2215,63 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
   if (ntask <= 0) return;
   const int rmax = kmax / 2 + 1;
   const int T = (kmax + kTile - 1) / kTile;
-  auto launch = [&](int kind, auto kernel, dim3 grid, dim3 block, auto... args) {
+  auto launch_shm = [&](int kind, auto kernel, dim3 grid, dim3 block, size_t shm, auto... args) {
     if (hook) {
       hipEvent_t e0, e1;
       hook->begin(hook->ctx, kind, &e0, &e1);
-      hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
+      hipExtLaunchKernelGGL(kernel, grid, block, shm, st, e0, e1, 0, args...);
       hook->end(hook->ctx, kind);
     } else {
-      hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+      hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
     }
+  };
+  auto launch = [&](int kind, auto kernel, dim3 grid, dim3 block, auto... args) {
+    launch_shm(kind, kernel, grid, block, 0, args...);
   };
   switch (step) {
     case 0: hipLaunchKernelGGL(k_large_gather<ADMM>, dim3(ntask, T * (T + 1) / 2), dim3(256), 0, st, a); break;
     case 1: {
-      // the panel steps of all tasks in lockstep; tasks are sorted by order
-      // (descending), so the tasks that still have panel p form a prefix;
-      // then one launch finishes every task in LDS
+      // tasks are sorted by order (descending): the two-stage tasks (order
+      // >= band_min) form a prefix, and so do the tasks that still have a
+      // given panel
+      int nband = 0;
+      while (nband < ntask && host_sizes[nband] >= a.band_min) ++nband;
+      if (nband) {
+        const int npm = band_panels(host_sizes[0]);
+        for (int p = 0; p <= npm; ++p) {
+          int na = 0;
+          while (na < nband && band_panels(host_sizes[na]) >= p) ++na;
+          launch(10, k_band_panel<ADMM>, dim3(na), dim3(kBandT), a, p);
+          const int n = host_sizes[0] - p * kBand - kBand;
+          if (n > 0) {
+            const int nt = (n + kBandTile - 1) / kBandTile;
+            launch(11, k_band_trail<ADMM>, dim3(na, nt * nt), dim3(kTrailT), a, p);
+          }
+        }
+        launch(12, k_band_chase<ADMM>, dim3(nband), dim3(64 * kChaseWaves), a);
+      }
+      // one-stage: the panel steps of the remaining tasks in lockstep, then
+      // one launch finishes every such task in LDS
       auto active = [&](int j0) {
         int n = 0;
         while (n < ntask && trd_tail_start(host_sizes[n]) > j0) ++n;
         return n;
       };
-      const int np = trd_tail_start(kmax) / kNB;
-      const int ldm = (kmax + 7) & ~7;
+      if (nband == ntask) break;
+      const int kmax1 = host_sizes[nband];   // largest one-stage order
+      const int np = trd_tail_start(kmax1) / kNB;
+      const int ldm = (kmax1 + 7) & ~7;
       for (int p = 0; p < np; ++p) {
         const int na = active(p * kNB);
         for (int i = 0; i < kNB; ++i) {
           const int j = p * kNB + i;
-          const int nallm = kmax - j - 1 + 2 * i;
+          const int nallm = kmax1 - j - 1 + 2 * i;
           const int ncy = (nallm + kSymvCols - 1) / kSymvCols;
           const int nrbm = (ldm - ((j + 1) & ~1) + kSymvRows - 1) / kSymvRows;
           launch(0, k_trd_symv<ADMM>, dim3(na, ncy * nrbm), dim3(256), a, p, i, ncy);
           launch(1, k_trd_update<ADMM>, dim3(na, (ldm + kUpdRows - 1) / kUpdRows), dim3(256), a, p, i);
         }
-        const int n2 = kmax - p * kNB - kNB;
+        const int n2 = kmax1 - p * kNB - kNB;
         launch(2, k_trd_trail<ADMM>, dim3(na, ((n2 + 127) / 128) * ((n2 + 63) / 64)), dim3(kTT), a, p);
       }
       launch(3, k_trd_tail<ADMM>, dim3(ntask), dim3(kTailT), a);
@@ -1467,6 +2285,18 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
       launch(7, k_eig_cluster<ADMM>, dim3(ntask, (rmax + 1) / 2), dim3(64), a);
       break;
     case 3:
+      if (host_sizes[0] >= a.band_min) {
+        // dynamic LDS above 64 KB (orders above 1000) needs the kernel's
+        // limit raised; set once per process
+        static const bool raised = [] {
+          const int bytes = (1024 + kBand) * kQ2C * (int)sizeof(double);
+          return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band_q2<ADMM>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+        }();
+        (void)raised;
+        launch_shm(13, k_band_q2<ADMM>, dim3(ntask, (rmax + kQ2C - 1) / kQ2C), dim3(64),
+                   (size_t)(kmax + kBand) * kQ2C * sizeof(double), a);
+      }
       launch(8, k_bt_tfactor<ADMM>, dim3(ntask, (kmax - 2 + kNB - 1) / kNB), dim3(1024), a);
       launch(9, k_bt_apply<ADMM>, dim3(ntask, (rmax + kBtNC - 1) / kBtNC), dim3(1024), a);
       break;
@@ -1479,20 +2309,24 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
 }
 
 void launch_cone_large_step(const DevPlan& d, const int32_t* tasks, int32_t ntask, int32_t kmax,
-                            const int32_t* host_sizes, int step, hipStream_t st, const LaunchHook* hook) {
+                            const int32_t* host_sizes, int step, hipStream_t st, int band_min,
+                            const LaunchHook* hook) {
   LargeArgs a{};
   a.d = d;
   a.tasks = tasks;
   a.work = d.big_work;
   a.woff = d.big_off;
   a.tsize = d.big_size;
+  a.band_min = band_min;
   run_large_step<true>(a, ntask, kmax, host_sizes, step, st, hook);
 }
 
 void launch_psd_project_large(const int32_t* sizes, const int64_t* offs, const int32_t* tasks,
                               const int32_t* task_sizes, const int32_t* host_sizes, int32_t ntask, int32_t kmax,
-                              const double* in, double* out, double* work, const int64_t* work_off, hipStream_t st) {
+                              const double* in, double* out, double* work, const int64_t* work_off, hipStream_t st,
+                              int band_min) {
   LargeArgs a{};
+  a.band_min = band_min;
   a.tasks = tasks;
   a.psizes = sizes;
   a.poffs = offs;

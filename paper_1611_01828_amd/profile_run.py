@@ -9,7 +9,7 @@ so that every dispatch is seen by the counters) through the C ABI.
 
 Workloads: maxcut (G(2000, 6000) max-cut relaxation, cliques up to 673),
 batch (256 block-arrow SDPs in one handle), uneven (uneven cliques 4..96,
-n = 5000, m = 2000).
+n = 5000, m = 2000); --method 1 / 2 runs the primal-only / dual-only ADMM.
 """
 from __future__ import annotations
 
@@ -27,6 +27,8 @@ def main():
     ap.add_argument("--workload", choices=["maxcut", "batch", "uneven"], default="maxcut")
     ap.add_argument("--iters", type=int, default=4)
     ap.add_argument("--no-copy", action="store_true", help="skip the 64 MiB copy calibration")
+    ap.add_argument("--method", type=int, default=0, choices=[0, 1, 2],
+                    help="settings.method: 0 self-dual, 1 primal-only, 2 dual-only ADMM")
     args = ap.parse_args()
 
     import torch
@@ -43,7 +45,7 @@ def main():
         del a, b
         print("[profile_run] 3 copies of 64 MiB done", flush=True)
     inst = {"maxcut": configs.maxcut_random_2000, "batch": configs.block_arrow_batch256, "uneven": configs.uneven_cliques_5000}[args.workload]()
-    s = cdcs.Solver(inst)
+    s = cdcs.Solver(inst, method=args.method)
     s.iterate(args.iters)
     torch.cuda.synchronize()
     s.close()

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared():
         assert hasattr(lib, name), name
     assert set(_declared()) == set(cdcs.EXPORTS)
-    assert lib.cdcs_abi_version() == 5 == cdcs.ABI_VERSION
+    assert lib.cdcs_abi_version() == 6 == cdcs.ABI_VERSION
 
 
 def test_default_settings_match_the_paper():

@@ -121,3 +121,49 @@ def test_adjoint_reports_its_outcome(lib):
         warnings.simplefilter("always")
         L.backward()
     assert any("iteration limit" in str(x.message) for x in rec)
+
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    with open(path) as f:
+        head = json.loads(f.readline()[1:])
+        vals = np.array([float(v) for v in f])
+    return head, vals
+
+
+def test_adjoint_clique_above_64_matches_stored_oracle_gradient(lib):
+    """Cliques of 70 and 24 vertices: the 70-vertex one takes the adjoint's
+    96-vertex eigen-cache.  Reference: the oracle's dense gradient stored by
+    tests/golden/make_grad_block_arrow_k70.py (forward solve to 1e-11)."""
+    import importlib.util
+    import os
+    _log("adjoint with a 70-vertex clique vs the stored dense oracle gradient")
+    spec = importlib.util.spec_from_file_location(
+        "make_k70", os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_grad_block_arrow_k70.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    inst = mk.instance()
+    prob = hsde.build_problem(inst)
+    head, ref = _golden("grad_block_arrow_k70.txt")
+    assert sorted(head["cliques"]) == sorted(len(c) for c in inst.cliques) and max(head["cliques"]) > 64
+    gc, gb = ref[:prob.nE], ref[prob.nE:]
+    s, dc, db, it = _gpu_grad(lib, [inst], [mk.weights(prob)])
+    r, why = s.adjoint_info()
+    s.close()
+    rc = np.linalg.norm(dc - gc) / np.linalg.norm(gc)
+    rb = np.linalg.norm(db - gb) / max(np.linalg.norm(gb), 1e-12)
+    _log(f"  adjoint iterations {it}, residual {r[0]:.1e} (reason {why[0]}), rel err dc {rc:.2e} db {rb:.2e}")
+    assert rc <= 1e-6 and rb <= 1e-6
+
+
+def test_adjoint_rejects_cliques_above_96(lib):
+    _log("adjoint refuses a 98-vertex clique")
+    inst = configs.small_block_arrow(62, n=98, block=96, arrow=2, m=6)
+    assert max(len(c) for c in inst.cliques) == 98
+    s = lib.Solver([inst], max_iter=5)
+    s.solve()
+    with pytest.raises(lib.CDCSError, match="96 vertices"):
+        s.adjoint(np.ones(hsde.build_problem(inst).nE), max_iter=10, tol=1e-8)
+    s.close()

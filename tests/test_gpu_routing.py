@@ -104,3 +104,35 @@ def test_bad_jacobi_max_rejected(lib):
     with pytest.raises(lib.CDCSError) as e:
         lib.Solver(inst, jacobi_max=48)
     assert e.value.code == -1
+
+
+# ----------------------------------------------------------------------------
+# the reduction to tridiagonal form (settings.band_min): two-stage (dense to
+# band, band to tridiagonal) for cliques of band_min vertices or more, the
+# one-stage blocked reduction below; the same eigenpairs up to rounding
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("band_min", [137, 200, 2000])
+def test_reductions_against_oracle(lib, band_min):
+    """Cliques of 130 and 250 vertices (the 250-vertex one through the
+    two-stage reduction unless band_min = 2000)."""
+    inst = configs.small_block_arrow(8, n=510, block=240, arrow=10, m=12, per_row=8)
+    w, _ = _iterate_parity(lib, inst, 15, band_min=band_min)
+    _log(f"band_min={band_min}, cliques of 250: worst rel {w:.2e}")
+
+
+@pytest.mark.parametrize("band_min", [300, 2000])
+def test_maxcut_mixed_reductions(lib, band_min):
+    """Max-cut G(2000, 6000): with band_min = 300 the 29 cliques above 300
+    vertices take the two-stage reduction and the 18 of 137..300 the
+    one-stage one in the same step; 2000 keeps the one-stage reduction for
+    all."""
+    w, _ = _iterate_parity(lib, configs.maxcut_random_2000(), 4, band_min=band_min)
+    _log(f"max-cut, band_min={band_min}: worst rel {w:.2e}")
+
+
+def test_bad_band_min_rejected(lib):
+    inst = configs.small_block_arrow(0, n=12, block=3, arrow=2, m=4)
+    with pytest.raises(lib.CDCSError) as e:
+        lib.Solver(inst, band_min=100)
+    assert e.value.code == -1

@@ -125,3 +125,24 @@ def test_dproj_block_is_self_adjoint_and_a_contraction():
     nA = np.sum(A * A)
     q = np.sum(A * grad.dproj_block(Y, A))
     assert -1e-13 <= q <= nA * (1 + 1e-13)
+
+
+def test_adjoint_solution_route_does_not_change_the_gradient(monkeypatch):
+    """The dense adjoint takes the minimum-norm least-squares solution of its
+    singular system; when the divide-and-conquer SVD does not converge it
+    falls back to the QR-iteration SVD, which gives the same solution (a
+    basic solution instead differs along the near-null directions by ~1e-5
+    of the gradient on this instance)."""
+    inst = configs.small_block_arrow(14, n=12, block=4, arrow=2, m=5)
+    prob = hsde.build_problem(inst)
+    w = np.random.default_rng(5).standard_normal(prob.nE)
+    _, res = grad.objective_weight_loss(inst, w, eps_tol=1e-11)
+    gc, gb = grad.adjoint_gradient_dense(res, w)
+
+    def refuse(*args, **kw):
+        raise np.linalg.LinAlgError("SVD did not converge")
+
+    monkeypatch.setattr(np.linalg, "lstsq", refuse)
+    gc2, gb2 = grad.adjoint_gradient_dense(res, w)
+    assert np.linalg.norm(gc2 - gc) <= 1e-8 * np.linalg.norm(gc)
+    assert np.linalg.norm(gb2 - gb) <= 1e-8 * max(np.linalg.norm(gb), 1e-12)
