@@ -57,24 +57,101 @@ def trd_tail_start(K, tail=136, nb=32):
     return ((K - tail + nb - 1) // nb) * nb if K > tail else 0
 
 
-def phase_work(inst_sizes, prob_dims):
+BAND = 8                     # bandwidth of the two-stage reduction's first stage
+BAND_MIN = 137               # default smallest clique order of the two-stage reduction
+
+
+def band_panels(K):
+    """Panels of the dense-to-band stage of a clique of order K."""
+    return (K - 9 + BAND - 1) // BAND
+
+
+def chase_steps(K):
+    """Bulge-chasing steps of a clique of order K (sweeps 0..K-3)."""
+    return sum((K - 1 - s + BAND - 1) // BAND for s in range(K - 2))
+
+
+def smaller_side_counts(solver, inst):
+    """Eigenvectors each large clique's projection computed at the last
+    iteration: min(#negative, #nonnegative) eigenvalues of Y = s - z (the
+    argument of the last conic step: s = Pi(Y), z = s - Y), from the
+    solver's state; None for the Jacobi cliques."""
+    import numpy as np
+    nE, ns, m, _ = solver.dims()
+    u, vt = solver.get_state()
+    y = u[nE:nE + ns] - vt[nE:nE + ns]
+    out, off = [], 0
+    for c in inst.cliques:
+        K = len(c)
+        blk = y[off:off + K * (K + 1) // 2]
+        off += K * (K + 1) // 2
+        if K <= JACOBI_MAX:
+            out.append(None)
+            continue
+        # svec over the lower triangle, column by column, off-diagonals x sqrt(2)
+        Y = np.zeros((K, K))
+        rows, cols = np.tril_indices(K)
+        order = np.lexsort((rows, cols))
+        Y[rows[order], cols[order]] = blk
+        Y = np.tril(Y, -1) / np.sqrt(2.0) + np.diag(np.diag(Y))
+        Y = Y + np.tril(Y, -1).T
+        nneg = int(np.sum(np.linalg.eigvalsh(Y) < 0.0))
+        out.append(min(nneg, K - nneg))
+    return out
+
+
+def phase_work(inst_sizes, prob_dims, band_min=BAND_MIN, rcounts=None):
     """Algorithmic work of one average launch of each kernel phase.
 
     Returns {phase: (bound, amount, unit)}; amount is bytes for memory-bound
-    phases and flops for arithmetic ones.  The tridiagonalisation runs one
-    symv and one update launch per column step of the panels (all large
-    cliques in lockstep, each until its last <= 136 columns), one trailing
-    update per panel of 32 and one LDS tail launch."""
+    phases and flops for arithmetic ones.  Cliques of band_min vertices or
+    more take the two-stage reduction: per panel of 8 columns one panel
+    launch (the panel's columns, V, Y, U and the column-tile partials of
+    A22 U once each) and one trailing-update launch (A22 read, and written
+    after the first panel), then one bulge-chasing launch (~950 flops per
+    8 x 8 step) and the back-transformation of its reflectors (32 flops per
+    reflector and eigenvector; rcounts: eigenvectors per clique, in clique
+    order, None where unknown).  The others: one symv and one update launch
+    per column step of the panels (all such cliques in lockstep, each until
+    its last <= 136 columns), one trailing update per panel of 32 and one
+    LDS tail launch."""
     large = sorted((k for k in inst_sizes if k > JACOBI_MAX), reverse=True)
     small = [k for k in inst_sizes if k <= JACOBI_MAX]
+    band = [k for k in large if k >= band_min]
+    one = [k for k in large if k < band_min]
     nE, ns, m, p = prob_dims
     out = {}
-    if large:
+    if band:
+        npm = band_panels(band[0])
+        pan_b = trail_b = 0.0
+        for pp in range(npm + 1):
+            for K in band:
+                if band_panels(K) < pp:
+                    break
+                n = K - BAND * pp
+                nct = (n + 127) // 128
+                pan_b += 8.0 * BAND * n * (6 + nct)
+                n2 = n - BAND
+                if n2 > 0:
+                    trail_b += 8.0 * n2 * n2 * (2 if pp > 0 else 1) + 8.0 * n2 * 3 * BAND
+        ntrail = sum(1 for pp in range(npm + 1) if band[0] - BAND * pp - BAND > 0)
+        out["band_panel"] = ("hbm", pan_b / (npm + 1), "GB/s")
+        out["band_trail"] = ("hbm", trail_b / ntrail, "GB/s")
+        out["band_chase"] = ("alu", sum(950.0 * chase_steps(K) for K in band), "TFLOP/s")
+        if rcounts is not None:
+            rk = [r for k, r in zip(inst_sizes, rcounts) if r is not None and k >= band_min]
+            kb = [k for k, r in zip(inst_sizes, rcounts) if r is not None and k >= band_min]
+            out["band_q2"] = ("alu", sum(32.0 * r * chase_steps(K) for K, r in zip(kb, rk)), "TFLOP/s")
+    if rcounts is not None:
+        # compact-WY back-transformation: 4 K^2 r flops per clique
+        out["bt_apply"] = ("alu", sum(4.0 * k * k * r for k, r in zip(inst_sizes, rcounts) if r is not None),
+                           "TFLOP/s")
+    if one:
         nbp = 32
-        npan = trd_tail_start(large[0]) // nbp
+        npan = trd_tail_start(one[0]) // nbp
         symv_b = upd_b = trail_f = 0.0
         for pp in range(npan):
-            for K in large:
+            for K in one:
                 if trd_tail_start(K) <= pp * nbp:
                     break
                 n2 = K - pp * nbp - nbp
@@ -91,7 +168,7 @@ def phase_work(inst_sizes, prob_dims):
             out["trd_update"] = ("hbm", upd_b / (npan * nbp), "GB/s")
             out["trd_trail"] = ("alu", trail_f / npan, "TFLOP/s")
         # the last n <= 136 columns of every clique, (4/3) n^3 flops each
-        out["trd_tail"] = ("alu", sum(4.0 / 3.0 * (K - trd_tail_start(K)) ** 3 for K in large), "TFLOP/s")
+        out["trd_tail"] = ("alu", sum(4.0 / 3.0 * (K - trd_tail_start(K)) ** 3 for K in one), "TFLOP/s")
     # Jacobi blocks: counted with the 10 K^3 eigen-decomposition convention
     for kmax, name in ((16, "cone_jacobi16"), (32, "cone_jacobi32"), (64, "cone_jacobi64"), (96, "cone_jacobi96")):
         lo = {16: 0, 32: 16, 64: 32, 96: 64}[kmax]
@@ -313,6 +390,11 @@ def main():
     torch.cuda.synchronize()
     dt_ev = time.perf_counter() - t0
     phases = timed.phase_times()
+    # eigenvectors each large clique's projection computed in the last timed
+    # iteration (the back-transformations' work scales with them)
+    rcounts = smaller_side_counts(timed, inst) if args.method == "self_dual" else None
+    print(f"[bench] eigenvectors of the large cliques at the last event-timed iteration: "
+          f"{sum(r for r in (rcounts or []) if r is not None)}", file=sys.stderr, flush=True)
     timed.close()
     print(f"[bench] event-timed pass ({ev_steps} iterations): {1e3 * dt_ev / ev_steps:.2f} ms/iteration",
           file=sys.stderr, flush=True)
@@ -320,7 +402,7 @@ def main():
     # dominant kernel and its roofline position (per-launch averages from HIP events)
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()}
     dom = max(phases, key=lambda k: phases[k][0])
-    work = phase_work(sizes, dims)
+    work = phase_work(sizes, dims, band_min=args.band_min or BAND_MIN, rcounts=rcounts)
     roof = None
     if dom in work:
         bound, amount, unit = work[dom]

@@ -1850,8 +1850,8 @@ __global__ __launch_bounds__(64) void k_eig_cluster(LargeArgs a) {
 // onwards and commute).  One wave per kQ2C eigenvectors, held in LDS row by
 // row; lane (k, c) applies reflector k (+ 8 per pass) of the sweep to
 // eigenvector c.  The next sweep's reflectors are loaded into registers
-// while the current sweep runs, then stored to the other LDS buffer (one
-// wave: LDS accesses are served in order, no barrier).
+// while the current sweep runs and stored over them after it (one wave:
+// LDS accesses are served in order, no barrier).
 constexpr int kQ2C = 8;
 constexpr int kQ2Pass = 4;   // reflector passes whose loads are issued together
 template <bool ADMM>
@@ -1859,7 +1859,7 @@ __global__ __launch_bounds__(64) void k_band_q2(LargeArgs a) {
   // rows of the eigenvectors, (kmax + kBand) x kQ2C doubles sized at launch
   // (rows past K stay zero), so that two or three workgroups share a CU
   extern __shared__ double Zr[];
-  __shared__ double R[2][128 * kBandRefl];
+  __shared__ double R[128 * kBandRefl];   // the current sweep's reflectors
   int K;
   int64_t base;
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
@@ -1884,13 +1884,12 @@ __global__ __launch_bounds__(64) void k_band_q2(LargeArgs a) {
     for (int q = 0; q < kPre; ++q) x[q] = src[min(lane + 64 * q, n - 1)];
   };
   double x[kPre];
-  int buf = 0;
   load_sweep(K - 3, x);
 #pragma unroll
-  for (int q = 0; q < kPre; ++q) R[0][lane + 64 * q] = x[q];
+  for (int q = 0; q < kPre; ++q) R[lane + 64 * q] = x[q];
   for (int s = K - 3; s >= 0; --s) {
-    if (s > 0) load_sweep(s - 1, x);
-    const double* rs_ = R[buf];
+    if (s > 0) load_sweep(s - 1, x);   // in registers until this sweep is done
+    const double* rs_ = R;
     const int ns = nsteps(s);
     // passes of 8 reflectors (lane (k, c): reflector kk + 8 j), kQ2Pass at
     // a time: all their loads first (the passes touch disjoint rows), then
@@ -1924,11 +1923,9 @@ __global__ __launch_bounds__(64) void k_band_q2(LargeArgs a) {
 #pragma unroll
           for (int i = 0; i < kBand; ++i) Zr[(rsq[jq] + i) * kQ2C + c] = z[jq][i];
     }
-    if (s > 0) {
+    if (s > 0)
 #pragma unroll
-      for (int q = 0; q < kPre; ++q) R[buf ^ 1][lane + 64 * q] = x[q];
-      buf ^= 1;
-    }
+      for (int q = 0; q < kPre; ++q) R[lane + 64 * q] = x[q];
   }
   for (int idx = lane; idx < nc * K; idx += 64) {
     const int cl = idx / K, row = idx - cl * K;

@@ -33,8 +33,9 @@ def test_tail_start(bench):
 
 
 def test_symv_work_hand_count(bench):
-    # one clique of 200: panels 0..1 (tail start 64), 32 columns each
-    w = bench.phase_work([200], (0, 0, 0, 1))
+    # one clique of 200 through the one-stage reduction: panels 0..1 (tail
+    # start 64), 32 columns each
+    w = bench.phase_work([200], (0, 0, 0, 1), band_min=2000)
     tot = 0.0
     for j in range(64):
         i = j % 32
@@ -43,6 +44,55 @@ def test_symv_work_hand_count(bench):
     assert w["trd_symv"][1] == pytest.approx(tot / 64)
     assert w["trd_symv"][0] == "hbm"
     assert w["trd_tail"][1] == pytest.approx(4.0 / 3.0 * (200 - 64) ** 3)
+
+
+def test_band_work_hand_count(bench):
+    # one clique of 150 through the two-stage reduction: panels 0..17
+    # (band_panels = ceil(141 / 8) = 18) and the closing launch 18
+    w = bench.phase_work([150], (0, 0, 0, 1), rcounts=[40])
+    assert bench.band_panels(150) == 18
+    pan = trail = 0.0
+    for p in range(19):
+        n = 150 - 8 * p
+        pan += 64.0 * n * (6 + (n + 127) // 128)
+        n2 = n - 8
+        if n2 > 0:
+            trail += 8.0 * n2 * n2 * (2 if p else 1) + 8.0 * n2 * 24
+    assert w["band_panel"] == ("hbm", pytest.approx(pan / 19), "GB/s")
+    assert w["band_trail"] == ("hbm", pytest.approx(trail / 18), "GB/s")   # no trail launch at p = 18
+    # sweep s has ceil((149 - s) / 8) steps
+    steps = sum(-(-(149 - s) // 8) for s in range(148))
+    assert bench.chase_steps(150) == steps
+    assert w["band_chase"][1] == pytest.approx(950.0 * steps)
+    assert w["band_q2"][1] == pytest.approx(32.0 * 40 * steps)
+    assert w["bt_apply"][1] == pytest.approx(4.0 * 150 * 150 * 40)
+    assert "trd_symv" not in w
+
+
+def test_smaller_side_counts_from_the_state(bench):
+    # a fake solver whose state holds Y = s - z for one clique of 70 with
+    # 20 negative eigenvalues, beside a Jacobi clique of 3
+    from oracle import hsde
+
+    class Inst:
+        cliques = [list(range(3)), list(range(70))]
+
+    rng = np.random.default_rng(1)
+    Q, _ = np.linalg.qr(rng.standard_normal((70, 70)))
+    Y = Q @ np.diag(np.r_[-np.arange(1, 21), np.arange(1, 51)].astype(float)) @ Q.T
+    small = hsde.svec_blocks(np.eye(3), 3)
+    yv = np.r_[small, hsde.svec_blocks(Y, 70)]
+    ns = yv.size
+
+    class Solver:
+        def dims(self):
+            return (2, ns, 1, 2)
+
+        def get_state(self):
+            u = np.r_[np.zeros(2), yv, np.zeros(1 + ns + 1)]
+            return u, np.zeros_like(u)
+
+    assert bench.smaller_side_counts(Solver(), Inst()) == [None, 20]
 
 
 def test_affine_work_hand_count(bench):
