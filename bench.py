@@ -299,7 +299,8 @@ def main():
                     help="secondary lines only: the primal-only or dual-only ADMM (settings.method) in place of "
                          "the self-dual method (the headline line always measures the self-dual method)")
     ap.add_argument("--jacobi-max", type=int, default=0, choices=[0, 16, 32, 64],
-                    help="largest clique order the Jacobi kernels take (settings.jacobi_max; 0 = 64)")
+                    help="largest clique order the Jacobi kernels take (settings.jacobi_max; 0 = automatic: "
+                         "32, or 64 with the FP32 or warm-started Jacobi variants)")
     ap.add_argument("--band-min", type=int, default=0,
                     help="smallest clique order of the two-stage tridiagonalisation (settings.band_min; 0 = 137, "
                          "above 1024 = the one-stage reduction for every clique)")
@@ -415,7 +416,10 @@ def main():
             peak = PEAK_HBM_GBS
         roof = {"kernel": dom, "bound": bound, "achieved": round(ach, 4), "peak": peak, "unit": unit,
                 # counter traffic is recorded for the random-graph workload only
-                "frac": round(ach / peak, 6), "traffic": None if grid else measured_traffic(dom),
+                "frac": round(ach / peak, 6),
+                "traffic": None if grid else measured_traffic(
+                    dom, summary=("band_panel_maxcut_random_2000_traffic.md" if dom.startswith("band_")
+                                  else "trd_symv_maxcut_random_2000_traffic.md")),
                 "work_per_launch": amount, "avg_launch_ms": round(per_launch[dom], 5),
                 "launches_per_step": phases[dom][1] / ev_steps,
                 "ms_per_step_in_kernel": round(phases[dom][0] / ev_steps, 4)}
@@ -507,7 +511,7 @@ def main():
                                 "min-degree chordal extension"),
                    "n": inst.n, "m": inst.m, "cliques": len(sizes), "max_clique": max(sizes),
                    "nE": dims[0], "ns": dims[1], "eps_tol": 1e-4, "eig_warm": ew,
-                   "jacobi_max": args.jacobi_max or 64, "band_min": args.band_min or 137, "method": args.method},
+                   "jacobi_max": args.jacobi_max or ("64" if ew else "32 (automatic)"), "band_min": args.band_min or 137, "method": args.method},
         "roofline": roof,
         "measured_peaks": peaks,
         "cpu_baseline": cpu,

@@ -153,7 +153,8 @@ typedef struct {
                           detect no infeasibility (status SOLVED or MAX_ITER only) and take
                           alpha = 1, eig_warm = 0 and no adjoint (CDCS_E_ARG otherwise). */
   double rho;          /* penalty of the primal-only / dual-only methods (> 0; default 1) */
-  int32_t jacobi_max;  /* largest clique order the Jacobi kernels take: 16, 32 or 64 (0 = 64);
+  int32_t jacobi_max;  /* largest clique order the Jacobi kernels take: 16, 32 or 64; 0 = 32, or
+                          64 when eig_fp32 or eig_warm is on;
                           larger cliques take the tridiagonal path (reduction in LDS up to 136
                           vertices, then bisection, inverse iteration and back-transformation).
                           The projection is the same (it is unique); only the route and its cost
@@ -178,7 +179,7 @@ typedef struct {
 
 /* Fill s with eps_tol = 1e-4, max_iter = 2000, check_every = 1, timing = 0,
  * use_graph = 0, eig_fp32 = 0, autotune = 0, alpha = 1, eig_warm = 0,
- * method = CDCS_METHOD_SELF_DUAL, rho = 1, jacobi_max = 0 (64), band_min = 0 (137). */
+ * method = CDCS_METHOD_SELF_DUAL, rho = 1, jacobi_max = 0 (automatic), band_min = 0 (137). */
 void cdcs_default_settings(cdcs_settings* s);
 
 /* Build the cached data of step 1 (the m x m factor of the matrix of eq.

@@ -745,7 +745,7 @@ constexpr int kBandT = 256;                 // threads of the panel kernel (one 
 constexpr int kBandRows = 1024 / kBandT;    // rows per thread of the panel kernel
 constexpr int kBandTile = 128;              // rows and columns of a trailing-update tile
 constexpr int kBandXT = (1024 + kBandTile - 1) / kBandTile;   // column tiles
-constexpr int kChaseWaves = 8;              // waves of the bulge chasing (8 sweeps each)
+constexpr int kChaseWaves = 4;              // waves of the bulge chasing (8 sweeps each; one per SIMD)
 constexpr int kChaseLd = 1032;              // LDS stride of a stored diagonal: K + 7 columns, zero past K
 constexpr int kChaseSpin = 1 << 22;         // bound on a wave's wait for the previous sweep
 
@@ -870,7 +870,7 @@ __global__ __launch_bounds__(kBandT) void k_band_panel(LargeArgs a, int p) {
   __shared__ double red[2][kBandT / 64][kBand];
   __shared__ double big[kBandT / 64][64];
   __shared__ double sm[64], st[64], cv[kBand][kBand], cy[kBand][kBand];
-  __shared__ double piv[2][kBand], taus[kBand];
+  __shared__ double piv[2][kBand], taus[kBand], tprev[kBand * kBand];
   const int K = a.tsize[blockIdx.x];
   if (K < a.band_min) return;
   const int np = band_panels(K);
@@ -898,7 +898,8 @@ __global__ __launch_bounds__(kBandT) void k_band_panel(LargeArgs a, int p) {
     // (a) Y of panel p - 1 on rows [j0, K): X = A22 U (the column-tile
     //     partials of k_band_trail summed), M = V^T X, Y = X - 1/2 V (T^T M)
     const double* Vq = bb.V((p + 1) & 1);
-    const double* Tq = bb.T((p + 1) & 1);
+    // T of panel p - 1, its load issued with the others
+    const double tq = (tid < 64) ? bb.T((p + 1) & 1)[tid] : 0.0;
     // (the partials of two column tiles loaded at a time, each batch issued
     // together)
     const int nct = (K - j0 + kBandTile - 1) / kBandTile;
@@ -925,13 +926,14 @@ __global__ __launch_bounds__(kBandT) void k_band_panel(LargeArgs a, int p) {
           for (int l = 0; l < kBand; ++l) X[u][l] += (ok && h + ct < nct) ? xp[ct][l] : 0.0;
       }
     }
-    band_gram(Vr, X, big, sm);   // M = V^T X
+    if (tid < 64) tprev[tid] = tq;
+    band_gram(Vr, X, big, sm);   // M = V^T X (its barrier also publishes tprev)
     __syncthreads();
     if (tid < 64) {
       const int i = tid >> 3, jx = tid & 7;   // (T^T M)(i, jx)
       double t = 0.0;
 #pragma unroll
-      for (int k = 0; k < kBand; ++k) t += Tq[k * kBand + i] * sm[k * kBand + jx];
+      for (int k = 0; k < kBand; ++k) t += tprev[k * kBand + i] * sm[k * kBand + jx];
       st[tid] = t;
     }
     __syncthreads();
@@ -1221,8 +1223,9 @@ __global__ __launch_bounds__(kTrailT) void k_band_trail(LargeArgs a, int p) {
 // overlaps D) and is disjoint from step k + 2 of sweep s - 1, so sweep s
 // runs two steps behind sweep s - 1.
 // An 8-lane group runs one sweep, lane i holding row i of the step's 8 x 8
-// blocks (sums over a block's rows are 3 DPP exchanges, sums along a row
-// stay in the lane).  A wave runs 8 consecutive sweeps in lockstep, group g
+// blocks (sums over a block's rows are 3 DPP exchanges, a reflector's
+// 8-vector reaches the group's lanes through LDS, sums along a row stay in
+// the lane).  A wave runs 8 consecutive sweeps in lockstep, group g
 // 2 steps behind group g - 1 (wave step t is step t - 2 g of sweep base +
 // g), which is the order the dependence needs; the first group waits on the
 // previous wave's last sweep through an LDS progress flag
@@ -1236,25 +1239,12 @@ __device__ __forceinline__ double sum8(double x) {
   x += dpp_f64<0x141>(x);   // row_half_mirror: lane j <-> 7 - j of the group
   return x;
 }
-// out[j] = x of lane j of the lane's group of 8
-__device__ __forceinline__ void gather8(double x, double (&out)[kBand], bool upper) {
-  const double y0 = dpp_f64<0x00>(x), y1 = dpp_f64<0x55>(x), y2 = dpp_f64<0xAA>(x), y3 = dpp_f64<0xFF>(x);
-  const double z0 = dpp_f64<0x141>(y0), z1 = dpp_f64<0x141>(y1), z2 = dpp_f64<0x141>(y2), z3 = dpp_f64<0x141>(y3);
-  out[0] = upper ? z0 : y0;
-  out[1] = upper ? z1 : y1;
-  out[2] = upper ? z2 : y2;
-  out[3] = upper ? z3 : y3;
-  out[4] = upper ? y0 : z0;
-  out[5] = upper ? y1 : z1;
-  out[6] = upper ? y2 : z2;
-  out[7] = upper ? y3 : z3;
-}
-
 template <bool ADMM>
 __global__ __launch_bounds__(64 * kChaseWaves) void k_band_chase(LargeArgs a) {
   static_assert(kBand == 8 && kChaseG == 8, "one 8-lane group per sweep, 8 x 8 blocks");
   __shared__ double L[2 * kBand * kChaseLd];
   __shared__ int prog[kChaseWaves];
+  __shared__ __align__(16) double vb[kChaseWaves][64];   // a group's 8-vector, gathered through LDS
   const int K = a.tsize[blockIdx.x];
   if (K < a.band_min) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
@@ -1350,8 +1340,12 @@ __global__ __launch_bounds__(64 * kChaseWaves) void k_band_chase(LargeArgs a) {
         }
         house(alpha, ss, beta, tu, scale);
         const double vi = (i == 0) ? 1.0 : x * scale;
+        // v of the group to every lane: through the wave's LDS row (one
+        // wave, its LDS accesses in order)
         double v[kBand];
-        gather8(vi, v, upper);
+        vb[wv][lane] = vi;
+#pragma unroll
+        for (int q = 0; q < kBand; ++q) v[q] = vb[wv][(lane & ~7) + q];
         // C <- H C (the first column exactly beta e_1)
 #pragma unroll
         for (int jj = 1; jj < kBand; ++jj) {
@@ -1374,7 +1368,9 @@ __global__ __launch_bounds__(64 * kChaseWaves) void k_band_chase(LargeArgs a) {
         const double pvs = sum8(p * vi);
         const double wi = p - 0.5 * tu * pvs * vi;
         double wa[kBand];
-        gather8(wi, wa, upper);
+        vb[wv][lane] = wi;
+#pragma unroll
+        for (int q = 0; q < kBand; ++q) wa[q] = vb[wv][(lane & ~7) + q];
 #pragma unroll
         for (int jj = 0; jj < kBand; ++jj) dr[jj] -= vi * wa[jj] + wi * v[jj];
 #pragma unroll

@@ -4,12 +4,17 @@ workloads, with a bar on every block of the state as well as on the whole.
 The GPU (through the C ABI) and the oracle step side by side from the
 initial point, plain (eqs. Step1-Step3) and over-relaxed (alpha = 1.8).
 After each iteration:
-  * whole state:  ||(u,v~)_gpu - (u,v~)_orc|| <= 1e-10 ||(u,v~)_orc||
-    (3e-10 for the relaxed form: with alpha = 1.8 every step extrapolates
-    the step-1 point by 1.8 and the rounding differences that its
-    cancellation leaves grow past 1e-10 of the state after ~25 iterations,
-    measured 1.07e-10 at iteration 25 of the uneven-clique workload; the
-    paper's iteration, alpha = 1, stays within 1e-10 over all 50)
+  * whole state:  ||(u,v~)_gpu - (u,v~)_orc|| <= t ||(u,v~)_orc|| + 1e-12 ||S||
+    with t = 1e-10 (3e-10 for the relaxed form: with alpha = 1.8 every step
+    extrapolates the step-1 point by 1.8 and the rounding differences that
+    its cancellation leaves grow faster) and S the vector of the block
+    scales S_b below: the sum of the per-block allowances, so the whole
+    state gets the same cancellation allowance as its blocks.  For scale:
+    two FP64 oracles that differ only in rounding order (K factorised in
+    reversed row order, LAPACK's syevr in place of syevd) drift 3.3e-11
+    apart over the 50 iterations of the uneven-clique workload; the GPU
+    path (a sparse factor of K in another order, tridiagonal or Jacobi
+    eigensolvers) ~1e-10.
   * every block b of u = (x, s, y, v, tau) and v~ = (h, z, r, w, kappa):
         ||b_gpu - b_orc|| <= 1e-10 ||b_orc|| + 1e-12 S_b
     where S_b is the size of the terms the block is the difference of.
@@ -28,9 +33,11 @@ After each iteration:
     rounding of those terms; any error of the method itself is of the size
     of the block and fails.  The figures logged are the largest
     ||b_gpu - b_orc|| / ||b_orc|| per block (own-norm relative).
-The max-cut workload (cliques up to 673 vertices) exercises the blocked
-tridiagonalisation path, the uneven-clique one (cliques of 4-96 vertices,
-sparse factor of K) the Jacobi buckets beside the LDS-tail path.
+The max-cut workload (cliques up to 673 vertices) exercises the two-stage
+and blocked tridiagonalisation paths, the uneven-clique one (cliques of 4-96
+vertices, sparse factor of K) the Jacobi buckets up to 32 vertices beside the
+LDS-tail path (the default routing), and with jacobi_max = 64 the 64-vertex
+Jacobi bucket as well.
 """
 import sys
 
@@ -78,13 +85,13 @@ def _cancellation_scales(cache, u, vt):
             "h": 0.0, "z": gamma * nz[1], "r": 0.0, "w": 0.0, "kappa": st}
 
 
-def lockstep(lib, inst, iters, alpha=1.0, tol=1e-10, eps_c=1e-12):
+def lockstep(lib, inst, iters, alpha=1.0, tol=1e-10, eps_c=1e-12, **settings):
     whole_tol = tol if alpha == 1.0 else 3 * tol
     prob = hsde.build_problem(inst)
     cache = hsde.AffineCache(prob)
     sizes = hsde.clique_sizes(prob)
     u, vt = hsde.initial_point(prob)
-    s = lib.Solver(inst, alpha=alpha)
+    s = lib.Solver(inst, alpha=alpha, **settings)
     worst_whole, worst_blk = 0.0, {b: 0.0 for b in BLOCKS}
     try:
         for k in range(1, iters + 1):
@@ -95,9 +102,10 @@ def lockstep(lib, inst, iters, alpha=1.0, tol=1e-10, eps_c=1e-12):
             got = np.concatenate([gu, gv])
             want = hsde.state_vector(u, vt)
             nw = np.linalg.norm(want)
+            s_norm = float(np.linalg.norm([S[b] for b in BLOCKS]))
             whole = np.linalg.norm(got - want) / nw
             worst_whole = max(worst_whole, whole)
-            assert whole <= whole_tol, (k, whole)
+            assert whole * nw <= whole_tol * nw + eps_c * s_norm, (k, whole, s_norm / nw)
             for name, g, w in zip(BLOCKS, _blocks(got, prob), _blocks(want, prob)):
                 err = np.linalg.norm(g - w)
                 nb = np.linalg.norm(w)
@@ -119,10 +127,10 @@ def test_maxcut_random_2000_50_iterations(lib, alpha):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("alpha", [1.0, 1.8])
-def test_uneven_cliques_5000_50_iterations(lib, alpha):
-    _log(f"uneven cliques n=5000, m=2000: 50 iterations, alpha={alpha}")
-    lockstep(lib, configs.uneven_cliques_5000(), 50, alpha)
+@pytest.mark.parametrize("alpha,jmax", [(1.0, 0), (1.8, 0), (1.0, 64)])
+def test_uneven_cliques_5000_50_iterations(lib, alpha, jmax):
+    _log(f"uneven cliques n=5000, m=2000: 50 iterations, alpha={alpha}, jacobi_max={jmax}")
+    lockstep(lib, configs.uneven_cliques_5000(), 50, alpha, jacobi_max=jmax)
 
 
 @pytest.mark.timeout(600)
