@@ -32,7 +32,6 @@ constexpr int kTT = 512;         // threads of the tridiagonalisation kernel
 constexpr int kNB = 32;          // panel width of the tridiagonalisation
 constexpr int kBand = 8;         // bandwidth of the two-stage reduction's first stage
 constexpr int kBandRefl = 8;     // doubles per stored bulge-chasing reflector: tau, v_1..v_7
-constexpr int kQ2Sweeps = 8;     // sweeps of reflectors staged per LDS chunk of the back-transformation
 // bulge-chasing steps per sweep (the first sweep's count; the stride of the
 // reflector array)
 __host__ __device__ __forceinline__ int band_nk(int K) { return (K + 6) / kBand; }
@@ -820,12 +819,14 @@ __device__ __forceinline__ void band_gram(const double (&A)[kBandRows][kBand], c
   }
 }
 
-// x of another lane through a DPP exchange (CTRL: the DPP control word)
+// x of another lane through a DPP exchange (CTRL: the DPP control word; the
+// controls used here read a valid lane for every lane, so the destination
+// needs no initial value)
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
   const int lo = __double2loint(x), hi = __double2hiint(x);
-  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  const int l2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
   return __hiloint2double(h2, l2);
 }
 __device__ __forceinline__ double readlane_f64(double x, int l) {
@@ -846,17 +847,21 @@ __device__ __forceinline__ double wave_sum_dpp(double x) {
 
 // block sums of NV values over kBandT threads (buf: one of two alternating
 // buffers, so that consecutive sums need one barrier each)
+// (values below k0 are left as they are; k0 is a constant after unrolling)
 template <int NV>
-__device__ __forceinline__ void band_block_sum(double (&v)[NV], double (*buf)[kBand]) {
+__device__ __forceinline__ void band_block_sum(double (&v)[NV], double (*buf)[kBand], int k0 = 0) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = wave_sum_dpp(v[k]);
+  for (int k = 0; k < NV; ++k)
+    if (k >= k0) v[k] = wave_sum_dpp(v[k]);
   if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) buf[wid][k] = v[k];
+    for (int k = 0; k < NV; ++k)
+      if (k >= k0) buf[wid][k] = v[k];
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
+    if (k < k0) continue;
     double t = 0.0;
 #pragma unroll
     for (int q = 0; q < kBandT / 64; ++q) t += buf[q][k];
@@ -900,30 +905,37 @@ __global__ __launch_bounds__(kBandT) void k_band_panel(LargeArgs a, int p) {
     const double* Vq = bb.V((p + 1) & 1);
     // T of panel p - 1, its load issued with the others
     const double tq = (tid < 64) ? bb.T((p + 1) & 1)[tid] : 0.0;
-    // (the partials of two column tiles loaded at a time, each batch issued
-    // together)
+    // (the partials of two column tiles loaded at a time for all of the
+    // thread's rows, each batch issued together)
     const int nct = (K - j0 + kBandTile - 1) / kBandTile;
     double X[kBandRows][kBand], Vr[kBandRows][kBand];
 #pragma unroll
     for (int u = 0; u < kBandRows; ++u) {
       const int r = j0 + tid + kBandT * u;
-      const bool ok = r < K;
       const int rc = min(r, K - 1);
 #pragma unroll
       for (int l = 0; l < kBand; ++l) {
-        Vr[u][l] = ok ? Vq[(size_t)rc * kBand + l] : 0.0;
+        Vr[u][l] = (r < K) ? Vq[(size_t)rc * kBand + l] : 0.0;
         X[u][l] = 0.0;
       }
-      for (int h = 0; h < nct; h += 2) {
-        double xp[2][kBand];
+    }
+    for (int h = 0; h < nct; h += 2) {
+      double xp[kBandRows][2][kBand];
+#pragma unroll
+      for (int u = 0; u < kBandRows; ++u) {
+        const int rc = min(j0 + tid + kBandT * u, K - 1);
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-          for (int l = 0; l < kBand; ++l) xp[ct][l] = bb.X()[((size_t)min(h + ct, nct - 1) * ld + rc) * kBand + l];
+          for (int l = 0; l < kBand; ++l) xp[u][ct][l] = bb.X()[((size_t)min(h + ct, nct - 1) * ld + rc) * kBand + l];
+      }
+#pragma unroll
+      for (int u = 0; u < kBandRows; ++u) {
+        const bool ok = j0 + tid + kBandT * u < K;
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-          for (int l = 0; l < kBand; ++l) X[u][l] += (ok && h + ct < nct) ? xp[ct][l] : 0.0;
+          for (int l = 0; l < kBand; ++l) X[u][l] += (ok && h + ct < nct) ? xp[u][ct][l] : 0.0;
       }
     }
     if (tid < 64) tprev[tid] = tq;
@@ -1028,7 +1040,7 @@ __global__ __launch_bounds__(kBandT) void k_band_panel(LargeArgs a, int p) {
     if (tid == kBand + l)
 #pragma unroll
       for (int mm = 0; mm < kBand; ++mm) pv[mm] = P[0][mm];
-    band_block_sum<kBand>(sg, red[nred++ & 1]);
+    band_block_sum<kBand>(sg, red[nred++ & 1], l);   // sums of columns l.. only
     const double alpha = pv[l];
     double beta, tu, scale;
     if (sg[l] == 0.0) {
@@ -1117,27 +1129,30 @@ __global__ __launch_bounds__(kBandT) void k_band_panel(LargeArgs a, int p) {
 }
 
 // A22 -= V Y^T + Y V^T of panel p - 1 (p > 0) and the partial sums of
-// X = A22 U of panel p (p < np) on a 128 x 128 tile of the trailing matrix
-// [8p + 8, K)^2 (both triangles).  Thread (row, quarter) takes 32 columns:
-// all its loads are issued before any store (stores count against the same
-// vector-memory counter as loads, so a load behind a store waits for it).
-// X partials: one ld x kBand array per column tile.
-constexpr int kTrailT = 512;
-constexpr int kTrailQ = kTrailT / kBandTile;          // column groups
+// X = A22 U of panel p (p < np) on a kTrailRows x kBandTile tile of the
+// trailing matrix [8p + 8, K)^2 (both triangles).  Thread (row, quarter)
+// takes 32 columns: all its loads are issued before any store (stores count
+// against the same vector-memory counter as loads, so a load behind a store
+// waits for it).  Four waves (one per SIMD) and at most 170 registers let
+// three workgroups share a CU, so that one tile's loads overlap another's
+// arithmetic.  X partials: one ld x kBand array per column tile.
+constexpr int kTrailT = 256;
+constexpr int kTrailRows = 64;
+constexpr int kTrailQ = kTrailT / kTrailRows;         // column groups
 constexpr int kTrailC = kBandTile / kTrailQ;          // columns per thread
 template <bool ADMM>
-__global__ __launch_bounds__(kTrailT) void k_band_trail(LargeArgs a, int p) {
+__global__ __launch_bounds__(kTrailT, 3) void k_band_trail(LargeArgs a, int p) {
   __shared__ double cs[kBandTile][3 * kBand];   // V, Y, U of the tile's columns
-  __shared__ double xh[kTrailQ - 1][kBandTile][kBand];
+  __shared__ double xh[kTrailQ - 1][kTrailRows][kBand];
   const int K = a.tsize[blockIdx.x];
   if (K < a.band_min) return;
   const int np = band_panels(K);
   if (p > np) return;
   const int R0 = p * kBand + kBand, n = K - R0;
   if (n <= 0) return;
-  const int nt = (n + kBandTile - 1) / kBandTile;
-  if ((int)blockIdx.y >= nt * nt) return;
-  const int tr = blockIdx.y % nt, tc = blockIdx.y / nt;
+  const int ntr = (n + kTrailRows - 1) / kTrailRows, ntc = (n + kBandTile - 1) / kBandTile;
+  if ((int)blockIdx.y >= ntr * ntc) return;
+  const int tr = blockIdx.y % ntr, tc = blockIdx.y / ntr;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const int ld = lead_dim(K);
   const BandBufs bb = band_bufs(w, ld);
@@ -1146,8 +1161,8 @@ __global__ __launch_bounds__(kTrailT) void k_band_trail(LargeArgs a, int p) {
   const int vpar = (p + 1) & 1;   // V of panel p - 1
   const int tid = threadIdx.x;
   const int cb0 = R0 + tc * kBandTile;
-  const int rl = tid & (kBandTile - 1), qt = tid / kBandTile;
-  const int r = R0 + tr * kBandTile + rl;
+  const int rl = tid & (kTrailRows - 1), qt = tid / kTrailRows;
+  const int r = R0 + tr * kTrailRows + rl;
   const int rc = min(r, K - 1);
   const int cs0 = qt * kTrailC;                       // first tile column of this thread
   // the thread's 32 entries (clamped addresses), issued first
@@ -1155,12 +1170,18 @@ __global__ __launch_bounds__(kTrailT) void k_band_trail(LargeArgs a, int p) {
 #pragma unroll
   for (int j = 0; j < kTrailC; ++j) x[j] = W[(size_t)min(cb0 + cs0 + j, K - 1) * ld + rc];
   // column operands (offset arithmetic: V, U, Y are kBand ld-row arrays at
-  // slots vpar, 2 and 3 of the workspace)
-  for (int idx = tid; idx < kBandTile * 3 * kBand; idx += kTrailT) {
+  // slots vpar, 2 and 3 of the workspace) and the row's V and Y, all loads
+  // issued before the first LDS store
+  constexpr int kCsN = kBandTile * 3 * kBand / kTrailT;
+  static_assert(kCsN * kTrailT == kBandTile * 3 * kBand, "column operand staging");
+  double cv[kCsN];
+#pragma unroll
+  for (int q = 0; q < kCsN; ++q) {
+    const int idx = tid + kTrailT * q;
     const int cc = idx / (3 * kBand), f = idx - cc * (3 * kBand), c = min(cb0 + cc, K - 1);
     const int sel = (f < kBand) ? vpar : ((f < 2 * kBand) ? 3 : 2);
     const bool on = (f < 2 * kBand) ? upd : sym;
-    cs[cc][f] = on ? bb.S[(size_t)sel * kBand * ld + (size_t)c * kBand + (f & (kBand - 1))] : 0.0;
+    cv[q] = on ? bb.S[(size_t)sel * kBand * ld + (size_t)c * kBand + (f & (kBand - 1))] : 0.0;
   }
   double vr[kBand], yr[kBand], acc[kBand];
 #pragma unroll
@@ -1168,6 +1189,12 @@ __global__ __launch_bounds__(kTrailT) void k_band_trail(LargeArgs a, int p) {
     vr[l] = upd ? bb.V(vpar)[(size_t)rc * kBand + l] : 0.0;
     yr[l] = upd ? bb.Y()[(size_t)rc * kBand + l] : 0.0;
     acc[l] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < kCsN; ++q) {
+    const int idx = tid + kTrailT * q;
+    const int cc = idx / (3 * kBand), f = idx - cc * (3 * kBand);
+    cs[cc][f] = cv[q];
   }
   __syncthreads();
   const int ncc = min(kTrailC, K - (cb0 + cs0));       // valid columns (may be <= 0)
@@ -1306,20 +1333,27 @@ __global__ __launch_bounds__(64 * kChaseWaves) void k_band_chase(LargeArgs a) {
       }
       const int k = t - 2 * g;
       if (k >= 0 && k < nst) {
-        // rows r.. of the block the step annihilates and reduces; column
-        // block pr0.. of the previous reflector (step 0: column s itself)
-        const int pr0 = (k == 0) ? s : s + 1 + kBand * (k - 1);
+        // rows r.. of the block the step annihilates and reduces; the
+        // previous reflector's column block r - 8.. (step 0: column s = r - 1)
         const int r = s + 1 + kBand * k;
-        // C = B(r:r+8, pr0:pr0+8) (step 0: column s only), row i;
+        // C = B(r:r+8, r-8:r), row i: entry jj at diagonal 8 + i - jj,
+        // column r - 8 + jj, i.e. (7 - jj) (kChaseLd - 1) after entry 7
+        // (diagonal 1 + i, column r - 1), which at step 0 is column s, the
+        // only column that step reads (every address stays inside L:
+        // diagonals 1..15, columns >= r - 8 > -kChaseLd);
         // D = B(r:r+8, r:r+8), row i
+        double* c7 = &L[(1 + i) * kChaseLd + r - 1];
         double c[kBand], dr[kBand];
 #pragma unroll
         for (int jj = 0; jj < kBand; ++jj) {
-          const int dj = (k > 0) ? jj : 0;   // step 0 reads column s only
-          const double cv = L[(r + i - pr0 - dj) * kChaseLd + pr0 + dj];
-          c[jj] = (k > 0 || jj == 0) ? cv : 0.0;
+          c[jj] = c7[(kBand - 1 - jj) * (kChaseLd - 1)];
           const int hi = max(i, jj), lo = min(i, jj);
           dr[jj] = L[(hi - lo) * kChaseLd + r + lo];
+        }
+        if (k == 0) {
+          c[0] = c[kBand - 1];
+#pragma unroll
+          for (int jj = 1; jj < kBand; ++jj) c[jj] = 0.0;
         }
         if (k > 0) {
           // C <- C H_prev (the fill the previous reflector makes)
@@ -1355,9 +1389,9 @@ __global__ __launch_bounds__(64 * kChaseWaves) void k_band_chase(LargeArgs a) {
         c[0] = (i == 0) ? beta : 0.0;
         if (k > 0) {
 #pragma unroll
-          for (int jj = 0; jj < kBand; ++jj) L[(r + i - pr0 - jj) * kChaseLd + pr0 + jj] = c[jj];
+          for (int jj = 0; jj < kBand; ++jj) c7[(kBand - 1 - jj) * (kChaseLd - 1)] = c[jj];
         } else {
-          L[(r + i - pr0) * kChaseLd + pr0] = c[0];
+          c7[0] = c[0];
         }
         w.refl[((size_t)s * NK + k) * kBandRefl + i] = (i == 0) ? tu : vi;
         // D <- H D H: p = tau D v, w = p - tau/2 (p^T v) v, D -= v w^T + w v^T
@@ -1586,16 +1620,20 @@ __global__ __launch_bounds__(kLT) void k_eig_prep(LargeArgs a) {
   }
 }
 
-// (b) bisection, kBisEig eigenvalues per workgroup, one wave each: the 64
-//     lanes evaluate the Sturm count at 64 interior points (multisection) and
-//     the interval shrinks by 65 per round.  The chosen side lies in
-//     [Gershgorin low, 0] or [0, Gershgorin high]; the count at 0 is the
-//     nneg of the prep, so count(lo) <= k < count(hi) holds from the start.
-//     Intervals are refined to an absolute width of about eps ||T||, the
-//     accuracy inverse iteration and the low-rank update can use.
-constexpr int kBisEig = 4;
+// (b) bisection: a group of kBisL lanes per eigenvalue (4 per wave, 16 per
+//     workgroup of 4 waves).  The group's lanes evaluate the Sturm count at
+//     kBisL interior points (multisection) and the interval shrinks by
+//     kBisL + 1 per round; 16 points take 13 rounds where 64 take 9, for a
+//     quarter of the lanes.  The chosen side lies in [Gershgorin low, 0] or
+//     [0, Gershgorin high]; the count at 0 is the nneg of the prep, so
+//     count(lo) <= k < count(hi) holds from the start.  Intervals are refined
+//     to an absolute width of about eps ||T||, the accuracy inverse iteration
+//     and the low-rank update can use.
+constexpr int kBisL = 16;
+constexpr int kBisWaves = 4;
+constexpr int kBisEig = kBisWaves * (64 / kBisL);
 template <bool ADMM>
-__global__ __launch_bounds__(64 * kBisEig) void k_eig_bisect(LargeArgs a) {
+__global__ __launch_bounds__(64 * kBisWaves) void k_eig_bisect(LargeArgs a) {
   __shared__ double sd[1024], se2[1024];
   int K;
   int64_t base;
@@ -1606,31 +1644,37 @@ __global__ __launch_bounds__(64 * kBisEig) void k_eig_bisect(LargeArgs a) {
   if (t0 >= r) return;
   const int pos = (int)w.meta[1], first = (int)w.meta[2];
   const double pivmin = w.meta[3], tnorm = w.meta[4];
-  const int tid = threadIdx.x, lane = tid & 63, t = t0 + (tid >> 6);
-  for (int i = tid; i < K; i += 64 * kBisEig) {
+  const int tid = threadIdx.x, lane = tid & 63, grp = lane / kBisL, gl = lane % kBisL;
+  const int t = t0 + (tid >> 6) * (64 / kBisL) + grp;
+  for (int i = tid; i < K; i += 64 * kBisWaves) {
     sd[i] = w.d[i];
     const double ei = (i < K - 1) ? w.e[i] : 0.0;
     se2[i] = ei * ei;
   }
   __syncthreads();
-  if (t >= r) return;   // whole waves; no barriers below
+  if (t0 + (tid >> 6) * (64 / kBisL) >= r) return;   // whole waves; no barriers below
+  const bool act = t < r;
   const double glo = -tnorm * (1.0 + 4.0 * kEps) - pivmin, ghi = tnorm * (1.0 + 4.0 * kEps) + pivmin;
   const double wtol = 2.0 * kEps * tnorm + 4.0 * pivmin;
   const int k = first + t;
   double lo = pos ? 0.0 : glo, hi = pos ? ghi : 0.0;
   for (int round = 0; round < 200; ++round) {
     const double width = hi - lo;
-    if (width <= fmax(wtol, 2.0 * kEps * fmax(fabs(lo), fabs(hi)))) break;
-    const double step = width / 65.0;
-    const double x = lo + step * (double)(lane + 1);
-    const uint64_t m = __ballot(sturm_count(sd, se2, K, x, pivmin) > k);
-    const int j0 = m ? __builtin_ctzll(m) : 64;   // first point with count > k
-    const double nlo = (j0 == 0) ? lo : lo + step * (double)j0;
-    const double nhi = (j0 == 64) ? hi : lo + step * (double)(j0 + 1);
-    lo = nlo;
-    hi = fmax(nhi, nlo);
+    const bool done = !act || width <= fmax(wtol, 2.0 * kEps * fmax(fabs(lo), fabs(hi)));
+    if (__ballot(!done) == 0) break;
+    const double step = width / (double)(kBisL + 1);
+    const double x = lo + step * (double)(gl + 1);
+    const uint64_t m = __ballot(!done && sturm_count(sd, se2, K, x, pivmin) > k);
+    const uint32_t gm = (uint32_t)(m >> (grp * kBisL)) & ((1u << kBisL) - 1u);
+    const int j0 = gm ? __builtin_ctz(gm) : kBisL;   // first point with count > k
+    if (!done) {
+      const double nlo = (j0 == 0) ? lo : lo + step * (double)j0;
+      const double nhi = (j0 == kBisL) ? hi : lo + step * (double)(j0 + 1);
+      lo = nlo;
+      hi = fmax(nhi, nlo);
+    }
   }
-  if (lane == 0) w.lam[t] = 0.5 * (lo + hi);
+  if (act && gl == 0) w.lam[t] = 0.5 * (lo + hi);
 }
 
 // Inverse iteration with a partially pivoted LU of T - lambda I.  The
@@ -1648,22 +1692,27 @@ __device__ __forceinline__ double eig_ortol(double tnorm) { return 1e-5 * tnorm;
 //     suffice: lambda is accurate to ~eps ||T|| and its gap to the other
 //     eigenvalues is above 1e-5 ||T||, so each solve shrinks the other
 //     components of a random start by ~1e-10 or more.
-//     The LDS-resident form (114 KB per workgroup) suits tasks with few chosen
-//     eigenvalues; tasks with more than kSingleLds of them use the wide form
-//     below (64 eigenvalues per workgroup, factors in the element-major global
-//     scratch), which keeps many more workgroups per CU.
-constexpr int kSingle = 2;
+//     The LDS-resident form (kSingle eigenvalues of orders up to kSingleK,
+//     54 KB per workgroup) suits small tasks with few chosen eigenvalues; the
+//     others use the wide form below (64 eigenvalues per workgroup, factors
+//     in the element-major global scratch), whose lanes are all busy.  (The
+//     LDS form sized for order 1024 held one workgroup of two busy lanes per
+//     CU: 364 us per max-cut iteration at its start, where every task has at
+//     most 32 chosen eigenvalues.)
+constexpr int kSingle = 8;
 constexpr int kSingleLds = 32;
+constexpr int kSingleK = 136;
+__device__ __forceinline__ bool single_lds(int r, int K) { return r <= kSingleLds && K <= kSingleK; }
 template <bool ADMM>
 __global__ __launch_bounds__(64) void k_eig_single(LargeArgs a) {
-  __shared__ double sd[1024], se[1024];
-  __shared__ double F[kSingle][6 * 1024];
+  __shared__ double sd[kSingleK], se[kSingleK];
+  __shared__ double F[kSingle][6 * kSingleK];
   int K;
   int64_t base;
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const int r = (int)w.meta[0];
-  if (r > kSingleLds || blockIdx.y * kSingle >= r) return;
+  if (!single_lds(r, K) || blockIdx.y * kSingle >= r) return;
   const double tnorm = w.meta[4];
   for (int i = threadIdx.x; i < K; i += 64) {
     sd[i] = w.d[i];
@@ -1692,7 +1741,7 @@ __global__ __launch_bounds__(64) void k_eig_single_wide(LargeArgs a) {
   if (!task_info<ADMM>(a, blockIdx.x, K, base)) return;
   Ws w = ws_of(a.work + a.woff[blockIdx.x], K);
   const int r = (int)w.meta[0];
-  if (r <= kSingleLds || blockIdx.y * 64 >= r) return;
+  if (single_lds(r, K) || blockIdx.y * 64 >= r) return;
   const double tnorm = w.meta[4];
   for (int i = threadIdx.x; i < K; i += 64) {
     sd[i] = w.d[i];
@@ -1844,16 +1893,17 @@ __global__ __launch_bounds__(64) void k_eig_cluster(LargeArgs a) {
 // bulge-chasing reflectors in the order they were made: sweeps from the last
 // to the first (a sweep's reflectors act on disjoint rows s + 1 + kBand k
 // onwards and commute).  One wave per kQ2C eigenvectors, held in LDS row by
-// row; lane (k, c) applies reflector k (+ 8 per pass) of the sweep to
+// row; lane (k, c) applies reflector k (+ 64 / kQ2C per pass) of the sweep to
 // eigenvector c.  The next sweep's reflectors are loaded into registers
 // while the current sweep runs and stored over them after it (one wave:
 // LDS accesses are served in order, no barrier).
-constexpr int kQ2C = 8;
+constexpr int kQ2C = 4;
 constexpr int kQ2Pass = 4;   // reflector passes whose loads are issued together
 template <bool ADMM>
 __global__ __launch_bounds__(64) void k_band_q2(LargeArgs a) {
   // rows of the eigenvectors, (kmax + kBand) x kQ2C doubles sized at launch
-  // (rows past K stay zero), so that two or three workgroups share a CU
+  // (rows past K stay zero): with the reflector buffer 30 KB at order 673,
+  // five workgroups per CU
   extern __shared__ double Zr[];
   __shared__ double R[128 * kBandRefl];   // the current sweep's reflectors
   int K;
@@ -1865,11 +1915,24 @@ __global__ __launch_bounds__(64) void k_band_q2(LargeArgs a) {
   const int c0 = blockIdx.y * kQ2C;
   if (c0 >= r) return;
   const int nc = min(kQ2C, r - c0);
-  const int lane = threadIdx.x, c = lane & (kQ2C - 1), kk = lane >> 3;
+  constexpr int kQ2K = 64 / kQ2C;   // reflectors per pass
+  const int lane = threadIdx.x, c = lane & (kQ2C - 1), kk = lane / kQ2C;
   const int NK = band_nk(K);
-  for (int idx = lane; idx < kQ2C * (K + kBand); idx += 64) {
-    const int row = idx / kQ2C, cl = idx - row * kQ2C;
-    Zr[idx] = (cl < nc && row < K) ? w.Z[(size_t)(c0 + cl) * K + row] : 0.0;
+  // the eigenvectors into LDS, 8 loads in flight per lane (clamped
+  // addresses, the value selected after)
+  for (int i0 = 0; i0 < kQ2C * (K + kBand); i0 += 64 * 8) {
+    double zv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = i0 + lane + 64 * q, row = idx / kQ2C, cl = idx - row * kQ2C;
+      zv[q] = w.Z[(size_t)(c0 + min(cl, nc - 1)) * K + min(row, K - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = i0 + lane + 64 * q;
+      const int row = idx / kQ2C, cl = idx - row * kQ2C;
+      if (row < K + kBand) Zr[idx] = (cl < nc && row < K) ? zv[q] : 0.0;
+    }
   }
   constexpr int kPre = 128 * kBandRefl / 64;   // reflector doubles per lane per sweep
   auto nsteps = [&](int s) { return (K - 1 - s + kBand - 1) / kBand; };
@@ -1887,15 +1950,15 @@ __global__ __launch_bounds__(64) void k_band_q2(LargeArgs a) {
     if (s > 0) load_sweep(s - 1, x);   // in registers until this sweep is done
     const double* rs_ = R;
     const int ns = nsteps(s);
-    // passes of 8 reflectors (lane (k, c): reflector kk + 8 j), kQ2Pass at
+    // passes of kQ2K reflectors (lane (k, c): reflector kk + kQ2K j), kQ2Pass at
     // a time: all their loads first (the passes touch disjoint rows), then
     // the updates.  Reflector entries past the matrix are stored as zero.
-    for (int j0 = 0; kBand * j0 < ns; j0 += kQ2Pass) {
+    for (int j0 = 0; kQ2K * j0 < ns; j0 += kQ2Pass) {
       double z[kQ2Pass][kBand], v[kQ2Pass][kBand];
       int rsq[kQ2Pass];
 #pragma unroll
       for (int jq = 0; jq < kQ2Pass; ++jq) {
-        const int k = kk + kBand * (j0 + jq);
+        const int k = kk + kQ2K * (j0 + jq);
         const bool on = k < ns;
         rsq[jq] = on ? s + 1 + kBand * k : K;   // K: a zero row block
         const double* rf = rs_ + min(k, NK - 1) * kBandRefl;
@@ -1946,31 +2009,35 @@ __device__ __forceinline__ int bt_ncols(int K, int sh) { return K - 1 - sh; }
 
 __device__ __forceinline__ double* bt_tbuf(const Ws& w) { return w.S; }   // 32 x 32 per panel
 
-// Stage rows [row0, row0 + kBtCR) of the panel's 32 reflectors into Vc.
-// Every load is unconditional, from a clamped address inside the task's W
-// (column j0 + min(a, nbp - 1) <= K - 3, row <= K - 1), and the empty asm
-// statements take each loaded value as an operand, so the compiler cannot
-// move a load under its lane condition: the thread's loads are in flight
-// together instead of one round trip each.  The value is selected after.
-__device__ __forceinline__ void bt_stage(double (*Vc)[33], const double* W, int ld, int K, int j0, int nbp,
-                                         int row0, int tid, int sh) {
-  constexpr int NQ = kBtCR * 32 / 1024;
-  double x[NQ];
+// Stage rows [row0, row0 + kBtCR) of the panel's 32 reflectors into Vc, in
+// two parts: bt_fetch issues the loads into registers, bt_put stores the
+// values (so that the next chunk's loads can be in flight while the current
+// one is used).  Every load is unconditional, from a clamped address inside
+// the task's W (column j0 + min(a, nbp - 1) <= K - 3, row <= K - 1), and the
+// empty asm statements take each loaded value as an operand, so the compiler
+// cannot move a load under its lane condition: the thread's loads are in
+// flight together instead of one round trip each.  The value is selected
+// when it is stored.
+constexpr int kBtNQ = kBtCR * 32 / 1024;
+__device__ __forceinline__ void bt_fetch(double (&x)[kBtNQ], const double* W, int ld, int K, int j0, int nbp, int row0,
+                                         int tid) {
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
+  for (int q = 0; q < kBtNQ; ++q) {
     const int idx = tid + 1024 * q, as = idx / kBtCR, rl = idx - as * kBtCR;
     x[q] = W[(size_t)(j0 + min(as, nbp - 1)) * ld + min(row0 + rl, K - 1)];
   }
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) asm volatile("" : "+v"(x[q]));
+  for (int q = 0; q < kBtNQ; ++q) asm volatile("" : "+v"(x[q]));
+}
+__device__ __forceinline__ void bt_put(double (*Vc)[33], const double (&x)[kBtNQ], int K, int j0, int nbp, int row0,
+                                       int tid, int sh) {
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
+  for (int q = 0; q < kBtNQ; ++q) {
     const int idx = tid + 1024 * q, as = idx / kBtCR, rl = idx - as * kBtCR, row = row0 + rl;
     const bool zero = as >= nbp || row >= K || row < j0 + as + sh;
     Vc[rl][as] = zero ? 0.0 : ((row == j0 + as + sh) ? 1.0 : x[q]);
   }
 }
-
 template <bool ADMM>
 __global__ __launch_bounds__(1024) void k_bt_tfactor(LargeArgs a) {
   __shared__ double Vc[32][33];
@@ -2040,43 +2107,62 @@ __global__ __launch_bounds__(1024) void k_bt_apply(LargeArgs a) {
   }
   const int a1 = tid & 31, cl1 = (tid >> 5) & 7, h1 = tid >> 8;   // pass 1: S(a, cl), row phase h
   const int rl3 = tid & 127, cl3 = tid >> 7;                        // pass 2: Z(row, cl)
+  // Chunks in order: panels P-1 .. 0, each pass 1 then pass 2 over rows
+  // [j0 + sh, K) in steps of kBtCR; the next chunk's reflectors (and the next
+  // panel's T) are loaded while the current chunk is used.
+  auto jb = [&](int p) { return p * kNB; };
+  auto nb = [&](int p) { return min(kNB, ncols - p * kNB); };
+  double x[kBtNQ];
+  bt_fetch(x, w.W, ld, K, jb(P - 1), nb(P - 1), jb(P - 1) + sh, tid);
+  double tnext = bt_tbuf(w)[(size_t)(P - 1) * kNB * kNB + tid];
   for (int p = P - 1; p >= 0; --p) {
-    const int j0 = p * kNB, nbp = min(kNB, ncols - j0);
-    Ts[tid >> 5][tid & 31] = bt_tbuf(w)[(size_t)p * kNB * kNB + tid];
-    // pass 1: S = V_p^T Z
+    const int j0 = jb(p), nbp = nb(p);
+    Ts[tid >> 5][tid & 31] = tnext;
+    if (p > 0) tnext = bt_tbuf(w)[(size_t)(p - 1) * kNB * kNB + tid];
     double sp = 0.0;
-    for (int row0 = j0 + sh; row0 < K; row0 += kBtCR) {
-      bt_stage(Vc, w.W, ld, K, j0, nbp, row0, tid, sh);
-      __syncthreads();
-      const int nr = min(kBtCR, K - row0);
-      for (int rr = h1; rr < nr; rr += 4) sp += Vc[rr][a1] * Zs[cl1][row0 + rr];
-      __syncthreads();
-    }
-    Sp[h1][a1][cl1] = sp;
-    __syncthreads();
-    // S <- T S
-    if (tid < 32 * kBtNC) {
-      const int k = tid & 31, cl = tid >> 5;
-      double t = 0.0;
-      for (int m = k; m < 32; ++m) t += Ts[k][m] * ((Sp[0][m][cl] + Sp[1][m][cl]) + (Sp[2][m][cl] + Sp[3][m][cl]));
-      Sq[k][cl] = t;
-    }
-    __syncthreads();
-    // pass 2: Z -= V_p S
-    for (int row0 = j0 + sh; row0 < K; row0 += kBtCR) {
-      bt_stage(Vc, w.W, ld, K, j0, nbp, row0, tid, sh);
-      __syncthreads();
-#pragma unroll
-      for (int hh = 0; hh < kBtCR / 128; ++hh) {
-        const int rr = hh * 128 + rl3, row = row0 + rr;
-        if (row < K) {
-          double t = 0.0;
-#pragma unroll 8
-          for (int aa = 0; aa < 32; ++aa) t += Vc[rr][aa] * Sq[aa][cl3];
-          Zs[cl3][row] -= t;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int row0 = j0 + sh; row0 < K; row0 += kBtCR) {
+        bt_put(Vc, x, K, j0, nbp, row0, tid, sh);
+        __syncthreads();
+        // the chunk after this one
+        if (row0 + kBtCR < K) {
+          bt_fetch(x, w.W, ld, K, j0, nbp, row0 + kBtCR, tid);
+        } else if (pass == 0) {
+          bt_fetch(x, w.W, ld, K, j0, nbp, j0 + sh, tid);
+        } else if (p > 0) {
+          bt_fetch(x, w.W, ld, K, jb(p - 1), nb(p - 1), jb(p - 1) + sh, tid);
         }
+        const int nr = min(kBtCR, K - row0);
+        if (pass == 0) {
+          // pass 1: S = V_p^T Z
+          for (int rr = h1; rr < nr; rr += 4) sp += Vc[rr][a1] * Zs[cl1][row0 + rr];
+        } else {
+          // pass 2: Z -= V_p S
+#pragma unroll
+          for (int hh = 0; hh < kBtCR / 128; ++hh) {
+            const int rr = hh * 128 + rl3, row = row0 + rr;
+            if (row < K) {
+              double t = 0.0;
+#pragma unroll 8
+              for (int aa = 0; aa < 32; ++aa) t += Vc[rr][aa] * Sq[aa][cl3];
+              Zs[cl3][row] -= t;
+            }
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
+      if (pass == 0) {
+        Sp[h1][a1][cl1] = sp;
+        __syncthreads();
+        // S <- T S
+        if (tid < 32 * kBtNC) {
+          const int k = tid & 31, cl = tid >> 5;
+          double t = 0.0;
+          for (int m = k; m < 32; ++m) t += Ts[k][m] * ((Sp[0][m][cl] + Sp[1][m][cl]) + (Sp[2][m][cl] + Sp[3][m][cl]));
+          Sq[k][cl] = t;
+        }
+        __syncthreads();
+      }
     }
   }
   for (int idx = tid; idx < nc * K; idx += 1024) {
@@ -2237,8 +2323,8 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
           launch(10, k_band_panel<ADMM>, dim3(na), dim3(kBandT), a, p);
           const int n = host_sizes[0] - p * kBand - kBand;
           if (n > 0) {
-            const int nt = (n + kBandTile - 1) / kBandTile;
-            launch(11, k_band_trail<ADMM>, dim3(na, nt * nt), dim3(kTrailT), a, p);
+            const int ntr = (n + kTrailRows - 1) / kTrailRows, ntc = (n + kBandTile - 1) / kBandTile;
+            launch(11, k_band_trail<ADMM>, dim3(na, ntr * ntc), dim3(kTrailT), a, p);
           }
         }
         launch(12, k_band_chase<ADMM>, dim3(nband), dim3(64 * kChaseWaves), a);
@@ -2272,7 +2358,7 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
     }
     case 2:
       launch(4, k_eig_prep<ADMM>, dim3(ntask), dim3(kLT), a);
-      launch(5, k_eig_bisect<ADMM>, dim3(ntask, (rmax + kBisEig - 1) / kBisEig), dim3(64 * kBisEig), a);
+      launch(5, k_eig_bisect<ADMM>, dim3(ntask, (rmax + kBisEig - 1) / kBisEig), dim3(64 * kBisWaves), a);
       launch(6, k_eig_single<ADMM>, dim3(ntask, (std::min(rmax, kSingleLds) + kSingle - 1) / kSingle), dim3(64), a);
       launch(6, k_eig_single_wide<ADMM>, dim3(ntask, (rmax + 63) / 64), dim3(64), a);
       launch(7, k_eig_cluster<ADMM>, dim3(ntask, (rmax + 1) / 2), dim3(64), a);
