@@ -1561,6 +1561,93 @@ __device__ __forceinline__ double tri_solve(const double* __restrict__ f, int st
   return 1.0 / sqrt(nn);
 }
 
+// tri_solve for factors and iterate in global memory: the same arithmetic in
+// the same order, with the operands of the next C steps loaded while the
+// current C are processed (two register sets), so that a sweep waits for
+// memory once instead of once per C steps
+template <int C>
+__device__ __forceinline__ double tri_solve_pf(const double* __restrict__ f, int st, size_t KR, int K, double* z,
+                                               int zs, double sc, double* zo = nullptr, int zos = 0) {
+  if (!zo) {
+    zo = z;
+    zos = zs;
+  }
+  // forward: P and the unit lower bidiagonal L (elements 0 .. K - 2; the
+  // loads of a batch read z above the rows the earlier batches write)
+  double cur = z[0] * sc;
+  auto fload = [&](int i0, double (&raw)[C], double (&lv)[C], double (&pv)[C]) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int i = min(i0 + j, K - 2);
+      raw[j] = z[(size_t)(i + 1) * zs];
+      lv[j] = f[(size_t)i * st];
+      pv[j] = f[KR + (size_t)i * st];
+    }
+  };
+  auto fproc = [&](int i0, const double (&raw)[C], const double (&lv)[C], const double (&pv)[C]) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int i = i0 + j;
+      if (i < K - 1) {
+        const double rw = raw[j] * sc;
+        const bool p = pv[j] != 0.0;
+        const double out = p ? rw : cur;
+        const double oth = p ? cur : rw;
+        z[(size_t)i * zs] = out;
+        cur = oth - lv[j] * out;
+      }
+    }
+  };
+  {
+    double ra[C], la[C], pa[C], rb[C], lb[C], pb[C];
+    fload(0, ra, la, pa);
+    for (int i0 = 0; i0 < K - 1; i0 += 2 * C) {
+      fload(i0 + C, rb, lb, pb);
+      fproc(i0, ra, la, pa);
+      fload(i0 + 2 * C, ra, la, pa);
+      fproc(i0 + C, rb, lb, pb);
+    }
+  }
+  z[(size_t)(K - 1) * zs] = cur;
+  // backward: upper triangular with two superdiagonals (rows K - 1 .. 0; the
+  // loads of a batch read rows below those the earlier batches write)
+  double z1 = 0.0, z2 = 0.0, nn = 0.0;
+  auto bload = [&](int i0, double (&zv)[C], double (&u1)[C], double (&u2)[C], double (&r0)[C]) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const size_t o = (size_t)max(i0 - j, 0);
+      zv[j] = z[o * zs];
+      u1[j] = f[3 * KR + o * st];
+      u2[j] = f[4 * KR + o * st];
+      r0[j] = f[2 * KR + o * st];
+    }
+  };
+  auto bproc = [&](int i0, const double (&zv)[C], const double (&u1)[C], const double (&u2)[C], const double (&r0)[C]) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int i = i0 - j;
+      if (i >= 0) {
+        const double zi = (zv[j] - u1[j] * z1 - u2[j] * z2) * r0[j];
+        zo[(size_t)i * zos] = zi;
+        nn += zi * zi;
+        z2 = z1;
+        z1 = zi;
+      }
+    }
+  };
+  {
+    double za[C], ua[C], va[C], ra[C], zb[C], ub[C], vb[C], rb[C];
+    bload(K - 1, za, ua, va, ra);
+    for (int i0 = K - 1; i0 >= 0; i0 -= 2 * C) {
+      bload(i0 - C, zb, ub, vb, rb);
+      bproc(i0, za, ua, va, ra);
+      bload(i0 - 2 * C, za, ua, va, ra);
+      bproc(i0 - C, zb, ub, vb, rb);
+    }
+  }
+  return 1.0 / sqrt(nn);
+}
+
 // (a) prep, one workgroup per task: negligible off-diagonals are set to zero
 //     (they split T), the Gershgorin bound, the Sturm count at 0 and the
 //     side; meta = [r, pos, first, pivmin, ||T||]
@@ -1759,8 +1846,8 @@ __global__ __launch_bounds__(64) void k_eig_single_wide(LargeArgs a) {
   double* zt = X + 5 * KR + t;
   tri_factor(sd, se, K, lam, kEps * tnorm, X + t, r, KR);
   for (int i = 0; i < K; ++i) zt[(size_t)i * r] = hash_unit((uint32_t)t, (uint32_t)i);
-  double sc = tri_solve<32>(X + t, r, KR, K, zt, r, 1.0);
-  sc = tri_solve<32>(X + t, r, KR, K, zt, r, sc, w.Z + (size_t)t * K, 1);
+  double sc = tri_solve_pf<16>(X + t, r, KR, K, zt, r, 1.0);
+  sc = tri_solve_pf<16>(X + t, r, KR, K, zt, r, sc, w.Z + (size_t)t * K, 1);
   w.zs[t] = sc;
 }
 
@@ -1824,7 +1911,7 @@ __global__ __launch_bounds__(64) void k_eig_cluster(LargeArgs a) {
     tri_factor(sd, se, K, slam[t], tiny, X + t, r, KR);
     double* zt = X + 5 * KR + t;
     for (int i = 0; i < K; ++i) zt[(size_t)i * r] = hash_unit((uint32_t)t, (uint32_t)i);
-    (void)tri_solve<32>(X + t, r, KR, K, zt, r, 1.0);
+    (void)tri_solve_pf<16>(X + t, r, KR, K, zt, r, 1.0);
   }
   __syncthreads();
   // (ii) members in order
