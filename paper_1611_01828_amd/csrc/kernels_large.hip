@@ -590,20 +590,21 @@ __global__ __launch_bounds__(kTT) void k_trd_trail(LargeArgs a, int p) {
   }
 }
 
-// The last columns [j0, K) of a task in LDS (full n x n storage, n <= kTail),
+// The last columns [j0, K) of a task in LDS (full n x n storage, n <= TAIL),
 // reduced column by column: x = A(c+1:n, c) gives the reflector, then
 // p = tau A22 v, w = p - tau/2 (p^T v) v and A22 -= v w^T + w v^T
 // (Golub & Van Loan Algorithm 8.3.1).  Thread (r, h) owns row r and the
-// columns q = h mod kTailG (kTailG groups of kTailR row slots; the last
-// threads of the block idle).
-constexpr int kTailT = 1024;
-constexpr int kTailR = 144;
-constexpr int kTailG = kTailT / kTailR;
-static_assert(kTailR >= kTail && kTail <= 192, "tail layout");
-template <bool ADMM>
-__global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
-  __shared__ double A[kTail * kTail];
-  __shared__ double vb[kTail], wb[kTail], ph[kTailG][kTail];
+// columns q = h mod TG (TG = TT / TR groups of TR row slots; the last
+// threads of the block idle).  Two shapes: tails up to 136 columns (148 KB
+// of LDS, 1024 threads, one workgroup per CU) and, for launches whose
+// one-stage cliques have at most 64 vertices, tails up to 64 (35 KB, 256
+// threads, four workgroups per CU).
+template <bool ADMM, int TAIL, int TT, int TR>
+__global__ __launch_bounds__(TT) void k_trd_tail(LargeArgs a) {
+  constexpr int TG = TT / TR;
+  static_assert(TR >= TAIL && TAIL <= 192 && TR * TG <= TT, "tail layout");
+  __shared__ double A[TAIL * TAIL];
+  __shared__ double vb[TAIL], wb[TAIL], ph[TG][TAIL];
   __shared__ double red[4];
   const int K = a.tsize[blockIdx.x];
   if (K >= a.band_min) return;   // tridiagonal after the two-stage reduction
@@ -612,22 +613,22 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
   const int ld = lead_dim(K);
   double* W = w.W;
   const int tid = threadIdx.x;
-  const int r = tid % kTailR, h = tid / kTailR;   // h == kTailG: idle
+  const int r = tid % TR, h = tid / TR;   // h == TG: idle
   {
     // all of the thread's loads in flight together, from clamped in-range
     // addresses (entry min(idx, n^2 - 1) of the n x n block)
-    constexpr int NL = (kTail * kTail + kTailT - 1) / kTailT;
+    constexpr int NL = (TAIL * TAIL + TT - 1) / TT;
     double x[NL];
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
-      const int idx = min(tid + kTailT * q, n * n - 1), c = idx / n, rr = idx - c * n;
+      const int idx = min(tid + TT * q, n * n - 1), c = idx / n, rr = idx - c * n;
       x[q] = W[(size_t)(j0 + c) * ld + j0 + rr];
     }
 #pragma unroll
     for (int q = 0; q < NL; ++q) asm volatile("" : "+v"(x[q]));
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
-      const int idx = tid + kTailT * q;
+      const int idx = tid + TT * q;
       if (idx < n * n) A[idx] = x[q];
     }
   }
@@ -660,7 +661,7 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
       for (int u = 0; u < 3; ++u) {
         const int rr = lane + 64 * u;
         const double vr = (rr == c + 1) ? 1.0 : ((rr > c + 1 && rr < n) ? xs[u] * scale : 0.0);
-        if (rr < kTail) vb[rr] = vr;
+        if (rr < TAIL) vb[rr] = vr;
         if (rr >= c + 2 && rr < n) W[(size_t)j * ld + j0 + rr] = vr;   // Householder vector
       }
       if (lane == 0) {
@@ -673,11 +674,11 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
     __syncthreads();
     const double tu = red[0];
     // (2) p = tau A22 v on rows and columns > c, column groups in ph
-    const bool live = h < kTailG && r > c && r < n;
+    const bool live = h < TG && r > c && r < n;
     double acc = 0.0;
     if (live)
-      for (int q = c + 1 + h; q < n; q += kTailG) acc += A[q * n + r] * vb[q];
-    if (h < kTailG && r < kTail) ph[h][r] = acc;
+      for (int q = c + 1 + h; q < n; q += TG) acc += A[q * n + r] * vb[q];
+    if (h < TG && r < TAIL) ph[h][r] = acc;
     __syncthreads();
     // (3) wave 0: w = p - tau/2 (p^T v) v
     if (tid < 64) {
@@ -688,7 +689,7 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
         double t = 0.0;
         if (rr > c && rr < n) {
 #pragma unroll
-          for (int g = 0; g < kTailG; ++g) t += ph[g][rr];
+          for (int g = 0; g < TG; ++g) t += ph[g][rr];
           t *= tu;
           pv += t * vb[rr];
         }
@@ -698,14 +699,14 @@ __global__ __launch_bounds__(kTailT) void k_trd_tail(LargeArgs a) {
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
         const int rr = lane + 64 * u;
-        if (rr < kTail) wb[rr] = (rr > c && rr < n) ? pr[u] - 0.5 * tu * pv * vb[rr] : 0.0;
+        if (rr < TAIL) wb[rr] = (rr > c && rr < n) ? pr[u] - 0.5 * tu * pv * vb[rr] : 0.0;
       }
     }
     __syncthreads();
     // (4) A22 -= v w^T + w v^T
     if (live) {
       const double vr = vb[r], wr = wb[r];
-      for (int q = c + 1 + h; q < n; q += kTailG) A[q * n + r] -= vr * wb[q] + wr * vb[q];
+      for (int q = c + 1 + h; q < n; q += TG) A[q * n + r] -= vr * wb[q] + wr * vb[q];
     }
     __syncthreads();
   }
@@ -2440,7 +2441,11 @@ static void run_large_step(const LargeArgs& a, int32_t ntask, int32_t kmax, cons
         const int n2 = kmax1 - p * kNB - kNB;
         launch(2, k_trd_trail<ADMM>, dim3(na, ((n2 + 127) / 128) * ((n2 + 63) / 64)), dim3(kTT), a, p);
       }
-      launch(3, k_trd_tail<ADMM>, dim3(ntask), dim3(kTailT), a);
+      // the smaller tail shape when every one-stage clique fits it
+      if (kmax1 <= 64)
+        launch(3, k_trd_tail<ADMM, 64, 256, 64>, dim3(ntask), dim3(256), a);
+      else
+        launch(3, k_trd_tail<ADMM, kTail, 1024, 144>, dim3(ntask), dim3(1024), a);
       break;
     }
     case 2:
