@@ -743,7 +743,7 @@ __global__ __launch_bounds__(TT) void k_trd_tail(LargeArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int kBandT = 256;                 // threads of the panel kernel (one wave per SIMD)
 constexpr int kBandRows = 1024 / kBandT;    // rows per thread of the panel kernel
-constexpr int kBandTile = 128;              // rows and columns of a trailing-update tile
+constexpr int kBandTile = 128;              // columns of a trailing-update tile (and of an A22 U partial)
 constexpr int kBandXT = (1024 + kBandTile - 1) / kBandTile;   // column tiles
 constexpr int kChaseWaves = 4;              // waves of the bulge chasing (8 sweeps each; one per SIMD)
 constexpr int kChaseLd = 1032;              // LDS stride of a stored diagonal: K + 7 columns, zero past K
