@@ -744,7 +744,6 @@ __global__ __launch_bounds__(TT) void k_trd_tail(LargeArgs a) {
 constexpr int kBandT = 256;                 // threads of the panel kernel (one wave per SIMD)
 constexpr int kBandRows = 1024 / kBandT;    // rows per thread of the panel kernel
 constexpr int kBandTile = 128;              // columns of a trailing-update tile (and of an A22 U partial)
-constexpr int kBandXT = (1024 + kBandTile - 1) / kBandTile;   // column tiles
 constexpr int kChaseWaves = 4;              // waves of the bulge chasing (8 sweeps each; one per SIMD)
 constexpr int kChaseLd = 1032;              // LDS stride of a stored diagonal: K + 7 columns, zero past K
 constexpr int kChaseSpin = 1 << 22;         // bound on a wave's wait for the previous sweep
@@ -1753,7 +1752,7 @@ __global__ __launch_bounds__(64 * kBisWaves) void k_eig_bisect(LargeArgs a) {
     const double step = width / (double)(kBisL + 1);
     const double x = lo + step * (double)(gl + 1);
     const uint64_t m = __ballot(!done && sturm_count(sd, se2, K, x, pivmin) > k);
-    const uint32_t gm = (uint32_t)(m >> (grp * kBisL)) & ((1u << kBisL) - 1u);
+    const uint32_t gm = (uint32_t)((m >> (grp * kBisL)) & ((1ull << kBisL) - 1ull));
     const int j0 = gm ? __builtin_ctz(gm) : kBisL;   // first point with count > k
     if (!done) {
       const double nlo = (j0 == 0) ? lo : lo + step * (double)j0;
@@ -1986,7 +1985,9 @@ __global__ __launch_bounds__(64) void k_eig_cluster(LargeArgs a) {
 // while the current sweep runs and stored over them after it (one wave:
 // LDS accesses are served in order, no barrier).
 constexpr int kQ2C = 4;
-constexpr int kQ2Pass = 4;   // reflector passes whose loads are issued together
+// reflector passes whose loads are issued together (1 against 2, 3, 4 and 8:
+// 1.61, 1.69, 1.74, 1.78 and 2.48 ms per max-cut iteration; fewer registers)
+constexpr int kQ2Pass = 1;
 template <bool ADMM>
 __global__ __launch_bounds__(64) void k_band_q2(LargeArgs a) {
   // rows of the eigenvectors, (kmax + kBand) x kQ2C doubles sized at launch
