@@ -58,7 +58,14 @@ def trd_tail_start(K, tail=136, nb=32):
 
 
 BAND = 8                     # bandwidth of the two-stage reduction's first stage
-BAND_MIN = 137               # default smallest clique order of the two-stage reduction
+BAND_MIN = 137               # smallest clique order of the two-stage reduction when it is on
+BAND_AUTO = 320              # automatic setting: on when the largest clique has at least this order
+
+
+def auto_band_min(sizes):
+    """settings.band_min = 0 as the library reads it: 137 when the largest
+    clique has at least BAND_AUTO vertices, otherwise no clique (1025)."""
+    return BAND_MIN if max(sizes) >= BAND_AUTO else 1025
 
 
 def band_panels(K):
@@ -302,8 +309,9 @@ def main():
                     help="largest clique order the Jacobi kernels take (settings.jacobi_max; 0 = automatic: "
                          "32, or 64 with the FP32 or warm-started Jacobi variants)")
     ap.add_argument("--band-min", type=int, default=0,
-                    help="smallest clique order of the two-stage tridiagonalisation (settings.band_min; 0 = 137, "
-                         "above 1024 = the one-stage reduction for every clique)")
+                    help="smallest clique order of the two-stage tridiagonalisation (settings.band_min; 0 = automatic: "
+                         "137 when the largest clique has at least 320 vertices, otherwise none; above 1024 = the "
+                         "one-stage reduction for every clique)")
     ap.add_argument("--no-extra", action="store_true",
                     help="leave out the compact batched and differentiated figures of the default line")
     args = ap.parse_args()
@@ -403,7 +411,7 @@ def main():
     # dominant kernel and its roofline position (per-launch averages from HIP events)
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()}
     dom = max(phases, key=lambda k: phases[k][0])
-    work = phase_work(sizes, dims, band_min=args.band_min or BAND_MIN, rcounts=rcounts)
+    work = phase_work(sizes, dims, band_min=args.band_min or auto_band_min(sizes), rcounts=rcounts)
     roof = None
     if dom in work:
         bound, amount, unit = work[dom]
@@ -511,7 +519,8 @@ def main():
                                 "min-degree chordal extension"),
                    "n": inst.n, "m": inst.m, "cliques": len(sizes), "max_clique": max(sizes),
                    "nE": dims[0], "ns": dims[1], "eps_tol": 1e-4, "eig_warm": ew,
-                   "jacobi_max": args.jacobi_max or ("64" if ew else "32 (automatic)"), "band_min": args.band_min or 137, "method": args.method},
+                   "jacobi_max": args.jacobi_max or ("64" if ew else "32 (automatic)"), "band_min": args.band_min or ("137 (automatic)" if auto_band_min(sizes) == BAND_MIN else "off (automatic)"),
+                   "method": args.method},
         "roofline": roof,
         "measured_peaks": peaks,
         "cpu_baseline": cpu,

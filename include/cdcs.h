@@ -163,9 +163,12 @@ typedef struct {
                           reduction (dense to a band of 8 sub-diagonals by panel QR, then band
                           to tridiagonal by bulge chasing in LDS); smaller cliques above the
                           Jacobi sizes take the one-stage blocked reduction (its last 136
-                          columns in LDS).  0 = 137 (every clique the LDS reduction cannot
-                          hold whole); values above 1024 keep the one-stage reduction for all;
-                          otherwise at least 137 (CDCS_E_ARG).  Same projection, other cost. */
+                          columns in LDS).  0 = automatic: 137 (every clique the LDS
+                          reduction cannot hold whole) when the largest clique has at least 320
+                          vertices, otherwise none (a lone clique of a few hundred vertices is
+                          reduced faster by the one-stage path); values above 1024 keep the
+                          one-stage reduction for all; otherwise at least 137 (CDCS_E_ARG).
+                          Same projection, other cost.  cdcs_psd_project uses 137. */
 } cdcs_settings;
 
 typedef struct {
@@ -179,7 +182,7 @@ typedef struct {
 
 /* Fill s with eps_tol = 1e-4, max_iter = 2000, check_every = 1, timing = 0,
  * use_graph = 0, eig_fp32 = 0, autotune = 0, alpha = 1, eig_warm = 0,
- * method = CDCS_METHOD_SELF_DUAL, rho = 1, jacobi_max = 0 (automatic), band_min = 0 (137). */
+ * method = CDCS_METHOD_SELF_DUAL, rho = 1, jacobi_max = 0 (automatic), band_min = 0 (automatic). */
 void cdcs_default_settings(cdcs_settings* s);
 
 /* Build the cached data of step 1 (the m x m factor of the matrix of eq.

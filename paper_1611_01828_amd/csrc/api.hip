@@ -203,8 +203,19 @@ int bucket_of(int K, int jmax = kJacobiMax) {
   return 3;
 }
 
-// smallest clique order that takes the two-stage tridiagonalisation
-int band_min_of(const cdcs_settings& s) { return s.band_min ? s.band_min : kBandMinDefault; }
+// smallest clique order that takes the two-stage tridiagonalisation.  0 =
+// automatic: 137 when the handle's largest clique has at least kBandAuto
+// vertices (its two-stage chain then sets the pace, and the other cliques of
+// 137 vertices or more ride in the same launches), otherwise none.  A lone
+// clique of a few hundred vertices is reduced faster by the one-stage path
+// (11 column steps and the LDS tail for the 147-vertex clique of the 40 x 50
+// grid max-cut: 714 against 497 iterations/s); the estimates from the
+// per-launch times cross near 300 vertices.
+constexpr int kBandAuto = 320;
+int band_min_of(const cdcs_handle* h) {
+  if (h->set.band_min) return h->set.band_min;
+  return (h->kmax_large >= kBandAuto) ? kBandMinDefault : 1025;
+}
 
 // largest clique order of the Jacobi kernels: 0 = 32, or 64 when the FP32 or
 // warm-started Jacobi variants are on (they act on Jacobi cliques only);
@@ -316,7 +327,7 @@ int launch_split_iteration(cdcs_handle* h, int32_t stop) {
     HIPCHK(hipStreamWaitEvent(lst, h->ev_fork, 0));
     PhaseTimer t(h, PH_LG_GATHER, lst);
     launch_psd_project_large(d.clq_size, d.clq_slot, h->tasks[4], d.big_size, h->large_sizes.data(), h->ntasks[4],
-                             h->kmax_large, a.w, a.p, d.big_work, d.big_off, lst, band_min_of(h->set));
+                             h->kmax_large, a.w, a.p, d.big_work, d.big_off, lst, band_min_of(h));
   }
   const int kmaxs[4] = {16, 32, 64, 96};
   for (int bk = 0; bk < 4; ++bk)
@@ -373,7 +384,7 @@ int launch_iteration(cdcs_handle* h, int32_t stop) {
     for (int step = 0; step < kLargeSteps; ++step) {
       PhaseTimer t(h, kLargeStepPhase[step], lst);
       launch_cone_large_step(d, h->tasks[4], h->ntasks[4], h->kmax_large, h->large_sizes.data(), step, lst,
-                             band_min_of(h->set),
+                             band_min_of(h),
                              h->set.timing ? &hook : nullptr);
     }
   }

@@ -135,6 +135,15 @@ def test_gpus_above_one_exit_with_a_message():
     assert "one GPU" in r.stderr
 
 
+def test_auto_band_min(bench):
+    """settings.band_min = 0 as the library reads it: the two-stage reduction
+    only when the largest clique has at least 320 vertices."""
+    assert bench.auto_band_min([673, 600, 140, 40]) == 137
+    assert bench.auto_band_min([320, 5]) == 137
+    assert bench.auto_band_min([319, 200]) == 1025
+    assert bench.auto_band_min([147, 64, 5]) == 1025
+
+
 def test_traffic_summaries_named_in_bench_exist():
     """Every counter summary bench.py reads is a committed file with a record."""
     import re
