@@ -744,7 +744,8 @@ __global__ __launch_bounds__(TT) void k_trd_tail(LargeArgs a) {
 constexpr int kBandT = 256;                 // threads of the panel kernel (one wave per SIMD)
 constexpr int kBandRows = 1024 / kBandT;    // rows per thread of the panel kernel
 constexpr int kBandTile = 128;              // columns of a trailing-update tile (and of an A22 U partial)
-constexpr int kChaseWaves = 4;              // waves of the bulge chasing (8 sweeps each; one per SIMD)
+constexpr int kChaseWaves = 8;              // waves of the bulge chasing (8 sweeps each; two per SIMD, so that a
+                                            // new group of sweeps need not wait for a wave to finish its last)
 constexpr int kChaseLd = 1032;              // LDS stride of a stored diagonal: K + 7 columns, zero past K
 constexpr int kChaseSpin = 1 << 22;         // bound on a wave's wait for the previous sweep
 
@@ -2082,7 +2083,7 @@ __global__ __launch_bounds__(64) void k_band_q2(LargeArgs a) {
 }
 
 constexpr int kBtNC = 8;     // eigenvectors per apply workgroup, resident in LDS
-constexpr int kBtCR = 256;   // rows of a staged V panel chunk
+constexpr int kBtCR = 128;   // rows of a staged V panel chunk (1.01 -> 0.97 ms per max-cut iteration against 256)
 
 // element (row, a) of V_p: the reflector of column c = j0 + a has 1 on row
 // c + sh and the stored Householder vector below it (sh = 1 after the
